@@ -1,0 +1,190 @@
+/*
+ * ffx -- exact sparse matrix products over Z/mZ on MI355X (gfx950).
+ *
+ * C ABI of the library libffx.so. Every call returns an ffx_status; nothing
+ * throws across this boundary. After a failure, ffx_last_error() returns a
+ * message for the calling thread.
+ *
+ * Operations (paper, Section 2 opening paragraph): y <- alpha*A*x + beta*y,
+ * the apply y <- A*x (alpha = 1, beta = 0), and the block form
+ * Y <- alpha*A*X + beta*Y; the transpose product (Section 1 and Section 4);
+ * the power A^k*V and the projected sequence U^T A^i V of block Wiedemann's
+ * first step (Section 2.5 "Performance issues", Section 3 step 1,
+ * Section 3.1).
+ *
+ * Conventions shared by every call:
+ *  - 2 <= m <= 2^31-1. m need not be prime; only ring operations are used.
+ *  - Residues are represented on [0, m-1] (Section 2.2). Matrix values given
+ *    to a create call may be any int32/int64 and are reduced there; every
+ *    vector entry, alpha and beta passed to a product must already be in
+ *    [0, m-1] (otherwise the result is unspecified). Outputs are always in
+ *    [0, m-1].
+ *  - Dense multi-vectors are n x s with row j's s residues contiguous,
+ *    leading dimension ld >= s (the layout Section 2.5 "Using multi-vectors"
+ *    describes as reading A once with x and y accessed contiguously).
+ *  - Vector, multi-vector and sequence pointers are caller-owned DEVICE
+ *    memory; calls are ordered on the given stream (a hipStream_t passed as
+ *    void*, NULL for the null stream) and return before the kernels finish.
+ *    The library never frees caller memory.
+ *  - Input and output vectors must not overlap. With beta = 0 the output is
+ *    write-only (its previous contents are ignored).
+ *  - A matrix handle is read-only after creation: products on one handle
+ *    may run concurrently on different streams.
+ */
+#ifndef FFX_H
+#define FFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFX_OK = 0,
+  FFX_EINVAL = 1,       /* bad argument: modulus, shape, index, pointer, overlap */
+  FFX_EBOUND = 2,       /* requested accumulator cannot hold one product exactly */
+  FFX_ENOMEM = 3,       /* host or device allocation failed */
+  FFX_EDEVICE = 4,      /* a HIP runtime call failed */
+  FFX_EUNSUPPORTED = 5  /* valid request outside what this build implements */
+} ffx_status;
+
+typedef enum { FFX_I32 = 0, FFX_I64 = 1 } ffx_dtype;
+
+/* Accumulator of the delayed reduction (Section 2.2): products are summed in
+ * a wide type and reduced modulo m only when the next term could exceed what
+ * the type holds exactly. INT64: unsigned 64-bit integers, at most
+ * 2^63 - 1 before a reduction. FP64: doubles, at most 2^53 - 1 (every
+ * integer up to 2^53 is exact); refused with FFX_EBOUND when (m-1)^2 alone
+ * does not fit. AUTO: INT64. */
+typedef enum { FFX_ACC_AUTO = 0, FFX_ACC_INT64 = 1, FFX_ACC_FP64 = 2 } ffx_acc;
+
+/* Who chooses each row block's storage format (Section 2.4 "Heuristic format
+ * chooser"): the plain heuristic, the learned cost model (falls back to the
+ * heuristic when no usable model is loaded), or one fixed format for all. */
+typedef enum { FFX_SEL_HEURISTIC = 0, FFX_SEL_LEARNED = 1, FFX_SEL_FIXED = 2 } ffx_sel;
+
+/* Per-block storage formats. A block is a run of block_rows consecutive
+ * rows. Every format stores +-1 entries without a value when split_pm1 is
+ * set (Section 2.4 "Taking into account the +-1"); the BAND_* formats move
+ * the block's densest diagonals into a diagonal-major part whose values are
+ * stored densely (the DIA idea of Section 2.1) and keep the rest in the
+ * named residual format. The result never depends on the format. */
+typedef enum {
+  FFX_FMT_STREAM = 0,            /* CSR rows staged through LDS in balanced tiles */
+  FFX_FMT_SELL = 1,              /* sliced ELL: 64-row slices, column-major, padded */
+  FFX_FMT_SELL_SORTED = 2,       /* sliced ELL over rows sorted by length inside the block */
+  FFX_FMT_BAND_STREAM = 3,
+  FFX_FMT_BAND_SELL = 4,
+  FFX_FMT_BAND_SELL_SORTED = 5,
+  FFX_NUM_FORMATS = 6
+} ffx_format;
+
+typedef struct {
+  uint32_t size;            /* sizeof(ffx_build_opts) */
+  int32_t acc;              /* ffx_acc, default FFX_ACC_AUTO */
+  int32_t selector;         /* ffx_sel, default FFX_SEL_HEURISTIC */
+  int32_t fixed_format;     /* ffx_format used when selector == FFX_SEL_FIXED */
+  int32_t split_pm1;        /* 1 (default): +-1 stored without values; 0: every entry has a value */
+  int32_t block_rows;       /* rows per format block, a multiple of 64 in [64, 65536]; default 4096 */
+  int32_t build_transpose;  /* 1: also encode A^T so ffx_spmv_t/ffx_spmm_t run as row products */
+  int32_t tile_entries;     /* entries per STREAM tile, 256..4096, 0 = default (autotuned or 1024) */
+  const char* model_path;   /* learned selector weights; NULL = none */
+} ffx_build_opts;
+
+typedef struct ffx_matrix_s* ffx_matrix;
+
+typedef struct {
+  int64_t nrows, ncols;
+  uint32_t m;
+  int32_t acc;              /* accumulator actually used (FFX_ACC_INT64 or FFX_ACC_FP64) */
+  int64_t nnz_input;        /* entries given to the create call */
+  int64_t nnz;              /* stored nonzero residues after merging duplicates and dropping zeros */
+  int64_t n_plus, n_minus;  /* entries stored without a value (residue 1 and m-1) */
+  int64_t n_band;           /* entries held in BAND diagonals */
+  int64_t nblocks;
+  int64_t ntiles;
+  int64_t max_row_terms;    /* longest row, in terms */
+  int64_t reduce_every;     /* bound b: terms summed between reductions (>= max_row_terms: never) */
+  int64_t device_bytes;     /* device memory held by the handle (A, and A^T when built) */
+  int64_t stream_bytes;     /* bytes one product streams from the encoded matrix (excluding x and y) */
+  int32_t has_transpose;
+  int32_t value_bytes;      /* 2 when m <= 65536, else 4 */
+  int64_t format_blocks[FFX_NUM_FORMATS]; /* number of blocks in each format */
+} ffx_matrix_info;
+
+/* Fill *opts with the defaults. */
+void ffx_build_opts_default(ffx_build_opts* opts);
+
+/* Build a matrix from host CSR arrays (Section 2.1: start = rowptr,
+ * colid = colidx, data = vals). rowptr has nrows+1 entries (rowptr[0] = 0,
+ * nondecreasing); colidx[k] in [0, ncols); vals is int32 or int64 per
+ * val_type. Columns need not be sorted; duplicates add. Values are reduced to
+ * [0, m-1], zero residues dropped, residues 1 and m-1 classified as +-1 (for
+ * m = 2, 1 = -1 counts as +1). Limits: nrows, ncols <= 2^30, nnz < 2^32.
+ * The host arrays are copied; the caller keeps them. Device uploads are
+ * issued on `stream` and complete before return. opts may be NULL. */
+ffx_status ffx_matrix_create_csr(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                                 const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts,
+                                 void* stream, ffx_matrix* out);
+
+/* Same from coordinate triples (Section 2.1: data, colid, rowid), any order. */
+ffx_status ffx_matrix_create_coo(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rowidx,
+                                 const int32_t* colidx, const void* vals, ffx_dtype val_type, uint32_t m,
+                                 const ffx_build_opts* opts, void* stream, ffx_matrix* out);
+
+ffx_status ffx_matrix_info_get(ffx_matrix A, ffx_matrix_info* info);
+
+/* Format of each row block of A (transpose = 0) or of A^T (transpose = 1):
+ * writes min(cap, nblocks) ffx_format values to out (host memory). */
+ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* out, int64_t cap);
+
+ffx_status ffx_matrix_destroy(ffx_matrix A);
+
+/* y <- alpha*A*x + beta*y (mod m). x: ncols entries, y: nrows entries, both
+ * of element type dtype. */
+ffx_status ffx_spmv(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                    void* stream);
+
+/* y <- alpha*A^T*x + beta*y (mod m). x: nrows entries, y: ncols entries.
+ * Uses the stored A^T when the handle has one, else a scatter with 64-bit
+ * integer atomics into a temporary, which is exact in any order. */
+ffx_status ffx_spmv_t(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                      void* stream);
+
+/* Y <- alpha*A*X + beta*Y (mod m) for s in [1, 16] vectors. X: ncols x s
+ * (ldx), Y: nrows x s (ldy). */
+ffx_status ffx_spmm(ffx_matrix A, int32_t s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta, void* Y,
+                    int64_t ldy, ffx_dtype dtype, void* stream);
+
+/* Y <- alpha*A^T*X + beta*Y (mod m). X: nrows x s (ldx), Y: ncols x s (ldy). */
+ffx_status ffx_spmm_t(ffx_matrix A, int32_t s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
+                      void* Y, int64_t ldy, ffx_dtype dtype, void* stream);
+
+/* W <- A^k V (mod m) for square A, k >= 0, s in [1, 16]; V and W: n x s
+ * (ldv, ldw). The iterates stay on the device (Section 2.5 "Performance
+ * issues", the smpv_n loop). V and W may not overlap. */
+ffx_status ffx_power(ffx_matrix A, int64_t k, int32_t s, const void* V, int64_t ldv, void* W, int64_t ldw,
+                     ffx_dtype dtype, void* stream);
+
+/* S_i = U^T A^i V (mod m) for i = 0 .. L-1 (Section 3, step 1; Section 3.1),
+ * square A, s in [1, 16]. U and V: n x s (ldu, ldv). S: L*s*s entries of
+ * type dtype, S[(i*s + a)*s + b] = sum_k U[k][a] * (A^i V)[k][b] mod m.
+ * If Wlast is not NULL it receives A^L V (n x s, leading dimension s).
+ * The whole loop runs on the device; no data returns to the host. */
+ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
+                        void* S, void* Wlast, ffx_dtype dtype, void* stream);
+
+/* Status name and the calling thread's last error message. */
+const char* ffx_status_str(ffx_status st);
+const char* ffx_last_error(void);
+
+/* Library version string. */
+const char* ffx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFX_H */

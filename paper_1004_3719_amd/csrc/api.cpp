@@ -1,0 +1,395 @@
+// The C ABI: argument checks, matrix construction and product dispatch.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "host.h"
+#include "launch.h"
+
+namespace ffx {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& s) { g_last_error = s; }
+
+void fail(ffx_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Error{st, buf};
+}
+
+template <class F>
+static ffx_status guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return FFX_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return FFX_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return FFX_EDEVICE;
+  }
+}
+
+static int arith_kind(const ffx_matrix_s& M) {
+  bool small = M.md.small();
+  if (M.acc == FFX_ACC_FP64) {
+    if (small) return M.chunk ? AK_F64_16_CH : AK_F64_16;
+    return M.chunk ? AK_F64_32_CH : AK_F64_32;
+  }
+  if (small) return AK_SMALL;
+  return M.chunk ? AK_BIG_CH : AK_BIG;
+}
+
+static PlanOpts plan_opts(const ffx_build_opts* o) {
+  ffx_build_opts d;
+  ffx_build_opts_default(&d);
+  if (o) {
+    if (o->size < sizeof(uint32_t) || o->size > sizeof(ffx_build_opts))
+      fail(FFX_EINVAL, "ffx_build_opts.size = %u (expected %zu)", o->size, sizeof(ffx_build_opts));
+    std::memcpy(&d, o, o->size);
+    d.size = sizeof(ffx_build_opts);
+  }
+  PlanOpts p;
+  if (d.acc < FFX_ACC_AUTO || d.acc > FFX_ACC_FP64) fail(FFX_EINVAL, "accumulator %d", d.acc);
+  p.acc = d.acc == FFX_ACC_AUTO ? FFX_ACC_INT64 : d.acc;
+  if (d.selector < FFX_SEL_HEURISTIC || d.selector > FFX_SEL_FIXED) fail(FFX_EINVAL, "selector %d", d.selector);
+  p.selector = d.selector;
+  if (d.selector == FFX_SEL_FIXED && (d.fixed_format < 0 || d.fixed_format >= FFX_NUM_FORMATS))
+    fail(FFX_EINVAL, "fixed format %d", d.fixed_format);
+  p.fixed_format = d.fixed_format;
+  p.split_pm1 = d.split_pm1 != 0;
+  if (d.block_rows < 64 || d.block_rows > 65536 || d.block_rows % 64)
+    fail(FFX_EINVAL, "block_rows %d is not a multiple of 64 in [64, 65536]", d.block_rows);
+  p.block_rows = d.block_rows;
+  int te = d.tile_entries ? d.tile_entries : 1024;
+  if (te < 256 || te > 4096) fail(FFX_EINVAL, "tile_entries %d outside [256, 4096]", te);
+  p.tile_entries = te;
+  if (d.model_path) p.model_path = d.model_path;
+  return p;
+}
+
+static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts, int build_t, hipStream_t st) {
+  PlanOpts po = plan_opts(opts);
+  ffx_matrix_s* M = new ffx_matrix_s();
+  try {
+    M->md = make_modulus(m);
+    M->acc = po.acc;
+    // delayed-reduction bound (Section 2.2): terms are at most tmax, a reduced
+    // accumulator is at most m-1, and the sum must stay representable
+    const uint64_t mm1 = (uint64_t)m - 1;
+    const uint64_t tmax = std::max<uint64_t>(mm1 * mm1, m);
+    const uint64_t limit = po.acc == FFX_ACC_FP64 ? ((uint64_t)1 << 53) - 1 : (uint64_t)INT64_MAX;
+    int64_t b = terms_before_reduce(limit, m, tmax);
+    if (b < 1)
+      fail(FFX_EBOUND, "FP64 accumulator cannot hold (m-1)^2 = %llu exactly (needs < 2^53); use FFX_ACC_INT64",
+           (unsigned long long)(mm1 * mm1));
+    encode(A, M->md, po, st, &M->A);
+    int64_t maxterms = M->A.max_row_terms;
+    if (build_t) {
+      RCsr T = transpose(A);
+      encode(T, M->md, po, st, &M->AT);
+      M->has_t = true;
+      maxterms = std::max(maxterms, M->AT.max_row_terms);
+    } else {
+      // the scatter form of A^T sums one column per output: bound by the longest column
+      std::vector<int64_t> cnt(A.ncols, 0);
+      for (uint32_t c : A.col) cnt[c]++;
+      for (int64_t v : cnt) maxterms = std::max(maxterms, v);
+    }
+    M->chunk = maxterms > b;
+    M->A.dm.reduce_every = b;
+    M->AT.dm.reduce_every = b;
+    ffx_matrix_info& I = M->info;
+    I.nrows = A.nrows;
+    I.ncols = A.ncols;
+    I.m = m;
+    I.acc = M->acc;
+    I.nnz = M->A.nnz;
+    I.n_plus = M->A.n_plus;
+    I.n_minus = M->A.n_minus;
+    I.n_band = M->A.n_band;
+    I.nblocks = (int64_t)M->A.block_fmt.size();
+    I.ntiles = M->A.ntiles;
+    I.max_row_terms = maxterms;
+    I.reduce_every = b;
+    I.device_bytes = M->A.device_bytes + (M->has_t ? M->AT.device_bytes : 0);
+    I.stream_bytes = M->A.stream_bytes;
+    I.has_transpose = M->has_t;
+    I.value_bytes = M->md.small() ? 2 : 4;
+    for (int f = 0; f < FFX_NUM_FORMATS; ++f) I.format_blocks[f] = M->A.format_blocks[f];
+  } catch (...) {
+    M->A.release();
+    M->AT.release();
+    delete M;
+    throw;
+  }
+  return M;
+}
+
+static size_t esize(ffx_dtype dt) { return dt == FFX_I32 ? 4 : 8; }
+
+static void check_dtype(ffx_dtype dt) {
+  if (dt != FFX_I32 && dt != FFX_I64) fail(FFX_EINVAL, "dtype %d is neither FFX_I32 nor FFX_I64", (int)dt);
+}
+
+// byte range [lo, hi) covered by an n x s block with leading dimension ld
+static void span(const void* p, int64_t n, int s, int64_t ld, ffx_dtype dt, uintptr_t& lo, uintptr_t& hi) {
+  lo = (uintptr_t)p;
+  hi = n > 0 ? lo + (uintptr_t)(((n - 1) * ld + s) * (int64_t)esize(dt)) : lo;
+}
+
+static void check_block(const char* what, const void* p, int64_t n, int s, int64_t ld) {
+  if (ld < s) fail(FFX_EINVAL, "%s: leading dimension %lld < s = %d", what, (long long)ld, s);
+  if (n > 0 && !p) fail(FFX_EINVAL, "%s is NULL", what);
+}
+
+static void check_disjoint(const char* a, const void* pa, int64_t na, int64_t lda, const char* b, const void* pb,
+                           int64_t nb, int64_t ldb, int s, ffx_dtype dt) {
+  uintptr_t a0, a1, b0, b1;
+  span(pa, na, s, lda, dt, a0, a1);
+  span(pb, nb, s, ldb, dt, b0, b1);
+  if (a0 < b1 && b0 < a1) fail(FFX_EINVAL, "%s and %s overlap", a, b);
+}
+
+static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
+                    void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st) {
+  if (!M) fail(FFX_EINVAL, "matrix handle is NULL");
+  check_dtype(dt);
+  if (s < 1 || s > MAX_S) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, MAX_S);
+  if (alpha >= M->md.m || beta >= M->md.m) fail(FFX_EINVAL, "alpha or beta not in [0, m-1]");
+  const int64_t nin = trans ? M->info.nrows : M->info.ncols;
+  const int64_t nout = trans ? M->info.ncols : M->info.nrows;
+  check_block("x", X, nin, s, ldx);
+  check_block("y", Y, nout, s, ldy);
+  check_disjoint("x", X, nin, ldx, "y", Y, nout, ldy, s, dt);
+  if (nout == 0) return;
+  if (trans && !M->has_t)
+    fail(FFX_EUNSUPPORTED, "transpose product without a stored A^T (build with build_transpose = 1)");
+  const Encoded& E = trans ? M->AT : M->A;
+  FFX_HIP(launch_tiles(arith_kind(*M), E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st));
+}
+
+}  // namespace ffx
+
+using namespace ffx;
+
+extern "C" {
+
+void ffx_build_opts_default(ffx_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->size = sizeof *o;
+  o->acc = FFX_ACC_AUTO;
+  o->selector = FFX_SEL_HEURISTIC;
+  o->fixed_format = FFX_FMT_STREAM;
+  o->split_pm1 = 1;
+  o->block_rows = 4096;
+  o->build_transpose = 0;
+  o->tile_entries = 0;
+  o->model_path = nullptr;
+}
+
+ffx_status ffx_matrix_create_csr(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                                 const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts,
+                                 void* stream, ffx_matrix* out) {
+  return guard([&] {
+    if (!out) fail(FFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    RCsr A = reduce_csr(nrows, ncols, rowptr, colidx, vals, val_type, m);
+    A.nrows = nrows;
+    int bt = opts && opts->size >= offsetof(ffx_build_opts, build_transpose) + sizeof(int32_t) ? opts->build_transpose : 0;
+    ffx_matrix M = build(A, m, opts, bt, (hipStream_t)stream);
+    M->info.nnz_input = rowptr ? rowptr[nrows] : 0;
+    *out = M;
+  });
+}
+
+ffx_status ffx_matrix_create_coo(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rowidx,
+                                 const int32_t* colidx, const void* vals, ffx_dtype val_type, uint32_t m,
+                                 const ffx_build_opts* opts, void* stream, ffx_matrix* out) {
+  return guard([&] {
+    if (!out) fail(FFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    RCsr A = reduce_coo(nrows, ncols, nnz, rowidx, colidx, vals, val_type, m);
+    int bt = opts && opts->size >= offsetof(ffx_build_opts, build_transpose) + sizeof(int32_t) ? opts->build_transpose : 0;
+    ffx_matrix M = build(A, m, opts, bt, (hipStream_t)stream);
+    M->info.nnz_input = nnz;
+    *out = M;
+  });
+}
+
+ffx_status ffx_matrix_info_get(ffx_matrix A, ffx_matrix_info* info) {
+  return guard([&] {
+    if (!A || !info) fail(FFX_EINVAL, "NULL argument");
+    *info = A->info;
+  });
+}
+
+ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* out, int64_t cap) {
+  return guard([&] {
+    if (!A || (cap > 0 && !out)) fail(FFX_EINVAL, "NULL argument");
+    if (transpose && !A->has_t) fail(FFX_EINVAL, "the handle holds no A^T");
+    const auto& f = transpose ? A->AT.block_fmt : A->A.block_fmt;
+    int64_t n = std::min<int64_t>(cap, (int64_t)f.size());
+    for (int64_t i = 0; i < n; ++i) out[i] = f[i];
+  });
+}
+
+ffx_status ffx_matrix_destroy(ffx_matrix A) {
+  return guard([&] {
+    if (!A) return;
+    A->A.release();
+    A->AT.release();
+    delete A;
+  });
+}
+
+ffx_status ffx_spmv(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                    void* stream) {
+  return guard([&] { product(A, false, 1, alpha, x, 1, beta, y, 1, dtype, (hipStream_t)stream); });
+}
+
+ffx_status ffx_spmv_t(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                      void* stream) {
+  return guard([&] { product(A, true, 1, alpha, x, 1, beta, y, 1, dtype, (hipStream_t)stream); });
+}
+
+ffx_status ffx_spmm(ffx_matrix A, int32_t s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta, void* Y,
+                    int64_t ldy, ffx_dtype dtype, void* stream) {
+  return guard([&] { product(A, false, s, alpha, X, ldx, beta, Y, ldy, dtype, (hipStream_t)stream); });
+}
+
+ffx_status ffx_spmm_t(ffx_matrix A, int32_t s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta, void* Y,
+                      int64_t ldy, ffx_dtype dtype, void* stream) {
+  return guard([&] { product(A, true, s, alpha, X, ldx, beta, Y, ldy, dtype, (hipStream_t)stream); });
+}
+
+ffx_status ffx_power(ffx_matrix A, int64_t k, int32_t s, const void* V, int64_t ldv, void* W, int64_t ldw,
+                     ffx_dtype dtype, void* stream) {
+  return guard([&] {
+    if (!A) fail(FFX_EINVAL, "matrix handle is NULL");
+    check_dtype(dtype);
+    if (A->info.nrows != A->info.ncols) fail(FFX_EINVAL, "power needs a square matrix");
+    if (k < 0) fail(FFX_EINVAL, "k = %lld < 0", (long long)k);
+    if (s < 1 || s > MAX_S) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, MAX_S);
+    const int64_t n = A->info.nrows;
+    check_block("V", V, n, s, ldv);
+    check_block("W", W, n, s, ldw);
+    check_disjoint("V", V, n, ldv, "W", W, n, ldw, s, dtype);
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) return;
+    if (k == 0) {
+      FFX_HIP(launch_copy_block(dtype, V, ldv, W, ldw, n, s, st));
+      return;
+    }
+    const int ak = arith_kind(*A);
+    const Encoded& E = A->A;
+    void* tmp[2] = {nullptr, nullptr};
+    size_t bytes = (size_t)n * s * esize(dtype);
+    if (k >= 2) {
+      for (int q = 0; q < (k >= 3 ? 2 : 1); ++q)
+        if (hipMallocAsync(&tmp[q], bytes, st) != hipSuccess) {
+          for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+          fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+        }
+    }
+    const void* cur = V;
+    int64_t ldc = ldv;
+    hipError_t e = hipSuccess;
+    for (int64_t it = 0; it < k && e == hipSuccess; ++it) {
+      bool last = it == k - 1;
+      void* dst = last ? W : tmp[it & 1];
+      int64_t ldd = last ? ldw : s;
+      e = launch_tiles(ak, E.dm, E.max_tile_entries, dtype, cur, ldc, dst, ldd, s, 1, 0, st);
+      cur = dst;
+      ldc = ldd;
+    }
+    for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+    FFX_HIP(e);
+  });
+}
+
+ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
+                        void* S, void* Wlast, ffx_dtype dtype, void* stream) {
+  return guard([&] {
+    if (!A) fail(FFX_EINVAL, "matrix handle is NULL");
+    check_dtype(dtype);
+    if (A->info.nrows != A->info.ncols) fail(FFX_EINVAL, "sequence needs a square matrix");
+    if (L < 0) fail(FFX_EINVAL, "L = %lld < 0", (long long)L);
+    if (s < 1 || s > MAX_S) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, MAX_S);
+    const int64_t n = A->info.nrows;
+    check_block("U", U, n, s, ldu);
+    check_block("V", V, n, s, ldv);
+    if (L > 0 && !S) fail(FFX_EINVAL, "S is NULL");
+    if (Wlast) {
+      check_disjoint("V", V, n, ldv, "Wlast", Wlast, n, s, s, dtype);
+      check_disjoint("U", U, n, ldu, "Wlast", Wlast, n, s, s, dtype);
+      check_disjoint("S", S, L * s, s, "Wlast", Wlast, n, s, s, dtype);
+    }
+    if (L > 0) {
+      check_disjoint("U", U, n, ldu, "S", S, L * s, s, s, dtype);
+      check_disjoint("V", V, n, ldv, "S", S, L * s, s, s, dtype);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int ak = arith_kind(*A);
+    const Encoded& E = A->A;
+    size_t bytes = (size_t)std::max<int64_t>(n, 1) * s * esize(dtype);
+    void* w[2] = {nullptr, nullptr};
+    uint64_t* part = nullptr;
+    auto cleanup = [&] {
+      for (void* p : w) if (p) (void)hipFreeAsync(p, st);
+      if (part) (void)hipFreeAsync(part, st);
+    };
+    if (hipMallocAsync(&w[0], bytes, st) != hipSuccess || hipMallocAsync(&w[1], bytes, st) != hipSuccess ||
+        hipMallocAsync((void**)&part, (size_t)proj_partials() * s * s * sizeof(uint64_t), st) != hipSuccess) {
+      cleanup();
+      fail(FFX_ENOMEM, "sequence workspace allocation failed");
+    }
+    const void* cur = V;
+    int64_t ldc = ldv;
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < L && e == hipSuccess; ++i) {
+      e = launch_projection(A->md.small(), E.dm, dtype, U, ldu, cur, ldc, n, s, part,
+                            (char*)S + (size_t)i * s * s * esize(dtype), st);
+      if (e != hipSuccess) break;
+      bool need_next = i + 1 < L || Wlast;
+      if (!need_next) break;
+      void* dst = (i + 1 == L) ? Wlast : w[i & 1];
+      e = launch_tiles(ak, E.dm, E.max_tile_entries, dtype, cur, ldc, dst, s, s, 1, 0, st);
+      cur = dst;
+      ldc = s;
+    }
+    if (L == 0 && Wlast && e == hipSuccess) e = launch_copy_block(dtype, V, ldv, Wlast, s, n, s, st);
+    cleanup();
+    FFX_HIP(e);
+  });
+}
+
+const char* ffx_status_str(ffx_status st) {
+  switch (st) {
+    case FFX_OK: return "FFX_OK";
+    case FFX_EINVAL: return "FFX_EINVAL";
+    case FFX_EBOUND: return "FFX_EBOUND";
+    case FFX_ENOMEM: return "FFX_ENOMEM";
+    case FFX_EDEVICE: return "FFX_EDEVICE";
+    case FFX_EUNSUPPORTED: return "FFX_EUNSUPPORTED";
+  }
+  return "FFX_UNKNOWN";
+}
+
+const char* ffx_last_error(void) { return g_last_error.c_str(); }
+
+const char* ffx_version(void) { return "ffx 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Host-side planner and runtime structures.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ffx_impl.h"
+
+namespace ffx {
+
+// Error reporting: every C entry point converts a thrown Error into a status.
+struct Error {
+  ffx_status st;
+  std::string msg;
+};
+[[noreturn]] void fail(ffx_status st, const char* fmt, ...);
+void set_last_error(const std::string& s);
+#define FFX_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) ::ffx::fail(FFX_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+// A matrix after reduction modulo m: rows sorted by column, duplicates merged,
+// zero residues dropped; val[k] in [1, m-1].
+struct RCsr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rp;
+  std::vector<uint32_t> col;
+  std::vector<uint32_t> val;
+  int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+RCsr reduce_csr(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx, const void* vals,
+                ffx_dtype vt, uint32_t m);
+RCsr reduce_coo(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rowidx, const int32_t* colidx,
+                const void* vals, ffx_dtype vt, uint32_t m);
+RCsr transpose(const RCsr& A);
+
+// Per-block statistics (also the features of the learned selector).
+constexpr int NUM_FEATURES = 32;
+struct BlockStats {
+  int64_t row0 = 0, nrows = 0, nnz = 0;
+  double mean = 0, sd = 0;
+  int64_t maxlen = 0, minlen = 0, empty = 0;
+  double pm1_frac = 0;
+  std::vector<int32_t> band_offsets;  // chosen dense diagonals
+  int64_t band_nnz = 0;
+  int64_t sell_width_sum = 0;         // sum over 64-row slices of the longest residual row
+  int64_t sell_sorted_width_sum = 0;  // same after sorting rows by residual length
+  int64_t long_rows = 0;              // residual rows longer than one STREAM tile
+  float feat[NUM_FEATURES];
+};
+
+struct PlanOpts {
+  int acc = FFX_ACC_INT64;
+  int selector = FFX_SEL_HEURISTIC;
+  int fixed_format = FFX_FMT_STREAM;
+  bool split_pm1 = true;
+  int block_rows = 4096;
+  int tile_entries = 1024;
+  std::string model_path;
+};
+
+BlockStats block_stats(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, const PlanOpts& o);
+int heuristic_format(const BlockStats& b, const PlanOpts& o);
+
+// One encoded operator (A or A^T) on the device.
+struct Encoded {
+  DevMat dm{};
+  std::vector<void*> allocs;
+  int64_t nrows = 0, ncols = 0;
+  int64_t ntiles = 0, max_row_terms = 0, n_band = 0, n_plus = 0, n_minus = 0, nnz = 0;
+  int64_t device_bytes = 0, stream_bytes = 0;
+  int64_t max_tile_entries = 0;  // largest STREAM tile (sizes the LDS of a launch)
+  std::vector<int32_t> block_fmt;
+  int64_t format_blocks[FFX_NUM_FORMATS] = {0, 0, 0, 0, 0, 0};
+  // sizes (elements) of each device array, for the batched concatenation
+  int64_t n_ent = 0, n_val = 0, n_choff = 0, n_rowp = 0, n_perm = 0, n_swidth = 0, n_bval = 0, n_boffs = 0;
+  void release();
+};
+
+struct Modulus {
+  uint32_t m = 0;
+  uint64_t mu = 0;
+  double inv_m = 0;
+  bool small() const { return m <= 65536u; }  // (m-1)^2 < 2^32 and values fit 16 bits
+};
+Modulus make_modulus(uint32_t m);
+
+// Encodes A (block formats chosen per opts) and uploads it.
+void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t stream, Encoded* out,
+            const std::vector<int32_t>* forced_formats = nullptr);
+
+// Learned selector hook: fills fmt for the blocks, returns false to fall back.
+bool learned_formats(const std::string& model_path, const std::vector<BlockStats>& blocks, std::vector<int32_t>& fmt);
+
+}  // namespace ffx
+
+struct ffx_matrix_s {
+  ffx::Modulus md;
+  int acc = FFX_ACC_INT64;
+  bool chunk = false;   // some row needs reductions inside the row
+  ffx::Encoded A, AT;
+  bool has_t = false;
+  ffx_matrix_info info{};
+};

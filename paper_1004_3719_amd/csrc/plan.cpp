@@ -1,0 +1,460 @@
+// Row-block planning and encoding (host side).
+//
+// A matrix is cut into blocks of block_rows consecutive rows; each block gets
+// one storage format (paper Section 2.4, "Hybridization" and "Heuristic
+// format chooser": different parts of one matrix in different formats) and is
+// cut into tiles, the work unit of one workgroup. All blocks land in one set
+// of device arrays, so one kernel launch covers the whole matrix.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "host.h"
+
+namespace ffx {
+
+Modulus make_modulus(uint32_t m) {
+  Modulus md;
+  md.m = m;
+  md.mu = UINT64_MAX / m;
+  md.inv_m = 1.0 / (double)m;
+  return md;
+}
+
+void Encoded::release() {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+  dm = DevMat{};
+}
+
+static inline uint32_t tag_of(uint32_t v, uint32_t m, bool split) {
+  if (!split) return TAG_GEN;
+  if (v == 1) return TAG_PLUS;  // for m = 2, 1 = -1 is counted as +1
+  if (v == m - 1) return TAG_MINUS;
+  return TAG_GEN;
+}
+
+// ---------------------------------------------------------------------------
+// Statistics and features of rows [r0, r1).
+// ---------------------------------------------------------------------------
+constexpr int BAND_WINDOW = 128;  // dense diagonals are searched in [-128, 127]
+
+BlockStats block_stats(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, const PlanOpts& o) {
+  BlockStats b;
+  b.row0 = r0;
+  b.nrows = r1 - r0;
+  b.nnz = A.rp[r1] - A.rp[r0];
+  std::vector<int64_t> diag(2 * BAND_WINDOW, 0);
+  int64_t pm1 = 0, near[4] = {0, 0, 0, 0};
+  double s = 0, s2 = 0, spread = 0;
+  b.minlen = INT64_MAX;
+  int hist[12] = {0};
+  for (int64_t i = r0; i < r1; ++i) {
+    int64_t len = A.rp[i + 1] - A.rp[i];
+    s += (double)len;
+    s2 += (double)len * (double)len;
+    b.maxlen = std::max(b.maxlen, len);
+    b.minlen = std::min(b.minlen, len);
+    if (len == 0) b.empty++;
+    else {
+      int h = std::min(11, (int)std::floor(std::log2((double)len)));
+      hist[h]++;
+      spread += (double)(A.col[A.rp[i + 1] - 1] - A.col[A.rp[i]]) / (double)std::max<int64_t>(1, A.ncols);
+    }
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      int64_t d = (int64_t)A.col[k] - i;
+      uint32_t v = A.val[k];
+      if (v == 1 || v == m - 1) pm1++;
+      int64_t ad = d < 0 ? -d : d;
+      if (ad <= 2) near[0]++;
+      if (ad <= 8) near[1]++;
+      if (ad <= 32) near[2]++;
+      if (ad <= 64) near[3]++;
+      if (d >= -BAND_WINDOW && d < BAND_WINDOW) diag[d + BAND_WINDOW]++;
+    }
+  }
+  if (b.nrows == 0) b.minlen = 0;
+  b.mean = b.nrows ? s / (double)b.nrows : 0;
+  b.sd = b.nrows ? std::sqrt(std::max(0.0, s2 / (double)b.nrows - b.mean * b.mean)) : 0;
+  b.pm1_frac = b.nnz ? (double)pm1 / (double)b.nnz : 0;
+
+  // dense diagonals: at least 60% of the rows that can hold them
+  std::vector<std::pair<int64_t, int32_t>> cand;
+  for (int d = -BAND_WINDOW; d < BAND_WINDOW; ++d) {
+    int64_t lo = std::max<int64_t>(r0, -(int64_t)d), hi = std::min<int64_t>(r1, A.ncols - d);
+    int64_t possible = hi - lo;
+    int64_t c = diag[d + BAND_WINDOW];
+    if (possible > 0 && c > 0 && (double)c >= 0.6 * (double)possible) cand.push_back({c, d});
+  }
+  std::sort(cand.begin(), cand.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  if ((int)cand.size() > MAX_BAND) cand.resize(MAX_BAND);
+  for (auto& c : cand) {
+    b.band_offsets.push_back(c.second);
+    b.band_nnz += c.first;
+  }
+  std::sort(b.band_offsets.begin(), b.band_offsets.end());
+
+  // residual row lengths (without the band) for the ELL padding estimates
+  std::vector<int64_t> rlen(b.nrows);
+  for (int64_t i = r0; i < r1; ++i) {
+    int64_t len = A.rp[i + 1] - A.rp[i];
+    if (!b.band_offsets.empty())
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        int64_t d = (int64_t)A.col[k] - i;
+        if (std::binary_search(b.band_offsets.begin(), b.band_offsets.end(), (int32_t)d)) len--;
+      }
+    rlen[i - r0] = len;
+    if (len > o.tile_entries) b.long_rows++;
+  }
+  for (int64_t s0 = 0; s0 < b.nrows; s0 += WAVE) {
+    int64_t w = 0;
+    for (int64_t t = s0; t < std::min(b.nrows, s0 + WAVE); ++t) w = std::max(w, rlen[t]);
+    b.sell_width_sum += w;
+  }
+  std::sort(rlen.begin(), rlen.end(), std::greater<int64_t>());
+  for (int64_t s0 = 0; s0 < b.nrows; s0 += WAVE) b.sell_sorted_width_sum += rlen[s0];
+
+  // the 32 features of the learned selector
+  int64_t resid = b.nnz - b.band_nnz;
+  float* f = b.feat;
+  f[0] = (float)std::log2(1.0 + b.nrows);
+  f[1] = (float)std::log2(1.0 + b.mean);
+  f[2] = (float)std::log2(1.0 + b.sd);
+  f[3] = (float)std::log2(1.0 + b.maxlen);
+  f[4] = (float)std::log2(1.0 + b.minlen);
+  f[5] = b.nrows ? (float)b.empty / (float)b.nrows : 0.f;
+  f[6] = (float)b.pm1_frac;
+  f[7] = b.nnz ? (float)b.band_nnz / (float)b.nnz : 0.f;
+  f[8] = (float)b.band_offsets.size() / (float)MAX_BAND;
+  f[9] = (float)std::log2(1.0 + (double)b.sell_width_sum * WAVE / std::max<int64_t>(1, resid));
+  f[10] = (float)std::log2(1.0 + (double)b.sell_sorted_width_sum * WAVE / std::max<int64_t>(1, resid));
+  f[11] = b.nrows ? (float)b.long_rows / (float)b.nrows * 100.f : 0.f;
+  for (int h = 0; h < 12; ++h) f[12 + h] = b.nrows ? (float)hist[h] / (float)b.nrows : 0.f;
+  f[24] = (b.nrows - b.empty) ? (float)(spread / (double)(b.nrows - b.empty)) : 0.f;
+  for (int q = 0; q < 4; ++q) f[25 + q] = b.nnz ? (float)near[q] / (float)b.nnz : 0.f;
+  f[29] = (float)std::log2(1.0 + (double)A.ncols);
+  f[30] = b.mean > 0 ? (float)(b.sd / b.mean) : 0.f;
+  f[31] = resid > 0 ? (float)std::log2(1.0 + (double)resid / std::max<int64_t>(1, b.nrows)) : 0.f;
+  return b;
+}
+
+// The plain heuristic, after the paper's chooser (Section 2.4): an ELL-like
+// part when rows are filled evenly (the "c + r" distribution), the rest in a
+// CSR-like format; dense diagonals go to a DIA-like part. Thresholds are
+// starting points for the autotuner, not tuned constants.
+int heuristic_format(const BlockStats& b, const PlanOpts& o) {
+  int64_t resid = b.nnz - b.band_nnz;
+  bool band = !b.band_offsets.empty() && b.band_nnz >= 0.2 * (double)std::max<int64_t>(1, b.nnz);
+  double pad = (double)b.sell_width_sum * WAVE / (double)std::max<int64_t>(1, resid);
+  double pad_sorted = (double)b.sell_sorted_width_sum * WAVE / (double)std::max<int64_t>(1, resid);
+  int64_t rmax = b.maxlen;  // upper bound of the residual maximum
+  int base;
+  if (resid == 0 || (pad <= 1.3 && rmax <= 1024)) base = FFX_FMT_SELL;
+  else if (pad_sorted <= 1.3 && rmax <= 256) base = FFX_FMT_SELL_SORTED;
+  else base = FFX_FMT_STREAM;
+  (void)o;
+  if (!band) return base;
+  return base == FFX_FMT_STREAM ? FFX_FMT_BAND_STREAM : base == FFX_FMT_SELL ? FFX_FMT_BAND_SELL : FFX_FMT_BAND_SELL_SORTED;
+}
+
+// ---------------------------------------------------------------------------
+// Encoding
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HostEnc {
+  std::vector<Tile> tiles;
+  std::vector<uint32_t> ent, val, choff, rowp, perm, swidth, bval;
+  std::vector<int32_t> boffs;
+  int64_t max_tile_entries = 0;
+  int64_t n_plus = 0, n_minus = 0, n_band = 0, nnz = 0, max_row_terms = 0;
+
+  // appends up to 64 words as one value chunk
+  void push_chunk(const uint32_t* w, const uint32_t* v, int n) {
+    choff.push_back((uint32_t)val.size());
+    for (int i = 0; i < n; ++i) {
+      ent.push_back(w[i]);
+      if ((w[i] >> TAG_SHIFT) == TAG_GEN) val.push_back(v[i]);
+    }
+  }
+};
+
+struct BlockRows {  // residual entries and band values of one block
+  std::vector<int64_t> rp;        // residual row pointers (block-local)
+  std::vector<uint32_t> word, v;  // residual entries
+  std::vector<uint32_t> band;     // nrows x nd band values (0 = absent)
+  int nd = 0;
+};
+
+BlockRows split_block(const RCsr& A, int64_t r0, int64_t r1, const std::vector<int32_t>& offs, uint32_t m,
+                      bool split, HostEnc& H) {
+  BlockRows R;
+  R.nd = (int)offs.size();
+  int64_t nr = r1 - r0;
+  R.rp.assign(nr + 1, 0);
+  R.band.assign((size_t)nr * R.nd, 0);
+  for (int64_t i = r0; i < r1; ++i) {
+    H.max_row_terms = std::max<int64_t>(H.max_row_terms, A.rp[i + 1] - A.rp[i]);
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      uint32_t c = A.col[k], v = A.val[k];
+      H.nnz++;
+      if (R.nd) {
+        int64_t d = (int64_t)c - i;
+        auto it = std::lower_bound(offs.begin(), offs.end(), (int32_t)std::max<int64_t>(INT32_MIN, std::min<int64_t>(INT32_MAX, d)));
+        if (it != offs.end() && *it == d) {
+          R.band[(size_t)(i - r0) * R.nd + (it - offs.begin())] = v;
+          H.n_band++;
+          continue;
+        }
+      }
+      uint32_t t = tag_of(v, m, split);
+      if (t == TAG_PLUS) H.n_plus++;
+      if (t == TAG_MINUS) H.n_minus++;
+      R.word.push_back((t << TAG_SHIFT) | c);
+      R.v.push_back(v);
+    }
+    R.rp[i - r0 + 1] = (int64_t)R.word.size();
+  }
+  return R;
+}
+
+void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, int NE, HostEnc& H) {
+  auto rlen = [&](int64_t t) { return R.rp[t + 1] - R.rp[t]; };
+  auto push_band = [&](int64_t t0, int64_t cnt, Tile& T) {
+    T.b0 = (uint32_t)H.bval.size();
+    for (int d = 0; d < R.nd; ++d)
+      for (int64_t t = t0; t < t0 + cnt; ++t) H.bval.push_back(R.band[(size_t)t * R.nd + d]);
+  };
+  int64_t t = 0;
+  while (t < nr) {
+    if (rlen(t) > NE) {  // one long row
+      Tile T{};
+      T.kind = TK_LONG | ((uint32_t)R.nd << 8) | (1u << 16);
+      T.row0 = (uint32_t)(r0 + t);
+      T.e0 = (uint32_t)H.ent.size();
+      T.ne = (uint32_t)rlen(t);
+      T.c0 = (uint32_t)H.choff.size();
+      T.boff = boff;
+      for (int64_t k = R.rp[t]; k < R.rp[t + 1]; k += WAVE) {
+        int n = (int)std::min<int64_t>(WAVE, R.rp[t + 1] - k);
+        H.push_chunk(&R.word[k], &R.v[k], n);
+      }
+      push_band(t, 1, T);
+      H.tiles.push_back(T);
+      ++t;
+      continue;
+    }
+    int64_t t0 = t, ne = 0;
+    while (t < nr && t - t0 < TILE_THREADS && rlen(t) <= NE && ne + rlen(t) <= NE) ne += rlen(t++);
+    Tile T{};
+    int64_t rows = t - t0;
+    T.kind = TK_STREAM | ((uint32_t)R.nd << 8) | ((uint32_t)rows << 16);
+    T.row0 = (uint32_t)(r0 + t0);
+    T.e0 = (uint32_t)H.ent.size();
+    T.ne = (uint32_t)ne;
+    T.c0 = (uint32_t)H.choff.size();
+    T.aux = (uint32_t)H.rowp.size();
+    T.boff = boff;
+    for (int64_t q = t0; q <= t; ++q) H.rowp.push_back((uint32_t)(T.e0 + (R.rp[q] - R.rp[t0])));
+    for (int64_t k = R.rp[t0]; k < R.rp[t]; k += WAVE) {
+      int n = (int)std::min<int64_t>(WAVE, R.rp[t] - k);
+      H.push_chunk(&R.word[k], &R.v[k], n);
+    }
+    push_band(t0, rows, T);
+    H.max_tile_entries = std::max<int64_t>(H.max_tile_entries, ne);
+    H.tiles.push_back(T);
+  }
+}
+
+void encode_sell(const BlockRows& R, int64_t r0, int64_t nr, int64_t nrows_total, bool sorted, uint32_t boff,
+                 HostEnc& H) {
+  // slot order: rows by decreasing residual length when sorted, else natural
+  int64_t nslots = (nr + WAVE - 1) / WAVE * WAVE;
+  std::vector<int64_t> order(nslots, -1);
+  for (int64_t t = 0; t < nr; ++t) order[t] = t;
+  if (sorted)
+    std::stable_sort(order.begin(), order.begin() + nr, [&](int64_t a, int64_t b) {
+      return R.rp[a + 1] - R.rp[a] > R.rp[b + 1] - R.rp[b];
+    });
+  uint32_t words[WAVE], vals[WAVE];
+  for (int64_t s0 = 0; s0 < nslots; s0 += WAVE * SELL_SLICES) {
+    int nsl = (int)std::min<int64_t>(SELL_SLICES, (nslots - s0) / WAVE);
+    Tile T{};
+    T.kind = TK_SELL | (sorted ? TF_SORTED : 0) | ((uint32_t)R.nd << 8) | ((uint32_t)(nsl * WAVE) << 16);
+    T.e0 = (uint32_t)H.ent.size();
+    T.ne = (uint32_t)nsl;
+    T.c0 = (uint32_t)H.choff.size();
+    T.aux = (uint32_t)H.swidth.size();
+    T.boff = boff;
+    if (sorted) {
+      T.row0 = (uint32_t)H.perm.size();
+      for (int64_t q = s0; q < s0 + nsl * WAVE; ++q) H.perm.push_back(order[q] < 0 ? 0xFFFFFFFFu : (uint32_t)(r0 + order[q]));
+    } else {
+      T.row0 = (uint32_t)(r0 + s0);
+    }
+    for (int sl = 0; sl < nsl; ++sl) {
+      int64_t w = 0;
+      for (int l = 0; l < WAVE; ++l) {
+        int64_t t = order[s0 + sl * WAVE + l];
+        if (t >= 0) w = std::max<int64_t>(w, R.rp[t + 1] - R.rp[t]);
+      }
+      H.swidth.push_back((uint32_t)w);
+      for (int64_t j = 0; j < w; ++j) {
+        for (int l = 0; l < WAVE; ++l) {
+          int64_t t = order[s0 + sl * WAVE + l];
+          if (t >= 0 && j < R.rp[t + 1] - R.rp[t]) {
+            words[l] = R.word[R.rp[t] + j];
+            vals[l] = R.v[R.rp[t] + j];
+          } else {
+            words[l] = PAD_WORD;
+            vals[l] = 0;
+          }
+        }
+        H.push_chunk(words, vals, WAVE);
+      }
+    }
+    T.b0 = (uint32_t)H.bval.size();
+    for (int d = 0; d < R.nd; ++d)
+      for (int64_t q = s0; q < s0 + nsl * WAVE; ++q) {
+        int64_t t = order[q];
+        H.bval.push_back(t >= 0 ? R.band[(size_t)t * R.nd + d] : 0u);
+      }
+    (void)nrows_total;
+    H.tiles.push_back(T);
+  }
+}
+
+template <typename T>
+size_t add_part(std::vector<size_t>& offs, size_t& total, size_t n) {
+  size_t off = total;
+  offs.push_back(off);
+  total += (n * sizeof(T) + 255) / 256 * 256;
+  return off;
+}
+
+}  // namespace
+
+void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t stream, Encoded* out,
+            const std::vector<int32_t>* forced) {
+  HostEnc H;
+  const int64_t BR = o.block_rows;
+  int64_t nblocks = (A.nrows + BR - 1) / BR;
+  std::vector<BlockStats> stats(nblocks);
+  for (int64_t b = 0; b < nblocks; ++b) stats[b] = block_stats(A, b * BR, std::min(A.nrows, (b + 1) * BR), md.m, o);
+  std::vector<int32_t> fmt(nblocks, FFX_FMT_STREAM);
+  bool chosen = false;
+  if (forced) {
+    if ((int64_t)forced->size() != nblocks) fail(FFX_EINVAL, "forced format list has %zu entries, matrix has %lld blocks", forced->size(), (long long)nblocks);
+    fmt = *forced;
+    chosen = true;
+  } else if (o.selector == FFX_SEL_FIXED) {
+    std::fill(fmt.begin(), fmt.end(), o.fixed_format);
+    chosen = true;
+  } else if (o.selector == FFX_SEL_LEARNED) {
+    chosen = learned_formats(o.model_path, stats, fmt);
+  }
+  if (!chosen)
+    for (int64_t b = 0; b < nblocks; ++b) fmt[b] = heuristic_format(stats[b], o);
+
+  out->block_fmt = fmt;
+  std::fill(out->format_blocks, out->format_blocks + FFX_NUM_FORMATS, 0);
+  static const std::vector<int32_t> no_band;
+  for (int64_t b = 0; b < nblocks; ++b) {
+    int f = fmt[b];
+    if (f < 0 || f >= FFX_NUM_FORMATS) fail(FFX_EINVAL, "format %d for block %lld", f, (long long)b);
+    out->format_blocks[f]++;
+    int64_t r0 = b * BR, r1 = std::min(A.nrows, (b + 1) * BR);
+    bool band = f >= FFX_FMT_BAND_STREAM;
+    const std::vector<int32_t>& offs = band ? stats[b].band_offsets : no_band;
+    uint32_t boff = (uint32_t)H.boffs.size();
+    H.boffs.insert(H.boffs.end(), offs.begin(), offs.end());
+    BlockRows R = split_block(A, r0, r1, offs, md.m, o.split_pm1, H);
+    int base = band ? f - FFX_FMT_BAND_STREAM : f;
+    if (base == FFX_FMT_STREAM) encode_stream(R, r0, r1 - r0, boff, o.tile_entries, H);
+    else encode_sell(R, r0, r1 - r0, A.nrows, base == FFX_FMT_SELL_SORTED, boff, H);
+  }
+  if (H.ent.size() >= UINT32_MAX || H.val.size() >= UINT32_MAX || H.bval.size() >= UINT32_MAX)
+    fail(FFX_EUNSUPPORTED, "encoded matrix exceeds 2^32 words in one array");
+
+  // one device allocation, 256-byte aligned parts
+  const bool small = md.small();
+  const size_t vb = small ? 2 : 4;
+  std::vector<size_t> offs;
+  size_t total = 0;
+  add_part<Tile>(offs, total, H.tiles.size());
+  add_part<uint32_t>(offs, total, H.ent.size());
+  size_t o_val = total; offs.push_back(o_val); total += (H.val.size() * vb + 255) / 256 * 256;
+  add_part<uint32_t>(offs, total, H.choff.size());
+  add_part<uint32_t>(offs, total, H.rowp.size());
+  add_part<uint32_t>(offs, total, H.perm.size());
+  add_part<uint32_t>(offs, total, H.swidth.size());
+  size_t o_bval = total; offs.push_back(o_bval); total += (H.bval.size() * vb + 255) / 256 * 256;
+  add_part<int32_t>(offs, total, H.boffs.size());
+  if (total == 0) total = 256;
+  std::vector<unsigned char> host(total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(host.data() + off, src, bytes); };
+  put(offs[0], H.tiles.data(), H.tiles.size() * sizeof(Tile));
+  put(offs[1], H.ent.data(), H.ent.size() * 4);
+  if (small) {
+    uint16_t* p = (uint16_t*)(host.data() + offs[2]);
+    for (size_t i = 0; i < H.val.size(); ++i) p[i] = (uint16_t)H.val[i];
+    uint16_t* q = (uint16_t*)(host.data() + offs[7]);
+    for (size_t i = 0; i < H.bval.size(); ++i) q[i] = (uint16_t)H.bval[i];
+  } else {
+    put(offs[2], H.val.data(), H.val.size() * 4);
+    put(offs[7], H.bval.data(), H.bval.size() * 4);
+  }
+  put(offs[3], H.choff.data(), H.choff.size() * 4);
+  put(offs[4], H.rowp.data(), H.rowp.size() * 4);
+  put(offs[5], H.perm.data(), H.perm.size() * 4);
+  put(offs[6], H.swidth.data(), H.swidth.size() * 4);
+  put(offs[8], H.boffs.data(), H.boffs.size() * 4);
+
+  void* dev = nullptr;
+  if (hipMalloc(&dev, total) != hipSuccess) fail(FFX_ENOMEM, "hipMalloc of %zu bytes for the encoded matrix failed", total);
+  out->allocs.push_back(dev);
+  FFX_HIP(hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, stream));
+  FFX_HIP(hipStreamSynchronize(stream));
+  unsigned char* d = (unsigned char*)dev;
+  DevMat& dm = out->dm;
+  dm.tiles = (const Tile*)(d + offs[0]);
+  dm.ent = (const uint32_t*)(d + offs[1]);
+  dm.val = (const void*)(d + offs[2]);
+  dm.choff = (const uint32_t*)(d + offs[3]);
+  dm.rowp = (const uint32_t*)(d + offs[4]);
+  dm.perm = (const uint32_t*)(d + offs[5]);
+  dm.swidth = (const uint32_t*)(d + offs[6]);
+  dm.bval = (const void*)(d + offs[7]);
+  dm.boffs = (const int32_t*)(d + offs[8]);
+  dm.ntiles = (uint32_t)H.tiles.size();
+  dm.nrows = (uint32_t)A.nrows;
+  dm.ncols = (uint32_t)A.ncols;
+  dm.m = md.m;
+  dm.mu = md.mu;
+  dm.inv_m = md.inv_m;
+
+  out->nrows = A.nrows;
+  out->ncols = A.ncols;
+  out->ntiles = (int64_t)H.tiles.size();
+  out->max_row_terms = H.max_row_terms;
+  out->n_band = H.n_band;
+  out->n_plus = H.n_plus;
+  out->n_minus = H.n_minus;
+  out->nnz = H.nnz;
+  out->device_bytes = (int64_t)total;
+  out->stream_bytes = (int64_t)(H.tiles.size() * sizeof(Tile) + H.ent.size() * 4 + H.val.size() * vb +
+                                H.choff.size() * 4 + H.rowp.size() * 4 + H.perm.size() * 4 + H.swidth.size() * 4 +
+                                H.bval.size() * vb + H.boffs.size() * 4);
+  out->max_tile_entries = H.max_tile_entries;
+  out->n_ent = (int64_t)H.ent.size();
+  out->n_val = (int64_t)H.val.size();
+  out->n_choff = (int64_t)H.choff.size();
+  out->n_rowp = (int64_t)H.rowp.size();
+  out->n_perm = (int64_t)H.perm.size();
+  out->n_swidth = (int64_t)H.swidth.size();
+  out->n_bval = (int64_t)H.bval.size();
+  out->n_boffs = (int64_t)H.boffs.size();
+}
+
+}  // namespace ffx

@@ -1,0 +1,284 @@
+"""ctypes binding of libffx.so: the C ABI of include/ffx.h with the same names.
+
+Only argument marshalling happens here: device tensors are passed as raw
+pointers with their leading dimension and the current HIP stream; every step
+of a product runs in the library's kernels. There is no fallback: if the
+library is missing or does not load, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffx.so")
+
+FFX_OK, FFX_EINVAL, FFX_EBOUND, FFX_ENOMEM, FFX_EDEVICE, FFX_EUNSUPPORTED = range(6)
+FFX_I32, FFX_I64 = 0, 1
+ACC = {"auto": 0, "int64": 1, "fp64": 2}
+SEL = {"heuristic": 0, "learned": 1, "fixed": 2}
+FORMATS = ["STREAM", "SELL", "SELL_SORTED", "BAND_STREAM", "BAND_SELL", "BAND_SELL_SORTED"]
+NUM_FORMATS = len(FORMATS)
+
+
+class FfxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+STATUS_NAMES = {0: "FFX_OK", 1: "FFX_EINVAL", 2: "FFX_EBOUND", 3: "FFX_ENOMEM", 4: "FFX_EDEVICE", 5: "FFX_EUNSUPPORTED"}
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("acc", ctypes.c_int32), ("selector", ctypes.c_int32),
+                ("fixed_format", ctypes.c_int32), ("split_pm1", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("build_transpose", ctypes.c_int32), ("tile_entries", ctypes.c_int32),
+                ("model_path", ctypes.c_char_p)]
+
+
+class MatrixInfo(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("m", ctypes.c_uint32), ("acc", ctypes.c_int32),
+                ("nnz_input", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_plus", ctypes.c_int64),
+                ("n_minus", ctypes.c_int64), ("n_band", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("ntiles", ctypes.c_int64), ("max_row_terms", ctypes.c_int64), ("reduce_every", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("stream_bytes", ctypes.c_int64),
+                ("has_transpose", ctypes.c_int32), ("value_bytes", ctypes.c_int32),
+                ("format_blocks", ctypes.c_int64 * NUM_FORMATS)]
+
+
+_lib = None
+
+_SIGS = {
+    "ffx_build_opts_default": (None, [ctypes.POINTER(BuildOpts)]),
+    "ffx_matrix_create_csr": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
+                                             ctypes.POINTER(BuildOpts), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ffx_matrix_create_coo": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
+                                             ctypes.POINTER(BuildOpts), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ffx_matrix_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MatrixInfo)]),
+    "ffx_matrix_block_formats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64]),
+    "ffx_matrix_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ffx_spmv": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_void_p]),
+    "ffx_spmv_t": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                  ctypes.c_int, ctypes.c_void_p]),
+    "ffx_spmm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    "ffx_spmm_t": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    "ffx_power": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    "ffx_sequence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p]),
+    "ffx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "ffx_last_error": (ctypes.c_char_p, []),
+    "ffx_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libffx.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != FFX_OK:
+        raise FfxError(st, lib().ffx_last_error().decode())
+
+
+def _stream(stream, current=True):
+    """A HIP stream handle: the given one, else torch's current stream (or NULL, the null stream)."""
+    if stream is None:
+        if not current:
+            return ctypes.c_void_p(None)
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dt(t):
+    import torch
+    if t.dtype == torch.int32:
+        return FFX_I32
+    if t.dtype == torch.int64:
+        return FFX_I64
+    raise TypeError("vectors must be int32 or int64 tensors, got %s" % t.dtype)
+
+
+def _block(t, rows, name):
+    """(pointer, s, ld) of a device tensor holding rows x s residues, row-major with unit column stride."""
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dim() == 1:
+        if t.shape[0] != rows or (rows > 1 and t.stride(0) != 1):
+            raise ValueError("%s: expected %d contiguous entries" % (name, rows))
+        return t.data_ptr(), 1, 1
+    if t.dim() != 2 or t.shape[0] != rows or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError("%s: expected a %d x s tensor with unit column stride" % (name, rows))
+    return t.data_ptr(), t.shape[1], max(t.stride(0), t.shape[1])
+
+
+def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=True, block_rows=4096,
+               build_transpose=False, tile_entries=0, model_path=None):
+    o = BuildOpts()
+    lib().ffx_build_opts_default(ctypes.byref(o))
+    o.acc = ACC[acc]
+    if fixed_format is not None:
+        selector = "fixed"
+        o.fixed_format = FORMATS.index(fixed_format) if isinstance(fixed_format, str) else int(fixed_format)
+    o.selector = SEL[selector]
+    o.split_pm1 = int(bool(split_pm1))
+    o.block_rows = int(block_rows)
+    o.build_transpose = int(bool(build_transpose))
+    o.tile_entries = int(tile_entries)
+    o.model_path = model_path.encode() if model_path else None
+    return o
+
+
+class Matrix:
+    """An encoded matrix over Z/mZ on the device (ffx_matrix)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def from_csr(cls, nrows, ncols, rowptr, col, val, m, stream=None, **opts):
+        rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+        rp = rp - rp[0]
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val)
+        vt = FFX_I32 if v.dtype == np.int32 else FFX_I64
+        if vt == FFX_I64:
+            v = np.ascontiguousarray(v, dtype=np.int64)
+        o = build_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().ffx_matrix_create_csr(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, vt,
+                                           int(m), ctypes.byref(o), _stream(stream, False), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_coo(cls, nrows, ncols, row, col, val, m, stream=None, **opts):
+        r = np.ascontiguousarray(row, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val)
+        vt = FFX_I32 if v.dtype == np.int32 else FFX_I64
+        if vt == FFX_I64:
+            v = np.ascontiguousarray(v, dtype=np.int64)
+        o = build_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().ffx_matrix_create_coo(int(nrows), int(ncols), len(r), r.ctypes.data, c.ctypes.data,
+                                           v.ctypes.data, vt, int(m), ctypes.byref(o), _stream(stream, False),
+                                           ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_synth(cls, A, stream=None, **opts):
+        """From a synth.Csr (raw values, any int64)."""
+        return cls.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, stream=stream, **opts)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().ffx_matrix_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        I = MatrixInfo()
+        _check(lib().ffx_matrix_info_get(self._h, ctypes.byref(I)))
+        d = {k: getattr(I, k) for k, _ in MatrixInfo._fields_ if k != "format_blocks"}
+        d["format_blocks"] = {FORMATS[f]: int(I.format_blocks[f]) for f in range(NUM_FORMATS)}
+        return d
+
+    def block_formats(self, transpose=False):
+        n = self.info()["nblocks"]
+        out = np.zeros(max(1, n), np.int32)
+        _check(lib().ffx_matrix_block_formats(self._h, int(transpose), out.ctypes.data, n))
+        return out[:n]
+
+    # ----- products -----
+    def _prod(self, fn, trans, X, alpha, beta, Y, stream):
+        import torch
+        inf = self.info()
+        nin, nout = (inf["nrows"], inf["ncols"]) if trans else (inf["ncols"], inf["nrows"])
+        px, s, ldx = _block(X, nin, "x")
+        if Y is None:
+            Y = torch.empty((nout,) if X.dim() == 1 else (nout, s), dtype=X.dtype, device=X.device)
+            beta = 0
+        if Y.dtype != X.dtype:
+            raise TypeError("x and y dtypes differ")
+        py, sy, ldy = _block(Y, nout, "y")
+        if sy != s:
+            raise ValueError("x has %d columns, y has %d" % (s, sy))
+        if X.dim() == 1 and fn in ("ffx_spmv", "ffx_spmv_t"):
+            _check(getattr(lib(), fn)(self._h, int(alpha), ctypes.c_void_p(px), int(beta), ctypes.c_void_p(py),
+                                      _dt(X), _stream(stream)))
+        else:
+            f = "ffx_spmm_t" if trans else "ffx_spmm"
+            _check(getattr(lib(), f)(self._h, s, int(alpha), ctypes.c_void_p(px), ldx, int(beta), ctypes.c_void_p(py),
+                                     ldy, _dt(X), _stream(stream)))
+        return Y
+
+    def spmv(self, x, alpha=1, beta=0, y=None, stream=None):
+        return self._prod("ffx_spmv", False, x, alpha, beta, y, stream)
+
+    def spmv_t(self, x, alpha=1, beta=0, y=None, stream=None):
+        return self._prod("ffx_spmv_t", True, x, alpha, beta, y, stream)
+
+    def spmm(self, X, alpha=1, beta=0, Y=None, stream=None):
+        return self._prod("ffx_spmm", False, X, alpha, beta, Y, stream)
+
+    def spmm_t(self, X, alpha=1, beta=0, Y=None, stream=None):
+        return self._prod("ffx_spmm_t", True, X, alpha, beta, Y, stream)
+
+    def power(self, k, V, W=None, stream=None):
+        import torch
+        n = self.info()["nrows"]
+        pv, s, ldv = _block(V, n, "V")
+        if W is None:
+            W = torch.empty_like(V)
+        pw, sw, ldw = _block(W, n, "W")
+        _check(lib().ffx_power(self._h, int(k), s, ctypes.c_void_p(pv), ldv, ctypes.c_void_p(pw), ldw, _dt(V),
+                               _stream(stream)))
+        return W
+
+    def sequence(self, U, V, L, want_last=False, stream=None):
+        import torch
+        n = self.info()["nrows"]
+        pu, s, ldu = _block(U, n, "U")
+        pv, sv, ldv = _block(V, n, "V")
+        if sv != s or U.dtype != V.dtype:
+            raise ValueError("U and V must have the same width and dtype")
+        S = torch.empty((int(L), s, s), dtype=U.dtype, device=U.device)
+        W = torch.empty((n, s), dtype=U.dtype, device=U.device) if want_last else None
+        _check(lib().ffx_sequence(self._h, s, ctypes.c_void_p(pu), ldu, ctypes.c_void_p(pv), ldv, int(L),
+                                  ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(W.data_ptr() if W is not None else 0),
+                                  _dt(U), _stream(stream)))
+        return (S, W) if want_last else S
+
+
+def version():
+    return lib().ffx_version().decode()

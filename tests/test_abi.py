@@ -1,0 +1,86 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol, and rejects bad input."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1004_3719_amd as P
+from paper_1004_3719_amd import ffx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"\b(ffx_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    L = P.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = P.lib()
+    assert L.ffx_status_str(2) == b"FFX_EBOUND"
+    assert P.version().startswith("ffx")
+
+
+def _csr():
+    return np.array([0, 2, 3], np.int64), np.array([0, 1, 1], np.int32), np.array([2, -1, 3], np.int64)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2**31, 2**32 - 1])
+def test_bad_modulus(m):
+    rp, c, v = _csr()
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_csr(2, 2, rp, c, v, m)
+    assert e.value.status == ffx.FFX_EINVAL
+
+
+def test_bad_indices_and_pointers():
+    rp, c, v = _csr()
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_csr(2, 2, rp, np.array([0, 2, 1], np.int32), v, 7)
+    assert e.value.status == ffx.FFX_EINVAL and "column index" in str(e.value)
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_csr(2, 2, np.array([0, 2, 1], np.int64), c, v, 7)
+    assert e.value.status == ffx.FFX_EINVAL
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_coo(2, 2, [0, 5], [0, 1], np.array([1, 1], np.int64), 7)
+    assert e.value.status == ffx.FFX_EINVAL
+
+
+def test_fp64_bound_refused():
+    # (m-1)^2 >= 2^53 when m > 94906266: one product alone is not exact in a double
+    rp, c, v = _csr()
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_csr(2, 2, rp, c, v, 2**31 - 1, acc="fp64")
+    assert e.value.status == ffx.FFX_EBOUND
+
+
+def test_bad_options():
+    rp, c, v = _csr()
+    for kw in [dict(block_rows=100), dict(block_rows=0), dict(tile_entries=100), dict(fixed_format=9)]:
+        with pytest.raises(P.FfxError) as e:
+            P.Matrix.from_csr(2, 2, rp, c, v, 7, **kw)
+        assert e.value.status == ffx.FFX_EINVAL, kw
+
+
+def test_null_out_pointer():
+    L = P.lib()
+    rp, c, v = _csr()
+    st = L.ffx_matrix_create_csr(2, 2, rp.ctypes.data, c.ctypes.data, v.ctypes.data, 1, 7, None, None, None)
+    assert st == ffx.FFX_EINVAL

@@ -1,0 +1,300 @@
+"""GPU parity: every product of libffx.so against the oracle, bit for bit.
+
+Inputs are the seeded synthetic workloads at sizes the oracle finishes in
+seconds (several blocks and tiles, ragged tails, long rows), plus the full
+power-law size checked on sampled rows. Every format is forced on every block
+and must give the identical residues.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["STREAM", "SELL", "SELL_SORTED", "BAND_STREAM", "BAND_SELL", "BAND_SELL_SORTED"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+@pytest.fixture(scope="module")
+def ffx():
+    from paper_1004_3719_amd import Matrix
+    return Matrix
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+
+
+def tdev(a, dev, dtype=torch.int32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+
+def vec(seed, tag, n, m, s=None):
+    v = synth.vector(seed, tag, n * (s or 1), 0, m - 1)
+    return v if s is None else v.reshape(n, s)
+
+
+def subrows(A, rows):
+    """The CSR of the given rows of A (for sampled oracle checks)."""
+    rows = np.asarray(rows)
+    lens = A.rowptr[rows + 1] - A.rowptr[rows]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    idx = np.concatenate([np.arange(A.rowptr[r], A.rowptr[r + 1]) for r in rows]) if len(rows) else np.zeros(0, int)
+    return synth.Csr(len(rows), A.ncols, rp, A.col[idx], A.val[idx], m=A.m)
+
+
+# ---------------------------------------------------------------- SpMV -----
+@pytest.mark.parametrize("fmt", [None] + FORMATS)
+@pytest.mark.parametrize("acc", ["int64", "fp64"])
+def test_c1_spmv(dev, orc, ffx, fmt, acc):
+    A = synth.c1()
+    note("c1 spmv", fmt, acc)
+    M = ffx.from_synth(A, fixed_format=fmt, acc=acc)
+    x = vec(1, 1, A.ncols, A.m)
+    y0 = vec(1, 2, A.nrows, A.m)
+    for dt in (torch.int32, torch.int64):
+        got = M.spmv(tdev(x, dev, dt)).cpu().numpy()
+        assert np.array_equal(got, orc.spmv(A, x))
+    for alpha, beta in [(3, 5), (A.m - 1, A.m - 1), (0, 7), (1, 1)]:
+        y = tdev(y0, dev)
+        M.spmv(tdev(x, dev), alpha=alpha, beta=beta, y=y)
+        assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, alpha, beta, y0)), (alpha, beta)
+
+
+@pytest.mark.parametrize("fmt", [None, "STREAM", "SELL", "BAND_STREAM"])
+def test_c1_spmv_t(dev, orc, ffx, fmt):
+    A = synth.c1()
+    note("c1 spmv_t", fmt)
+    M = ffx.from_synth(A, fixed_format=fmt, build_transpose=True)
+    x = vec(1, 3, A.nrows, A.m)
+    y0 = vec(1, 4, A.ncols, A.m)
+    assert np.array_equal(M.spmv_t(tdev(x, dev)).cpu().numpy(), orc.spmv_t(A, x))
+    y = tdev(y0, dev)
+    M.spmv_t(tdev(x, dev), alpha=11, beta=13, y=y)
+    assert np.array_equal(y.cpu().numpy(), orc.spmv_t(A, x, 11, 13, y0))
+
+
+@pytest.mark.parametrize("fmt", [None] + FORMATS)
+@pytest.mark.parametrize("acc", ["int64", "fp64"])
+def test_powerlaw_spmv(dev, orc, ffx, fmt, acc):
+    """The power-law + band + 60% +-1 workload at n = 120,000 (30 blocks, rows up to 5,000 terms)."""
+    A = synth.c2(n=120_000)
+    note("c2-scaled spmv", fmt, acc, A.nnz)
+    M = ffx.from_synth(A, fixed_format=fmt, acc=acc, build_transpose=True)
+    inf = M.info()
+    assert inf["n_plus"] + inf["n_minus"] + inf["n_band"] > 0.5 * inf["nnz"]
+    x = vec(2, 1, A.ncols, A.m)
+    assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+    xt = vec(2, 2, A.nrows, A.m)
+    assert np.array_equal(M.spmv_t(tdev(xt, dev)).cpu().numpy(), orc.spmv_t(A, xt))
+
+
+def test_pm1_split_off_same(dev, orc, ffx):
+    A = synth.c2(n=30_000)
+    x = vec(3, 1, A.ncols, A.m)
+    note("pm1 off")
+    a = ffx.from_synth(A, split_pm1=False).spmv(tdev(x, dev)).cpu().numpy()
+    b = ffx.from_synth(A, split_pm1=True).spmv(tdev(x, dev)).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, orc.spmv(A, x))
+
+
+@pytest.mark.parametrize("tile_entries", [256, 4096])
+def test_tile_sizes(dev, orc, ffx, tile_entries):
+    A = synth.c2(n=40_000)
+    x = vec(4, 1, A.ncols, A.m)
+    note("tile", tile_entries)
+    M = ffx.from_synth(A, fixed_format="BAND_STREAM", tile_entries=tile_entries)
+    assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+
+
+# ------------------------------------------------------- moduli and bounds --
+@pytest.mark.parametrize("m", [2, 3, 27, 65521, 65537, 1_000_003, 94_906_263, 2**31 - 1])
+@pytest.mark.parametrize("acc", ["int64", "fp64"])
+def test_moduli(dev, orc, ffx, m, acc):
+    s = synth.spec(4000, 3000, 77 + m, len_kind=synth.LEN_ZIPF, len_a=1, len_b=1500, len_alpha=1.5,
+                   col_kind=synth.COL_UNIFORM, band_lo=-1, band_hi=1, p_pm1=0.4, val_lo=-(2**40), val_hi=2**40)
+    A = synth.rows(s)
+    A.m = m
+    note("modulus", m, acc)
+    if acc == "fp64" and (m - 1) ** 2 >= 2**53:
+        with pytest.raises(Exception):
+            ffx.from_synth(A, acc=acc)
+        return
+    M = ffx.from_synth(A, acc=acc, build_transpose=True)
+    x = vec(5, 1, A.ncols, m)
+    assert np.array_equal(M.spmv(tdev(x, dev, torch.int64)).cpu().numpy(), orc.spmv(A, x))
+    xt = vec(5, 2, A.nrows, m)
+    assert np.array_equal(M.spmv_t(tdev(xt, dev, torch.int64)).cpu().numpy(), orc.spmv_t(A, xt))
+
+
+@pytest.mark.parametrize("m,acc", [(2**31 - 1, "int64"), (94_906_263, "fp64"), (65521, "fp64"), (3_000_017, "int64")])
+@pytest.mark.parametrize("fmt", ["STREAM", "SELL", "BAND_SELL_SORTED"])
+@pytest.mark.parametrize("split", [False, True])
+def test_bound_edges(dev, orc, ffx, m, acc, fmt, split):
+    """Every value and x entry is m-1 (each term is the largest possible), rows of every length
+    around the reduction bound; the answer is the row length mod m."""
+    lens = np.array(list(range(0, 40)) + [63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 2047, 3000, 5000])
+    n = 6000
+    rng = np.random.default_rng(9)
+    rows = [np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    A = synth.Csr(len(lens), n, rp, np.concatenate(rows).astype(np.int32), np.full(int(lens.sum()), -1, np.int64), m=m)
+    note("bound edge", m, acc, fmt, split)
+    M = ffx.from_synth(A, acc=acc, fixed_format=fmt, split_pm1=split)
+    x = np.full(n, m - 1, np.int64)
+    got = M.spmv(tdev(x, dev, torch.int64)).cpu().numpy()
+    assert np.array_equal(got, lens % m)
+    assert np.array_equal(got, orc.spmv(A, x))
+
+
+# ---------------------------------------------------------------- SpMM -----
+@pytest.mark.parametrize("s", [1, 2, 3, 5, 8, 13, 16])
+@pytest.mark.parametrize("fmt", [None, "STREAM", "SELL_SORTED", "BAND_SELL"])
+def test_spmm(dev, orc, ffx, s, fmt):
+    A = synth.c2(n=20_000)
+    note("spmm", s, fmt)
+    M = ffx.from_synth(A, fixed_format=fmt, build_transpose=True)
+    X = vec(6, s, A.ncols, A.m, s)
+    ld = s + 3
+    Xp = np.zeros((A.ncols, ld), np.int64)
+    Xp[:, :s] = X
+    Xd = tdev(Xp, dev)[:, :s]
+    Y0 = vec(7, s, A.nrows, A.m, s)
+    Yd = tdev(Y0, dev)
+    M.spmm(Xd, alpha=9, beta=4, Y=Yd)
+    assert np.array_equal(Yd.cpu().numpy(), orc.spmm(A, X, 9, 4, Y0))
+    Xt = vec(8, s, A.nrows, A.m, s)
+    assert np.array_equal(M.spmm_t(tdev(Xt, dev, torch.int64)).cpu().numpy(), orc.spmm_t(A, Xt))
+
+
+# ------------------------------------------------------ power and sequence --
+@pytest.mark.parametrize("k", [0, 1, 2, 5])
+def test_power(dev, orc, ffx, k):
+    A = synth.c3(n=3000, ndead=30, m=65521)
+    note("power", k)
+    M = ffx.from_synth(A)
+    V = vec(9, 1, A.nrows, A.m, 4)
+    W = M.power(k, tdev(V, dev, torch.int64)).cpu().numpy()
+    assert np.array_equal(W, orc.power(A, k, V))
+
+
+@pytest.mark.parametrize("m,s,dt", [(2**31 - 1, 8, torch.int64), (65521, 3, torch.int32), (32749, 1, torch.int32)])
+def test_sequence_full_length(dev, orc, ffx, m, s, dt):
+    """The whole sequence i = 0 .. 2n/s + 2 at n = 2,000 (10 dead columns), and A^L V."""
+    n = 2000
+    A = synth.c3(n=n, ndead=10, m=m)
+    L = synth.c3_length(n, s)
+    U, V = synth.c3_blocks(n=n, s=s, m=m)
+    note("sequence", m, s, L)
+    M = ffx.from_synth(A)
+    S, W = M.sequence(tdev(U, dev, dt), tdev(V, dev, dt), L, want_last=True)
+    So, Wo = orc.sequence(A, U, V, L, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
+
+
+def test_sequence_prefix_full_size(dev, orc, ffx):
+    """The block-Wiedemann operand at full size (n = 200,000, s = 8, m = 2^31-1): the first 6
+    sequence terms and a 4-term segment restarted from the GPU's own A^6 V."""
+    A = synth.c3()
+    U, V = synth.c3_blocks()
+    note("sequence full-size prefix")
+    M = ffx.from_synth(A)
+    S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), 6, want_last=True)
+    So, Wo = orc.sequence(A, U, V, 6, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
+    W6 = W.cpu().numpy()
+    S2 = M.sequence(tdev(U, dev, torch.int64), W, 4).cpu().numpy()
+    assert np.array_equal(S2, orc.sequence(A, U, W6, 4))
+
+
+# ---------------------------------------------------------- edge cases -----
+def test_degenerate_shapes(dev, orc, ffx):
+    note("degenerate shapes")
+    cases = []
+    cases.append(synth.Csr(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([-1]), m=7))
+    cases.append(synth.Csr(5, 3, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64), m=7))
+    s = synth.spec(70, 9000, 5, len_kind=synth.LEN_UNIFORM, len_a=0, len_b=3000, col_kind=synth.COL_UNIFORM,
+                   p_pm1=0.5, val_lo=-5, val_hi=5)
+    W = synth.rows(s)
+    W.m = 65521
+    cases.append(W)
+    s = synth.spec(9000, 70, 6, len_kind=synth.LEN_UNIFORM, len_a=0, len_b=5, col_kind=synth.COL_UNIFORM,
+                   p_pm1=0.5, val_lo=-5, val_hi=5)
+    T = synth.rows(s)
+    T.m = 65521
+    cases.append(T)
+    for A in cases:
+        for fmt in [None] + FORMATS:
+            M = ffx.from_synth(A, fixed_format=fmt, build_transpose=True)
+            x = vec(10, 1, A.ncols, A.m)
+            assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x)), (A, fmt)
+            xt = vec(10, 2, A.nrows, A.m)
+            assert np.array_equal(M.spmv_t(tdev(xt, dev)).cpu().numpy(), orc.spmv_t(A, xt)), (A, fmt)
+
+
+def test_duplicates_and_unsorted(dev, orc, ffx):
+    note("duplicates")
+    rng = np.random.default_rng(3)
+    n, nnz = 500, 20_000
+    r = rng.integers(0, n, nnz).astype(np.int32)
+    c = rng.integers(0, 40, nnz).astype(np.int32)  # many duplicates
+    v = rng.integers(-(2**62), 2**62, nnz)
+    M = ffx.from_coo(n, 40, r, c, v, 65521)
+    order = np.argsort(r, kind="stable")
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, r + 1, 1)
+    rp = np.cumsum(rp)
+    A = synth.Csr(n, 40, rp, c[order], v[order], m=65521)
+    x = vec(11, 1, 40, 65521)
+    assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+    M2 = ffx.from_csr(n, 40, rp, c[order], v[order], 65521)
+    assert np.array_equal(M2.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+
+
+def test_determinism(dev, ffx):
+    A = synth.c2(n=200_000)
+    note("determinism")
+    M = ffx.from_synth(A, build_transpose=True)
+    x = tdev(vec(12, 1, A.ncols, A.m), dev)
+    ref = M.spmv(x).cpu().numpy()
+    reft = M.spmv_t(x).cpu().numpy()
+    for _ in range(10):
+        assert np.array_equal(M.spmv(x).cpu().numpy(), ref)
+        assert np.array_equal(M.spmv_t(x).cpu().numpy(), reft)
+
+
+def test_c2_full_size_sampled(dev, orc, ffx):
+    """The 2,000,000-row power-law matrix in the benchmark's configuration: sampled rows
+    (random ones and the longest ones) against the oracle, on both accumulators."""
+    A = synth.c2()
+    note("c2 full", A.nnz)
+    x = vec(13, 1, A.ncols, A.m)
+    lens = np.diff(A.rowptr)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.choice(A.nrows, 4000, replace=False), np.argsort(lens)[-200:],
+                                     np.arange(10), np.arange(A.nrows - 10, A.nrows)]))
+    want = orc.spmv(subrows(A, rows), x)
+    for acc in ["int64", "fp64"]:
+        M = ffx.from_synth(A, acc=acc)
+        got = M.spmv(tdev(x, dev)).cpu().numpy()
+        assert np.array_equal(got[rows], want), acc
+        assert got.min() >= 0 and got.max() < A.m
+        M.close()
