@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
     ap.add_argument("--selector", default="heuristic", choices=["heuristic", "learned"])
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
+    ap.add_argument("--tile-entries", type=int, default=0)
+    ap.add_argument("--fixed-format", default=None)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -82,7 +84,7 @@ def main():
     x_np = synth.vector(synth.SEED0 + 1, 1, A.ncols, 0, m - 1)
     print("[bench] generated n=%d nnz=%d in %.1fs" % (A.nrows, A.nnz, time.time() - t0), file=sys.stderr, flush=True)
     t0 = time.time()
-    opts = dict(acc=args.acc, selector=args.selector)
+    opts = dict(acc=args.acc, selector=args.selector, tile_entries=args.tile_entries, fixed_format=args.fixed_format)
     if args.selector == "learned":
         opts["model_path"] = args.model
     M = Matrix.from_synth(A, **opts)

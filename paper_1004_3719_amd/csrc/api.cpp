@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "host.h"
@@ -75,8 +76,25 @@ static PlanOpts plan_opts(const ffx_build_opts* o) {
   int te = d.tile_entries ? d.tile_entries : 1024;
   if (te < 256 || te > 4096) fail(FFX_EINVAL, "tile_entries %d outside [256, 4096]", te);
   p.tile_entries = te;
+  if (d.compact_x < -1 || d.compact_x > 1) fail(FFX_EINVAL, "compact_x %d not in {-1, 0, 1}", d.compact_x);
+  p.compact_x = d.compact_x;
   if (d.model_path) p.model_path = d.model_path;
   return p;
+}
+
+// Keeps freed stream-ordered allocations in the device pool, so the per-call
+// workspaces of products do not return to the driver between calls.
+static void warm_pool(hipStream_t st) {
+  static std::once_flag once;
+  std::call_once(once, [&] {
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+  (void)st;
 }
 
 static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts, int build_t, hipStream_t st) {
@@ -108,6 +126,7 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
       for (int64_t v : cnt) maxterms = std::max(maxterms, v);
     }
     M->chunk = maxterms > b;
+    M->compact_x = M->md.small() && (po.compact_x == 1 || (po.compact_x == -1 && A.ncols * 4 > (1 << 20)));
     M->A.dm.reduce_every = b;
     M->AT.dm.reduce_every = b;
     ffx_matrix_info& I = M->info;
@@ -177,7 +196,19 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
   if (trans && !M->has_t)
     fail(FFX_EUNSUPPORTED, "transpose product without a stored A^T (build with build_transpose = 1)");
   const Encoded& E = trans ? M->AT : M->A;
-  FFX_HIP(launch_tiles(arith_kind(*M), E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st));
+  const int ak = arith_kind(*M);
+  if (s == 1 && M->compact_x && nin > 0) {
+    warm_pool(st);
+    uint16_t* x16 = nullptr;
+    if (hipMallocAsync((void**)&x16, (size_t)nin * 2, st) != hipSuccess)
+      fail(FFX_ENOMEM, "hipMallocAsync of %lld bytes failed", (long long)nin * 2);
+    hipError_t e = launch_compact_x(dt, X, ldx, x16, nin, st);
+    if (e == hipSuccess) e = launch_tiles(ak, E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16);
+    (void)hipFreeAsync(x16, st);
+    FFX_HIP(e);
+    return;
+  }
+  FFX_HIP(launch_tiles(ak, E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st));
 }
 
 }  // namespace ffx
@@ -197,6 +228,7 @@ void ffx_build_opts_default(ffx_build_opts* o) {
   o->block_rows = 4096;
   o->build_transpose = 0;
   o->tile_entries = 0;
+  o->compact_x = -1;
   o->model_path = nullptr;
 }
 

@@ -61,6 +61,7 @@ struct PlanOpts {
   bool split_pm1 = true;
   int block_rows = 4096;
   int tile_entries = 1024;
+  int compact_x = -1;
   std::string model_path;
 };
 
@@ -103,6 +104,7 @@ struct ffx_matrix_s {
   ffx::Modulus md;
   int acc = FFX_ACC_INT64;
   bool chunk = false;   // some row needs reductions inside the row
+  bool compact_x = false;  // one-vector products gather x from a 16-bit copy
   ffx::Encoded A, AT;
   bool has_t = false;
   ffx_matrix_info info{};

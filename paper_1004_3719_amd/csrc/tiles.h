@@ -1,4 +1,4 @@
-// gfx950 kernels for y = alpha*A*X + beta*Y over Z/mZ on the tile table.
+// gfx950 kernels for Y = alpha*A*X + beta*Y over Z/mZ on the tile table.
 //
 // One launch covers the whole matrix: workgroup g takes tile g, whatever the
 // format of its row block. Three tile shapes:
@@ -16,12 +16,21 @@
 // Every tile may carry a band part: dense diagonals with one value per row,
 // applied by one lane per row (the DIA idea of Section 2.1).
 //
+// Latency: a lane issues the loads of U chunks (entry words, then values and
+// gathers) before it uses any of them, and the band part and row pointers,
+// which do not depend on the entry stream, are loaded before it.
+//
 // Arithmetic (Section 2.2): each lane sums its terms in a wide accumulator
 // and reduces modulo m only when the next term could overflow what the type
 // represents exactly (CHUNK variants; the host sets reduce_every from the
 // bound), otherwise once per row. Entries of residue 1 and m-1 carry no value
 // and add x or m - x (Section 2.4, "Taking into account the +-1").
+//
+// Tx is the element type read from X (int32, int64, or a 16-bit copy of x
+// when m <= 65536), Tv the element type of Y.
 #pragma once
+
+#include <algorithm>
 
 #include "ffx_impl.h"
 
@@ -111,9 +120,10 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask, int width) {
 __device__ inline double shfl_xor_acc(double v, int mask, int width) { return __shfl_xor(v, mask, width); }
 __device__ inline uint64_t shfl_xor_acc(uint64_t v, int mask, int width) { return shfl_xor_u64(v, mask, width); }
 
+// stored values are streamed once: non-temporal loads keep them out of the way of x in L2
 template <typename V>
 __device__ inline uint32_t ldval(const void* p, uint32_t i) {
-  return (uint32_t)((const V*)p)[i];
+  return (uint32_t)__builtin_nontemporal_load((const V*)p + i);
 }
 
 // Writes row `row` of Y from the residues r[0..s).
@@ -131,28 +141,84 @@ __device__ inline void write_row(const DevMat& A, Tv* Y, int64_t ldy, uint32_t r
   }
 }
 
-// Adds the band terms of one row (diagonals d = first, first+step, ...).
-template <class AR, typename Tv, int S>
+// Adds the band terms of one row (diagonals d = first, first+step, ...). The
+// x address depends only on the row and the offset, never on the stored value
+// (absent entries hold 0), so all loads of a batch are issued together.
+constexpr int BAND_BATCH = 8;
+template <class AR, typename Tx, int S>
 __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>& acc, uint32_t row, uint32_t slot,
-                                  uint32_t rows_in_tile, uint32_t first, uint32_t step, const Tv* X, int64_t ldx,
+                                  uint32_t rows_in_tile, uint32_t first, uint32_t step, const Tx* X, int64_t ldx,
                                   int s) {
   const uint32_t nd = tile_nd(T.kind);
-  for (uint32_t d = first; d < nd; d += step) {
-    uint32_t v = ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot);
-    if (v) {
-      int64_t col = (int64_t)row + A.boffs[T.boff + d];
-      const Tv* xr = X + col * ldx;
+  for (uint32_t d0 = first; d0 < nd; d0 += BAND_BATCH * step) {
+    uint32_t v[BAND_BATCH];
+    uint32_t xv[BAND_BATCH][S];
 #pragma unroll
-      for (int c = 0; c < S; ++c)
-        if (c < s) acc.a[c] += AR::mul(v, (uint32_t)xr[c]);
-      acc.tick(A);
+    for (int q = 0; q < BAND_BATCH; ++q) {
+      uint32_t d = d0 + q * step;
+      bool in = d < nd;
+      v[q] = in ? ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot) : 0u;
+      int64_t col = in ? (int64_t)row + A.boffs[T.boff + d] : -1;
+      bool ok = col >= 0 && col < (int64_t)A.ncols;
+      const Tx* xr = X + (ok ? col : 0) * ldx;
+#pragma unroll
+      for (int c = 0; c < S; ++c) xv[q][c] = (ok && c < s) ? (uint32_t)xr[c] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < BAND_BATCH; ++q) {
+      if (d0 + q * step < nd) {
+#pragma unroll
+        for (int c = 0; c < S; ++c) acc.a[c] += AR::mul(v[q], xv[q][c]);
+        acc.tick(A);
+      }
     }
   }
 }
 
+// U chunks of 64 entries: all entry words first, then the values (one ballot
+// per chunk) and the gathered x, then the terms.
+template <class AR, typename Tx, int S, int U>
+struct ChunkBatch {
+  uint32_t w[U];
+  uint32_t v[U];
+  uint32_t xv[U][S];
+  // word_at(u): this lane's entry word pointer in chunk u, or null; choff_at(u): the chunk's value offset
+  template <class WordAt, class ChOff>
+  __device__ inline void load(const DevMat& A, const Tx* X, int64_t ldx, int s, WordAt word_at, ChOff choff_at) {
+    uint32_t vo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t* p = word_at(u);
+      w[u] = p ? __builtin_nontemporal_load(p) : PAD_WORD;
+      vo[u] = choff_at(u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t tag = w[u] >> TAG_SHIFT;
+      uint64_t gm = __ballot(tag == TAG_GEN);
+      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, vo[u] + lanes_below(gm)) : 0u;
+      const Tx* xr = X + (int64_t)(w[u] & COL_MASK) * ldx;
+#pragma unroll
+      for (int c = 0; c < S; ++c) xv[u][c] = (tag != TAG_PAD && c < s) ? (uint32_t)xr[c] : 0u;
+    }
+  }
+  __device__ inline void accumulate(const DevMat& A, LaneAcc<AR, S>& acc, int s) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t tag = w[u] >> TAG_SHIFT;
+      if (tag != TAG_PAD) {
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+          if (c < s) acc.a[c] += term<AR>(tag, v[u], xv[u][c], A.m);
+        acc.tick(A);
+      }
+    }
+  }
+};
+
 // ------------------------------- SELL tile ---------------------------------
-template <class AR, typename Tv, int S>
-__device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tv* __restrict__ X, int64_t ldx,
+template <class AR, typename Tx, typename Tv, int S, int U>
+__device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                  Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta) {
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t nsl = T.ne;
@@ -167,21 +233,16 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tv* __res
   const uint32_t* choff = A.choff + T.c0 + off;
   LaneAcc<AR, S> acc;
   acc.init(A);
-  for (uint32_t j = 0; j < width; ++j) {
-    uint32_t w = ent[(size_t)j * WAVE];
-    uint32_t tag = w >> TAG_SHIFT;
-    uint64_t gm = __ballot(tag == TAG_GEN);
-    if (tag != TAG_PAD) {
-      uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j] + lanes_below(gm)) : 0u;
-      const Tv* xr = X + (int64_t)(w & COL_MASK) * ldx;
-#pragma unroll
-      for (int c = 0; c < S; ++c)
-        if (c < s) acc.a[c] += term<AR>(tag, v, (uint32_t)xr[c], A.m);
-      acc.tick(A);
-    }
+  if (valid) band_terms<AR, Tx, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
+  for (uint32_t j0 = 0; j0 < width; j0 += U) {
+    ChunkBatch<AR, Tx, S, U> b;
+    b.load(
+        A, X, ldx, s,
+        [&](int u) -> const uint32_t* { return j0 + u < width ? ent + (size_t)(j0 + u) * WAVE : nullptr; },
+        [&](int u) -> uint32_t { return j0 + u < width ? choff[j0 + u] : 0u; });
+    b.accumulate(A, acc, s);
   }
   if (!valid) return;
-  band_terms<AR, Tv, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
   uint32_t r[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) r[c] = AR::reduce(acc.a[c], A);
@@ -189,30 +250,31 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tv* __res
 }
 
 // ------------------------------- LONG tile ---------------------------------
-template <class AR, typename Tv, int S>
-__device__ inline void long_tile(const DevMat& A, const Tile& T, const Tv* __restrict__ X, int64_t ldx,
+template <class AR, typename Tx, typename Tv, int S, int U>
+__device__ inline void long_tile(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                  Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta,
                                  unsigned char* lds) {
   using Acc = typename AR::Acc;
+  constexpr uint32_t NW = TILE_THREADS / WAVE;
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t nchunks = (T.ne + WAVE - 1) / WAVE;
   LaneAcc<AR, S> acc;
   acc.init(A);
-  for (uint32_t ch = wave; ch < nchunks; ch += TILE_THREADS / WAVE) {
-    uint32_t k = ch * WAVE + lane;
-    uint32_t w = k < T.ne ? A.ent[T.e0 + k] : PAD_WORD;
-    uint32_t tag = w >> TAG_SHIFT;
-    uint64_t gm = __ballot(tag == TAG_GEN);
-    if (tag != TAG_PAD) {
-      uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, A.choff[T.c0 + ch] + lanes_below(gm)) : 0u;
-      const Tv* xr = X + (int64_t)(w & COL_MASK) * ldx;
-#pragma unroll
-      for (int c = 0; c < S; ++c)
-        if (c < s) acc.a[c] += term<AR>(tag, v, (uint32_t)xr[c], A.m);
-      acc.tick(A);
-    }
+  band_terms<AR, Tx, S>(A, T, acc, T.row0, 0, 1, threadIdx.x, TILE_THREADS, X, ldx, s);
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    ChunkBatch<AR, Tx, S, U> b;
+    b.load(
+        A, X, ldx, s,
+        [&](int u) -> const uint32_t* {
+          uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
+          return (ch < nchunks && k < T.ne) ? A.ent + T.e0 + k : nullptr;
+        },
+        [&](int u) -> uint32_t {
+          uint32_t ch = ch0 + u * NW;
+          return ch < nchunks ? A.choff[T.c0 + ch] : 0u;
+        });
+    b.accumulate(A, acc, s);
   }
-  band_terms<AR, Tv, S>(A, T, acc, T.row0, 0, 1, threadIdx.x, TILE_THREADS, X, ldx, s);
   acc.to_residues(A);
   Acc* red = (Acc*)lds;  // [4 waves][S]
 #pragma unroll
@@ -227,7 +289,7 @@ __device__ inline void long_tile(const DevMat& A, const Tile& T, const Tv* __res
 #pragma unroll
     for (int c = 0; c < S; ++c) {
       Acc t = 0;
-      for (int q = 0; q < TILE_THREADS / WAVE; ++q) t += red[q * S + c];
+      for (uint32_t q = 0; q < NW; ++q) t += red[q * S + c];
       r[c] = AR::reduce(t, A);
     }
     write_row<Tv, S>(A, Y, ldy, T.row0, r, s, alpha, beta);
@@ -235,94 +297,137 @@ __device__ inline void long_tile(const DevMat& A, const Tile& T, const Tv* __res
 }
 
 // ------------------------------- STREAM tile -------------------------------
-// one vector: terms to LDS, then groups of lanes per row
-template <class AR, typename Tv>
-__device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tv* __restrict__ X, int64_t ldx,
+// One vector. The tile's terms (value times gathered x) go to LDS; then every
+// thread sums an equal run of consecutive terms and adds each row's piece to
+// that row's LDS sum with an LDS atomic (exact in any order: integers, or
+// integer-valued doubles below 2^53), so one long row inside a tile does not
+// serialize on one lane. Row pointers and the band part are loaded first.
+template <class AR, typename Tx, typename Tv, int U>
+__device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                      Tv* __restrict__ Y, int64_t ldy, uint32_t alpha, uint32_t beta,
                                      unsigned char* lds) {
   using Prod = typename AR::Prod;
   using Acc = typename AR::Acc;
-  Prod* prod = (Prod*)lds;
+  constexpr uint32_t NW = TILE_THREADS / WAVE;
+  Acc* rowsum = (Acc*)lds;                                 // [256]
+  uint32_t* rps = (uint32_t*)(rowsum + TILE_THREADS);     // [257] tile-relative row starts
+  Prod* prod = (Prod*)(rps + TILE_THREADS + 4);            // [ne]
   const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-  const uint32_t nchunks = (T.ne + WAVE - 1) / WAVE;
-  for (uint32_t ch = wave; ch < nchunks; ch += TILE_THREADS / WAVE) {
-    uint32_t k = ch * WAVE + lane;
-    bool in = k < T.ne;
-    uint32_t w = in ? A.ent[T.e0 + k] : PAD_WORD;
-    uint32_t tag = w >> TAG_SHIFT;
-    uint64_t gm = __ballot(tag == TAG_GEN);
-    Prod p = 0;
-    if (tag != TAG_PAD) {
-      uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, A.choff[T.c0 + ch] + lanes_below(gm)) : 0u;
-      p = term<AR>(tag, v, (uint32_t)X[(int64_t)(w & COL_MASK) * ldx], A.m);
+  const uint32_t ne = T.ne;
+  const uint32_t nchunks = (ne + WAVE - 1) / WAVE;
+  const uint32_t nr = tile_rows(T.kind);
+  if (tid < nr) rps[tid] = A.rowp[T.aux + tid] - T.e0;
+  if (tid == 0) rps[nr] = ne;  // nr may be 256: the sentinel needs its own writer
+  if (tid < nr) {
+    LaneAcc<AR, 1> band;
+    band.init(A);
+    band_terms<AR, Tx, 1>(A, T, band, T.row0 + tid, tid, nr, 0, 1, X, ldx, 1);
+    band.to_residues(A);
+    rowsum[tid] = band.a[0];
+  }
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    ChunkBatch<AR, Tx, 1, U> b;
+    b.load(
+        A, X, ldx, 1,
+        [&](int u) -> const uint32_t* {
+          uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
+          return (ch < nchunks && k < ne) ? A.ent + T.e0 + k : nullptr;
+        },
+        [&](int u) -> uint32_t {
+          uint32_t ch = ch0 + u * NW;
+          return ch < nchunks ? A.choff[T.c0 + ch] : 0u;
+        });
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
+      if (ch < nchunks && k < ne) prod[k] = term<AR>(b.w[u] >> TAG_SHIFT, b.v[u], b.xv[u][0], A.m);
     }
-    if (in) prod[k] = p;
   }
   __syncthreads();
-  const uint32_t nr = tile_rows(T.kind);
-  uint32_t lpr = 1;
-  while (lpr < WAVE && lpr * 2 * nr <= TILE_THREADS) lpr <<= 1;
-  const uint32_t r = tid / lpr, sub = tid & (lpr - 1);
-  const bool active = r < nr;
-  LaneAcc<AR, 1> acc;
-  acc.init(A);
-  if (active) {
-    uint32_t kb = A.rowp[T.aux + r] - T.e0, ke = A.rowp[T.aux + r + 1] - T.e0;
-    for (uint32_t k = kb + sub; k < ke; k += lpr) {
-      acc.a[0] += prod[k];
+  // entry-balanced segmented sum
+  const uint32_t per = (ne + TILE_THREADS - 1) / TILE_THREADS;
+  const uint32_t p0 = tid * per, p1 = min(ne, p0 + per);
+  if (p0 < p1) {
+    uint32_t lo = 0, hi = nr;  // last row r with rps[r] <= p0
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (rps[mid] <= p0) lo = mid;
+      else hi = mid;
+    }
+    uint32_t r = lo, next = rps[r + 1];
+    LaneAcc<AR, 1> acc;
+    acc.init(A);
+    for (uint32_t p = p0; p < p1; ++p) {
+      while (p >= next) {
+        acc.to_residues(A);
+        atomicAdd(&rowsum[r], acc.a[0]);
+        acc.init(A);
+        next = rps[++r + 1];
+      }
+      acc.a[0] += prod[p];
       acc.tick(A);
     }
-    band_terms<AR, Tv, 1>(A, T, acc, T.row0 + r, r, nr, sub, lpr, X, ldx, 1);
-  }
-  Acc v = acc.a[0];
-  if (lpr > 1) {
     acc.to_residues(A);
-    v = acc.a[0];
-    for (uint32_t o = lpr / 2; o > 0; o >>= 1) v += shfl_xor_acc(v, (int)o, (int)lpr);
+    atomicAdd(&rowsum[r], acc.a[0]);
   }
-  if (active && sub == 0) {
-    uint32_t res = AR::reduce(v, A);
-    write_row<Tv, 1>(A, Y, ldy, T.row0 + r, &res, 1, alpha, beta);
+  __syncthreads();
+  if (tid < nr) {
+    uint32_t res = AR::reduce(rowsum[tid], A);
+    write_row<Tv, 1>(A, Y, ldy, T.row0 + tid, &res, 1, alpha, beta);
   }
 }
 
 // s > 1 vectors: stage words and values in LDS, one lane per row
-template <class AR, typename Tv, int S>
-__device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tv* __restrict__ X, int64_t ldx,
+template <class AR, typename Tx, typename Tv, int S>
+__device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                      Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta,
                                      unsigned char* lds) {
+  constexpr uint32_t NW = TILE_THREADS / WAVE;
+  constexpr int U = 4;
   uint32_t* sw = (uint32_t*)lds;
   uint32_t* sv = sw + T.ne;
   const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
   const uint32_t nchunks = (T.ne + WAVE - 1) / WAVE;
-  for (uint32_t ch = wave; ch < nchunks; ch += TILE_THREADS / WAVE) {
-    uint32_t k = ch * WAVE + lane;
-    bool in = k < T.ne;
-    uint32_t w = in ? A.ent[T.e0 + k] : PAD_WORD;
-    uint32_t tag = w >> TAG_SHIFT;
-    uint64_t gm = __ballot(tag == TAG_GEN);
-    uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, A.choff[T.c0 + ch] + lanes_below(gm)) : 0u;
-    if (in) {
-      sw[k] = w;
-      sv[k] = v;
+  const uint32_t nr = tile_rows(T.kind);
+  uint32_t kb = 0, ke = 0;
+  if (tid < nr) {
+    kb = A.rowp[T.aux + tid] - T.e0;
+    ke = A.rowp[T.aux + tid + 1] - T.e0;
+  }
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    uint32_t w[U], vo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
+      w[u] = (ch < nchunks && k < T.ne) ? __builtin_nontemporal_load(A.ent + T.e0 + k) : PAD_WORD;
+      vo[u] = ch < nchunks ? A.choff[T.c0 + ch] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
+      uint32_t tag = w[u] >> TAG_SHIFT;
+      uint64_t gm = __ballot(tag == TAG_GEN);
+      uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, vo[u] + lanes_below(gm)) : 0u;
+      if (ch < nchunks && k < T.ne) {
+        sw[k] = w[u];
+        sv[k] = v;
+      }
     }
   }
   __syncthreads();
-  const uint32_t nr = tile_rows(T.kind);
   if (tid >= nr) return;
   const uint32_t row = T.row0 + tid;
   LaneAcc<AR, S> acc;
   acc.init(A);
-  uint32_t kb = A.rowp[T.aux + tid] - T.e0, ke = A.rowp[T.aux + tid + 1] - T.e0;
+  band_terms<AR, Tx, S>(A, T, acc, row, tid, nr, 0, 1, X, ldx, s);
   for (uint32_t k = kb; k < ke; ++k) {
     uint32_t w = sw[k], tag = w >> TAG_SHIFT, v = sv[k];
-    const Tv* xr = X + (int64_t)(w & COL_MASK) * ldx;
+    const Tx* xr = X + (int64_t)(w & COL_MASK) * ldx;
 #pragma unroll
     for (int c = 0; c < S; ++c)
       if (c < s) acc.a[c] += term<AR>(tag, v, (uint32_t)xr[c], A.m);
     acc.tick(A);
   }
-  band_terms<AR, Tv, S>(A, T, acc, row, tid, nr, 0, 1, X, ldx, s);
   uint32_t r[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) r[c] = AR::reduce(acc.a[c], A);
@@ -330,46 +435,89 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tv* _
 }
 
 // ------------------------------- the launch --------------------------------
-template <class AR, typename Tv, int S>
-__global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tv* __restrict__ X, int64_t ldx,
+template <class AR, typename Tx, typename Tv, int S, int U>
+__global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __restrict__ X, int64_t ldx,
                                                         Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha,
                                                         uint32_t beta) {
   extern __shared__ __align__(16) unsigned char lds[];
   const Tile T = A.tiles[blockIdx.x];
   switch (tile_kind(T.kind)) {
-    case TK_SELL: sell_tile<AR, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta); break;
-    case TK_LONG: long_tile<AR, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
+    case TK_SELL: sell_tile<AR, Tx, Tv, S, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta); break;
+    case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 4)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
     default:
-      if (S == 1) stream_tile_1<AR, Tv>(A, T, X, ldx, Y, ldy, alpha, beta, lds);
-      else stream_tile_s<AR, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
+      if constexpr (S == 1) stream_tile_1<AR, Tx, Tv, U>(A, T, X, ldx, Y, ldy, alpha, beta, lds);
+      else stream_tile_s<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
   }
+}
+
+template <typename Tv>
+__global__ void k_to_u16(const Tv* __restrict__ x, int64_t ldx, uint16_t* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint16_t)x[i * ldx];
 }
 
 // Dynamic LDS of one launch.
 template <class AR>
 inline size_t tiles_lds_bytes(int64_t max_tile_entries, int S) {
-  size_t stream = (size_t)max_tile_entries * (S == 1 ? sizeof(typename AR::Prod) : 8);
+  size_t stream = S == 1 ? TILE_THREADS * sizeof(typename AR::Acc) + (TILE_THREADS + 4) * 4 +
+                               (size_t)max_tile_entries * sizeof(typename AR::Prod)
+                         : (size_t)max_tile_entries * 8;
   size_t red = (size_t)(TILE_THREADS / WAVE) * S * sizeof(typename AR::Acc);
   size_t b = stream > red ? stream : red;
   return b < 16 ? 16 : b;
 }
 
+// Unroll of the one-vector STREAM/LONG paths: every chunk of a tile in one batch.
+inline int unroll_for(int64_t max_tile_entries) {
+  int64_t per_wave = (max_tile_entries + TILE_THREADS - 1) / TILE_THREADS;
+  return per_wave <= 4 ? 4 : per_wave <= 8 ? 8 : 16;
+}
+
+template <class AR, typename Tx, typename Tv, int U>
+static void launch_s1(const DevMat& A, size_t lds, const Tx* x, int64_t ldx, Tv* y, int64_t ldy, uint32_t alpha,
+                      uint32_t beta, hipStream_t st) {
+  hipLaunchKernelGGL((k_tiles<AR, Tx, Tv, 1, U>), dim3(A.ntiles), dim3(TILE_THREADS), lds, st, A, x, ldx, y, ldy, 1,
+                     alpha, beta);
+}
+
+// x16: when not null, a 16-bit copy of the one vector (s must be 1)
 template <class AR, typename Tv>
 hipError_t launch_tiles_t(const DevMat& A, int64_t max_tile_entries, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                          int s, uint32_t alpha, uint32_t beta, hipStream_t st) {
+                          int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16) {
   if (A.ntiles == 0) return hipSuccess;
   const int S = s <= 1 ? 1 : s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;
   size_t lds = tiles_lds_bytes<AR>(max_tile_entries, S);
   dim3 grid(A.ntiles), block(TILE_THREADS);
   const Tv* x = (const Tv*)X;
   Tv* y = (Tv*)Y;
-  switch (S) {
-    case 1: hipLaunchKernelGGL((k_tiles<AR, Tv, 1>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
-    case 2: hipLaunchKernelGGL((k_tiles<AR, Tv, 2>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
-    case 4: hipLaunchKernelGGL((k_tiles<AR, Tv, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
-    case 8: hipLaunchKernelGGL((k_tiles<AR, Tv, 8>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
-    default: hipLaunchKernelGGL((k_tiles<AR, Tv, 16>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+  if (S == 1) {
+    const int U = unroll_for(max_tile_entries);
+    if (x16) {
+      if (U == 4) launch_s1<AR, uint16_t, Tv, 4>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      else if (U == 8) launch_s1<AR, uint16_t, Tv, 8>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      else launch_s1<AR, uint16_t, Tv, 16>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+    } else {
+      if (U == 4) launch_s1<AR, Tv, Tv, 4>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      else if (U == 8) launch_s1<AR, Tv, Tv, 8>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      else launch_s1<AR, Tv, Tv, 16>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+    }
+    return hipGetLastError();
   }
+  switch (S) {
+    case 2: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 2, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+    case 4: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 4, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+    case 8: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 8, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+    default: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 16, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+  }
+  return hipGetLastError();
+}
+
+// 16-bit copy of one vector (residues < 65536), for the compact-x path.
+template <typename Tv>
+hipError_t launch_to_u16(const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_to_u16<Tv>), dim3(blocks), dim3(256), 0, st, (const Tv*)X, ldx, out, n);
   return hipGetLastError();
 }
 

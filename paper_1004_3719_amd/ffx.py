@@ -34,7 +34,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("acc", ctypes.c_int32), ("selector", ctypes.c_int32),
                 ("fixed_format", ctypes.c_int32), ("split_pm1", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("build_transpose", ctypes.c_int32), ("tile_entries", ctypes.c_int32),
-                ("model_path", ctypes.c_char_p)]
+                ("compact_x", ctypes.c_int32), ("model_path", ctypes.c_char_p)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -134,7 +134,7 @@ def _block(t, rows, name):
 
 
 def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=True, block_rows=4096,
-               build_transpose=False, tile_entries=0, model_path=None):
+               build_transpose=False, tile_entries=0, compact_x=-1, model_path=None):
     o = BuildOpts()
     lib().ffx_build_opts_default(ctypes.byref(o))
     o.acc = ACC[acc]
@@ -146,6 +146,7 @@ def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=Tr
     o.block_rows = int(block_rows)
     o.build_transpose = int(bool(build_transpose))
     o.tile_entries = int(tile_entries)
+    o.compact_x = int(compact_x)
     o.model_path = model_path.encode() if model_path else None
     return o
 

@@ -277,8 +277,19 @@ def test_determinism(dev, ffx):
     ref = M.spmv(x).cpu().numpy()
     reft = M.spmv_t(x).cpu().numpy()
     for _ in range(10):
-        assert np.array_equal(M.spmv(x).cpu().numpy(), ref)
-        assert np.array_equal(M.spmv_t(x).cpu().numpy(), reft)
+        got = M.spmv(x).cpu().numpy()
+        assert np.array_equal(got, ref), np.nonzero(got != ref)[0][:20]
+        gott = M.spmv_t(x).cpu().numpy()
+        assert np.array_equal(gott, reft), np.nonzero(gott != reft)[0][:20]
+    # tiles of exactly 256 one-entry rows (the row cap of a STREAM tile)
+    B = synth.rows(synth.spec(300_000, 300_000, 5, len_kind=synth.LEN_FIXED, len_a=1, col_kind=synth.COL_UNIFORM,
+                              p_pm1=0.5, val_lo=1, val_hi=100))
+    B.m = A.m
+    MB = ffx.from_synth(B, fixed_format="STREAM")
+    xb = vec(12, 2, B.ncols, B.m)
+    want = oracle.get().spmv(B, xb)
+    for _ in range(10):
+        assert np.array_equal(MB.spmv(tdev(xb, dev)).cpu().numpy(), want)
 
 
 def test_c2_full_size_sampled(dev, orc, ffx):
@@ -298,3 +309,22 @@ def test_c2_full_size_sampled(dev, orc, ffx):
         assert np.array_equal(got[rows], want), acc
         assert got.min() >= 0 and got.max() < A.m
         M.close()
+
+
+@pytest.mark.parametrize("compact", [0, 1])
+@pytest.mark.parametrize("acc", ["int64", "fp64"])
+@pytest.mark.parametrize("tile_entries", [1024, 2048, 4096])
+def test_compact_x_and_unroll(dev, orc, ffx, compact, acc, tile_entries):
+    """Gathering x from a 16-bit copy, and the 4/8/16-chunk load batches, change nothing."""
+    A = synth.c2(n=60_000)
+    note("compact_x", compact, acc, tile_entries)
+    M = ffx.from_synth(A, compact_x=compact, acc=acc, tile_entries=tile_entries, build_transpose=True)
+    x = vec(14, 1, A.ncols, A.m)
+    y0 = vec(14, 2, A.nrows, A.m)
+    for dt in (torch.int32, torch.int64):
+        assert np.array_equal(M.spmv(tdev(x, dev, dt)).cpu().numpy(), orc.spmv(A, x))
+        y = tdev(y0, dev, dt)
+        M.spmv(tdev(x, dev, dt), alpha=17, beta=19, y=y)
+        assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, 17, 19, y0))
+    xt = vec(14, 3, A.nrows, A.m)
+    assert np.array_equal(M.spmv_t(tdev(xt, dev)).cpu().numpy(), orc.spmv_t(A, xt))
