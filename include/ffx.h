@@ -89,7 +89,7 @@ typedef struct {
   int32_t split_pm1;        /* 1 (default): +-1 stored without values; 0: every entry has a value */
   int32_t block_rows;       /* rows per format block, a multiple of 64 in [64, 65536]; default 4096 */
   int32_t build_transpose;  /* 1: also encode A^T so ffx_spmv_t/ffx_spmm_t run as row products */
-  int32_t tile_entries;     /* entries per STREAM tile, 256..4096, 0 = default (autotuned or 1024) */
+  int32_t tile_entries;     /* entries per STREAM tile, 256..4096, 0 = default (2048) */
   int32_t compact_x;        /* m <= 65536, one vector: gather x from a 16-bit copy made per product
                                (-1 = when x exceeds 1 MiB, 0 = never, 1 = always); never changes a result */
   const char* model_path;   /* learned selector weights; NULL = none */

@@ -73,7 +73,7 @@ static PlanOpts plan_opts(const ffx_build_opts* o) {
   if (d.block_rows < 64 || d.block_rows > 65536 || d.block_rows % 64)
     fail(FFX_EINVAL, "block_rows %d is not a multiple of 64 in [64, 65536]", d.block_rows);
   p.block_rows = d.block_rows;
-  int te = d.tile_entries ? d.tile_entries : 1024;
+  int te = d.tile_entries ? d.tile_entries : 2048;
   if (te < 256 || te > 4096) fail(FFX_EINVAL, "tile_entries %d outside [256, 4096]", te);
   p.tile_entries = te;
   if (d.compact_x < -1 || d.compact_x > 1) fail(FFX_EINVAL, "compact_x %d not in {-1, 0, 1}", d.compact_x);

@@ -37,6 +37,11 @@ constexpr uint32_t TF_SORTED = 1u << 4;  // SELL slots map to rows through perm[
 
 constexpr int TILE_THREADS = 256;
 constexpr int WAVE = 64;
+// STREAM and LONG tiles are read 4 consecutive entry words (16 bytes) per
+// lane: their entries start 16-byte aligned, are padded to a multiple of 4,
+// and their value chunks cover 256 entries. SELL chunks cover 64 entries.
+constexpr int WIDE = 4;
+constexpr int WCHUNK = WAVE * WIDE;
 constexpr int SELL_SLICES = TILE_THREADS / WAVE;  // 4
 constexpr int MAX_BAND = 64;                      // diagonals per band part
 constexpr int MAX_S = 16;

@@ -170,7 +170,11 @@ struct HostEnc {
   int64_t max_tile_entries = 0;
   int64_t n_plus = 0, n_minus = 0, n_band = 0, nnz = 0, max_row_terms = 0;
 
-  // appends up to 64 words as one value chunk
+  // pads the entry stream to a 16-byte boundary with padding words
+  void align_ent() {
+    while (ent.size() % WIDE) ent.push_back(PAD_WORD);
+  }
+  // appends n words (64 for SELL, up to 256 for STREAM/LONG) as one value chunk
   void push_chunk(const uint32_t* w, const uint32_t* v, int n) {
     choff.push_back((uint32_t)val.size());
     for (int i = 0; i < n; ++i) {
@@ -232,14 +236,16 @@ void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, in
       Tile T{};
       T.kind = TK_LONG | ((uint32_t)R.nd << 8) | (1u << 16);
       T.row0 = (uint32_t)(r0 + t);
+      H.align_ent();
       T.e0 = (uint32_t)H.ent.size();
       T.ne = (uint32_t)rlen(t);
       T.c0 = (uint32_t)H.choff.size();
       T.boff = boff;
-      for (int64_t k = R.rp[t]; k < R.rp[t + 1]; k += WAVE) {
-        int n = (int)std::min<int64_t>(WAVE, R.rp[t + 1] - k);
+      for (int64_t k = R.rp[t]; k < R.rp[t + 1]; k += WCHUNK) {
+        int n = (int)std::min<int64_t>(WCHUNK, R.rp[t + 1] - k);
         H.push_chunk(&R.word[k], &R.v[k], n);
       }
+      H.align_ent();
       push_band(t, 1, T);
       H.tiles.push_back(T);
       ++t;
@@ -251,16 +257,18 @@ void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, in
     int64_t rows = t - t0;
     T.kind = TK_STREAM | ((uint32_t)R.nd << 8) | ((uint32_t)rows << 16);
     T.row0 = (uint32_t)(r0 + t0);
+    H.align_ent();
     T.e0 = (uint32_t)H.ent.size();
     T.ne = (uint32_t)ne;
     T.c0 = (uint32_t)H.choff.size();
     T.aux = (uint32_t)H.rowp.size();
     T.boff = boff;
     for (int64_t q = t0; q <= t; ++q) H.rowp.push_back((uint32_t)(T.e0 + (R.rp[q] - R.rp[t0])));
-    for (int64_t k = R.rp[t0]; k < R.rp[t]; k += WAVE) {
-      int n = (int)std::min<int64_t>(WAVE, R.rp[t] - k);
+    for (int64_t k = R.rp[t0]; k < R.rp[t]; k += WCHUNK) {
+      int n = (int)std::min<int64_t>(WCHUNK, R.rp[t] - k);
       H.push_chunk(&R.word[k], &R.v[k], n);
     }
+    H.align_ent();
     push_band(t0, rows, T);
     H.max_tile_entries = std::max<int64_t>(H.max_tile_entries, ne);
     H.tiles.push_back(T);

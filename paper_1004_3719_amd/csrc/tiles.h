@@ -180,18 +180,22 @@ __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>
 template <class AR, typename Tx, int S, int U>
 struct ChunkBatch {
   uint32_t w[U];
+  uint32_t vo[U];
   uint32_t v[U];
   uint32_t xv[U][S];
-  // word_at(u): this lane's entry word pointer in chunk u, or null; choff_at(u): the chunk's value offset
+  // step 1: the entry words. word_at(u): this lane's word pointer in chunk u, or null;
+  // choff_at(u): the chunk's value offset
   template <class WordAt, class ChOff>
-  __device__ inline void load(const DevMat& A, const Tx* X, int64_t ldx, int s, WordAt word_at, ChOff choff_at) {
-    uint32_t vo[U];
+  __device__ inline void load_words(WordAt word_at, ChOff choff_at) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t* p = word_at(u);
       w[u] = p ? __builtin_nontemporal_load(p) : PAD_WORD;
       vo[u] = choff_at(u);
     }
+  }
+  // step 2: values and gathered x (needs the words)
+  __device__ inline void load_gathers(const DevMat& A, const Tx* X, int64_t ldx, int s) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       uint32_t tag = w[u] >> TAG_SHIFT;
@@ -216,6 +220,67 @@ struct ChunkBatch {
   }
 };
 
+// U chunks of 256 entries read 4 words (16 bytes) per lane, for STREAM and
+// LONG tiles. Entry (lane, k) of a chunk is word 4*lane + k; values follow the
+// entry order, so the value index of a general entry is the chunk offset plus
+// the general entries of lower lanes (four ballots) plus those before it in
+// the lane.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class AR, typename Tx, int S, int U>
+struct Chunk4 {
+  uint32_t w[U][WIDE];
+  uint32_t vo[U];
+  uint32_t v[U][WIDE];
+  uint32_t xv[U][WIDE][S];
+  // step 1: at(u): this lane's 16-byte word group in chunk u, or null
+  template <class At, class ChOff>
+  __device__ inline void load_words(At at, ChOff choff_at) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u32x4* p = at(u);
+      u32x4 q = p ? __builtin_nontemporal_load(p) : (u32x4)(PAD_WORD);
+      w[u][0] = q.x;
+      w[u][1] = q.y;
+      w[u][2] = q.z;
+      w[u][3] = q.w;
+      vo[u] = choff_at(u);
+    }
+  }
+  // step 2: values and gathered x
+  __device__ inline void load_gathers(const DevMat& A, const Tx* X, int64_t ldx, int s) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t idx = vo[u];
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) idx += lanes_below(__ballot((w[u][k] >> TAG_SHIFT) == TAG_GEN));
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        uint32_t tag = w[u][k] >> TAG_SHIFT;
+        bool gen = tag == TAG_GEN;
+        v[u][k] = gen ? ldval<typename AR::ValT>(A.val, idx) : 0u;
+        idx += gen ? 1u : 0u;
+        const Tx* xr = X + (int64_t)(w[u][k] & COL_MASK) * ldx;
+#pragma unroll
+        for (int c = 0; c < S; ++c) xv[u][k][c] = (tag != TAG_PAD && c < s) ? (uint32_t)xr[c] : 0u;
+      }
+    }
+  }
+  __device__ inline void accumulate(const DevMat& A, LaneAcc<AR, S>& acc, int s) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        uint32_t tag = w[u][k] >> TAG_SHIFT;
+        if (tag != TAG_PAD) {
+#pragma unroll
+          for (int c = 0; c < S; ++c)
+            if (c < s) acc.a[c] += term<AR>(tag, v[u][k], xv[u][k][c], A.m);
+          acc.tick(A);
+        }
+      }
+  }
+};
+
 // ------------------------------- SELL tile ---------------------------------
 template <class AR, typename Tx, typename Tv, int S, int U>
 __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
@@ -236,10 +301,9 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
   if (valid) band_terms<AR, Tx, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
   for (uint32_t j0 = 0; j0 < width; j0 += U) {
     ChunkBatch<AR, Tx, S, U> b;
-    b.load(
-        A, X, ldx, s,
-        [&](int u) -> const uint32_t* { return j0 + u < width ? ent + (size_t)(j0 + u) * WAVE : nullptr; },
-        [&](int u) -> uint32_t { return j0 + u < width ? choff[j0 + u] : 0u; });
+    b.load_words([&](int u) -> const uint32_t* { return j0 + u < width ? ent + (size_t)(j0 + u) * WAVE : nullptr; },
+                 [&](int u) -> uint32_t { return j0 + u < width ? choff[j0 + u] : 0u; });
+    b.load_gathers(A, X, ldx, s);
     b.accumulate(A, acc, s);
   }
   if (!valid) return;
@@ -257,22 +321,25 @@ __device__ inline void long_tile(const DevMat& A, const Tile& T, const Tx* __res
   using Acc = typename AR::Acc;
   constexpr uint32_t NW = TILE_THREADS / WAVE;
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-  const uint32_t nchunks = (T.ne + WAVE - 1) / WAVE;
+  const uint32_t nchunks = (T.ne + WCHUNK - 1) / WCHUNK;
   LaneAcc<AR, S> acc;
   acc.init(A);
   band_terms<AR, Tx, S>(A, T, acc, T.row0, 0, 1, threadIdx.x, TILE_THREADS, X, ldx, s);
-  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
-    ChunkBatch<AR, Tx, S, U> b;
-    b.load(
-        A, X, ldx, s,
-        [&](int u) -> const uint32_t* {
-          uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
-          return (ch < nchunks && k < T.ne) ? A.ent + T.e0 + k : nullptr;
+  auto words = [&](Chunk4<AR, Tx, S, U>& b, uint32_t ch0) {
+    b.load_words(
+        [&](int u) -> const u32x4* {
+          uint32_t ch = ch0 + u * NW, k = ch * WCHUNK + lane * WIDE;
+          return (ch < nchunks && k < T.ne) ? (const u32x4*)(A.ent + T.e0 + k) : nullptr;
         },
         [&](int u) -> uint32_t {
           uint32_t ch = ch0 + u * NW;
           return ch < nchunks ? A.choff[T.c0 + ch] : 0u;
         });
+  };
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    Chunk4<AR, Tx, S, U> b;
+    words(b, ch0);
+    b.load_gathers(A, X, ldx, s);
     b.accumulate(A, acc, s);
   }
   acc.to_residues(A);
@@ -314,7 +381,7 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
   Prod* prod = (Prod*)(rps + TILE_THREADS + 4);            // [ne]
   const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
   const uint32_t ne = T.ne;
-  const uint32_t nchunks = (ne + WAVE - 1) / WAVE;
+  const uint32_t nchunks = (ne + WCHUNK - 1) / WCHUNK;
   const uint32_t nr = tile_rows(T.kind);
   if (tid < nr) rps[tid] = A.rowp[T.aux + tid] - T.e0;
   if (tid == 0) rps[nr] = ne;  // nr may be 256: the sentinel needs its own writer
@@ -325,23 +392,28 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
     band.to_residues(A);
     rowsum[tid] = band.a[0];
   }
-  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
-    ChunkBatch<AR, Tx, 1, U> b;
-    b.load(
-        A, X, ldx, 1,
-        [&](int u) -> const uint32_t* {
-          uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
-          return (ch < nchunks && k < ne) ? A.ent + T.e0 + k : nullptr;
+  auto words = [&](Chunk4<AR, Tx, 1, U>& b, uint32_t ch0) {
+    b.load_words(
+        [&](int u) -> const u32x4* {
+          uint32_t ch = ch0 + u * NW, k = ch * WCHUNK + lane * WIDE;
+          return (ch < nchunks && k < ne) ? (const u32x4*)(A.ent + T.e0 + k) : nullptr;
         },
         [&](int u) -> uint32_t {
           uint32_t ch = ch0 + u * NW;
           return ch < nchunks ? A.choff[T.c0 + ch] : 0u;
         });
+  };
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    Chunk4<AR, Tx, 1, U> b;
+    words(b, ch0);
+    b.load_gathers(A, X, ldx, 1);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
-      if (ch < nchunks && k < ne) prod[k] = term<AR>(b.w[u] >> TAG_SHIFT, b.v[u], b.xv[u][0], A.m);
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        uint32_t e = (ch0 + u * NW) * WCHUNK + lane * WIDE + k;
+        if (e < ne) prod[e] = term<AR>(b.w[u][k] >> TAG_SHIFT, b.v[u][k], b.xv[u][k][0], A.m);
+      }
   }
   __syncthreads();
   // entry-balanced segmented sum
@@ -383,11 +455,11 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* _
                                      Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta,
                                      unsigned char* lds) {
   constexpr uint32_t NW = TILE_THREADS / WAVE;
-  constexpr int U = 4;
+  constexpr int U = 2;
   uint32_t* sw = (uint32_t*)lds;
   uint32_t* sv = sw + T.ne;
   const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-  const uint32_t nchunks = (T.ne + WAVE - 1) / WAVE;
+  const uint32_t nchunks = (T.ne + WCHUNK - 1) / WCHUNK;
   const uint32_t nr = tile_rows(T.kind);
   uint32_t kb = 0, ke = 0;
   if (tid < nr) {
@@ -395,22 +467,33 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* _
     ke = A.rowp[T.aux + tid + 1] - T.e0;
   }
   for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
-    uint32_t w[U], vo[U];
+    uint32_t w[U][WIDE], vo[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
-      w[u] = (ch < nchunks && k < T.ne) ? __builtin_nontemporal_load(A.ent + T.e0 + k) : PAD_WORD;
+      uint32_t ch = ch0 + u * NW, k = ch * WCHUNK + lane * WIDE;
+      u32x4 q = (ch < nchunks && k < T.ne) ? __builtin_nontemporal_load((const u32x4*)(A.ent + T.e0 + k))
+                                           : (u32x4)(PAD_WORD);
+      w[u][0] = q.x;
+      w[u][1] = q.y;
+      w[u][2] = q.z;
+      w[u][3] = q.w;
       vo[u] = ch < nchunks ? A.choff[T.c0 + ch] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t ch = ch0 + u * NW, k = ch * WAVE + lane;
-      uint32_t tag = w[u] >> TAG_SHIFT;
-      uint64_t gm = __ballot(tag == TAG_GEN);
-      uint32_t v = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, vo[u] + lanes_below(gm)) : 0u;
-      if (ch < nchunks && k < T.ne) {
-        sw[k] = w[u];
-        sv[k] = v;
+      uint32_t idx = vo[u];
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) idx += lanes_below(__ballot((w[u][k] >> TAG_SHIFT) == TAG_GEN));
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        bool gen = (w[u][k] >> TAG_SHIFT) == TAG_GEN;
+        uint32_t v = gen ? ldval<typename AR::ValT>(A.val, idx) : 0u;
+        idx += gen ? 1u : 0u;
+        uint32_t e = (ch0 + u * NW) * WCHUNK + lane * WIDE + k;
+        if (e < T.ne) {
+          sw[e] = w[u][k];
+          sv[e] = v;
+        }
       }
     }
   }
@@ -443,7 +526,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
   const Tile T = A.tiles[blockIdx.x];
   switch (tile_kind(T.kind)) {
     case TK_SELL: sell_tile<AR, Tx, Tv, S, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta); break;
-    case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 4)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
+    case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 1)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
     default:
       if constexpr (S == 1) stream_tile_1<AR, Tx, Tv, U>(A, T, X, ldx, Y, ldy, alpha, beta, lds);
       else stream_tile_s<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
@@ -469,8 +552,8 @@ inline size_t tiles_lds_bytes(int64_t max_tile_entries, int S) {
 
 // Unroll of the one-vector STREAM/LONG paths: every chunk of a tile in one batch.
 inline int unroll_for(int64_t max_tile_entries) {
-  int64_t per_wave = (max_tile_entries + TILE_THREADS - 1) / TILE_THREADS;
-  return per_wave <= 4 ? 4 : per_wave <= 8 ? 8 : 16;
+  int64_t per_wave = (max_tile_entries + (int64_t)WCHUNK * (TILE_THREADS / WAVE) - 1) / ((int64_t)WCHUNK * (TILE_THREADS / WAVE));
+  return per_wave <= 1 ? 1 : per_wave <= 2 ? 2 : 4;
 }
 
 template <class AR, typename Tx, typename Tv, int U>
@@ -493,13 +576,13 @@ hipError_t launch_tiles_t(const DevMat& A, int64_t max_tile_entries, const void*
   if (S == 1) {
     const int U = unroll_for(max_tile_entries);
     if (x16) {
-      if (U == 4) launch_s1<AR, uint16_t, Tv, 4>(A, lds, x16, 1, y, ldy, alpha, beta, st);
-      else if (U == 8) launch_s1<AR, uint16_t, Tv, 8>(A, lds, x16, 1, y, ldy, alpha, beta, st);
-      else launch_s1<AR, uint16_t, Tv, 16>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      if (U == 1) launch_s1<AR, uint16_t, Tv, 1>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      else if (U == 2) launch_s1<AR, uint16_t, Tv, 2>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      else launch_s1<AR, uint16_t, Tv, 4>(A, lds, x16, 1, y, ldy, alpha, beta, st);
     } else {
-      if (U == 4) launch_s1<AR, Tv, Tv, 4>(A, lds, x, ldx, y, ldy, alpha, beta, st);
-      else if (U == 8) launch_s1<AR, Tv, Tv, 8>(A, lds, x, ldx, y, ldy, alpha, beta, st);
-      else launch_s1<AR, Tv, Tv, 16>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      if (U == 1) launch_s1<AR, Tv, Tv, 1>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      else if (U == 2) launch_s1<AR, Tv, Tv, 2>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      else launch_s1<AR, Tv, Tv, 4>(A, lds, x, ldx, y, ldy, alpha, beta, st);
     }
     return hipGetLastError();
   }
