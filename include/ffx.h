@@ -178,6 +178,48 @@ ffx_status ffx_power(ffx_matrix A, int64_t k, int32_t s, const void* V, int64_t 
 ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
                         void* S, void* Wlast, ffx_dtype dtype, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched products: Y_k <- A_k X_k (mod m) for many matrices of uneven size,
+ * each with its own number s_k of right-hand sides, in one persistent launch.
+ * It generalises the paper's treatment of submatrices in parallel
+ * (Section 2.4, "New formats": split A into submatrices treated in parallel)
+ * to independent matrices; the launch parameters come from a tuner that
+ * times candidates on the batch itself, as the paper suggests tuning the
+ * format parameters for the machine (Section 2.4, "Heuristic format chooser").
+ * ------------------------------------------------------------------------ */
+typedef struct ffx_batch_s* ffx_batch;
+
+typedef struct {
+  int32_t wg_per_cu;   /* persistent workgroups per compute unit (1..8); 0 = tuned or default 4 */
+  int32_t order;       /* 0: work items by decreasing estimated cost, 1: matrix order */
+  int32_t max_chunk;   /* right-hand sides per work item: 4 or 8 (wider blocks are split) */
+  int32_t use_graph;   /* 1: replay a captured hipGraph of the launch */
+} ffx_batch_params;
+
+/* Group `count` matrices (all with the same modulus and accumulator) with
+ * s[k] in [1, 16] right-hand sides each. The handles stay owned by the
+ * caller and must outlive the batch. The batch copies their descriptors and
+ * builds its work list on the device. params may be NULL (defaults). */
+ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t* s, const ffx_batch_params* params,
+                            void* stream, ffx_batch* out);
+
+/* Y_k <- A_k X_k for all k, one launch. X and Y are HOST arrays of `count`
+ * DEVICE pointers; ldx[k] >= s[k], ldy[k] >= s[k] (host arrays). X_k has
+ * ncols_k rows, Y_k nrows_k rows, all of element type dtype. */
+ffx_status ffx_batch_spmm(ffx_batch B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
+                          ffx_dtype dtype, void* stream);
+
+/* Times each candidate launch configuration `reps` times on the given
+ * operands, keeps the fastest in the batch and writes it to *best (may be
+ * NULL). When cache_path is not NULL the choice is also stored there (JSON,
+ * keyed by device name and batch signature) and read back by later calls. */
+ffx_status ffx_batch_tune(ffx_batch B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
+                          ffx_dtype dtype, int32_t reps, const char* cache_path, void* stream, ffx_batch_params* best);
+
+ffx_status ffx_batch_get_params(ffx_batch B, ffx_batch_params* params);
+ffx_status ffx_batch_set_params(ffx_batch B, const ffx_batch_params* params);
+ffx_status ffx_batch_destroy(ffx_batch B);
+
 /* Status name and the calling thread's last error message. */
 const char* ffx_status_str(ffx_status st);
 const char* ffx_last_error(void);

@@ -52,6 +52,9 @@ static int arith_kind(const ffx_matrix_s& M) {
   return M.chunk ? AK_BIG_CH : AK_BIG;
 }
 
+int matrix_arith_kind(const ffx_matrix_s& M) { return arith_kind(M); }
+const std::vector<uint32_t>& matrix_tile_cost(const ffx_matrix_s& M) { return M.A.tile_cost; }
+
 static PlanOpts plan_opts(const ffx_build_opts* o) {
   ffx_build_opts d;
   ffx_build_opts_default(&d);
@@ -374,36 +377,26 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
       check_disjoint("V", V, n, ldv, "S", S, L * s, s, s, dtype);
     }
     hipStream_t st = (hipStream_t)stream;
-    const int ak = arith_kind(*A);
+    if (n == 0) return;
+    if (L == 0) {
+      if (Wlast) FFX_HIP(launch_copy_block(dtype, V, ldv, Wlast, s, n, s, st));
+      return;
+    }
+    warm_pool(st);
     const Encoded& E = A->A;
-    size_t bytes = (size_t)std::max<int64_t>(n, 1) * s * esize(dtype);
-    void* w[2] = {nullptr, nullptr};
-    uint64_t* part = nullptr;
-    auto cleanup = [&] {
-      for (void* p : w) if (p) (void)hipFreeAsync(p, st);
-      if (part) (void)hipFreeAsync(part, st);
-    };
-    if (hipMallocAsync(&w[0], bytes, st) != hipSuccess || hipMallocAsync(&w[1], bytes, st) != hipSuccess ||
-        hipMallocAsync((void**)&part, (size_t)proj_partials() * s * s * sizeof(uint64_t), st) != hipSuccess) {
-      cleanup();
-      fail(FFX_ENOMEM, "sequence workspace allocation failed");
-    }
-    const void* cur = V;
-    int64_t ldc = ldv;
-    hipError_t e = hipSuccess;
-    for (int64_t i = 0; i < L && e == hipSuccess; ++i) {
-      e = launch_projection(A->md.small(), E.dm, dtype, U, ldu, cur, ldc, n, s, part,
-                            (char*)S + (size_t)i * s * s * esize(dtype), st);
-      if (e != hipSuccess) break;
-      bool need_next = i + 1 < L || Wlast;
-      if (!need_next) break;
-      void* dst = (i + 1 == L) ? Wlast : w[i & 1];
-      e = launch_tiles(ak, E.dm, E.max_tile_entries, dtype, cur, ldc, dst, s, s, 1, 0, st);
-      cur = dst;
-      ldc = s;
-    }
-    if (L == 0 && Wlast && e == hipSuccess) e = launch_copy_block(dtype, V, ldv, Wlast, s, n, s, st);
-    cleanup();
+    size_t wbytes = (size_t)n * s * esize(dtype);
+    size_t pbytes = ((size_t)std::max<int64_t>(E.ntiles, 1) * SELL_SLICES + 64) * s * s * sizeof(uint64_t);
+    void* ws[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[5] = {wbytes, wbytes, pbytes, pbytes, sizeof(int64_t)};
+    for (int q = 0; q < 5; ++q)
+      if (hipMallocAsync(&ws[q], sizes[q], st) != hipSuccess) {
+        for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
+        fail(FFX_ENOMEM, "sequence workspace allocation failed");
+      }
+    const int batch = L >= 128 ? 64 : 0;
+    hipError_t e = launch_sequence(A->md.small(), A->chunk, E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
+                                   Wlast, ws[0], ws[1], (uint64_t*)ws[2], (uint64_t*)ws[3], (int64_t*)ws[4], batch, st);
+    for (void* p : ws) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
   });
 }

@@ -77,6 +77,7 @@ struct Encoded {
   int64_t device_bytes = 0, stream_bytes = 0;
   int64_t max_tile_entries = 0;  // largest STREAM tile (sizes the LDS of a launch)
   std::vector<int32_t> block_fmt;
+  std::vector<uint32_t> tile_cost;  // per tile: entry words read (with padding) plus band slots
   int64_t format_blocks[FFX_NUM_FORMATS] = {0, 0, 0, 0, 0, 0};
   // sizes (elements) of each device array, for the batched concatenation
   int64_t n_ent = 0, n_val = 0, n_choff = 0, n_rowp = 0, n_perm = 0, n_swidth = 0, n_bval = 0, n_boffs = 0;

@@ -36,12 +36,13 @@ inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype d
 // 16-bit copy of one vector of n residues (stride ldx) for the compact-x path.
 hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st);
 
-// Projection S[a][b] = sum_k U[k][a] * W[k][b] mod m (n x s operands), as
-// per-workgroup partial sums followed by one combining launch. `partial`
-// holds at least proj_partials() * s * s uint64 values.
-int proj_partials();
-hipError_t launch_projection(bool small, const DevMat& A, ffx_dtype dt, const void* U, int64_t ldu, const void* W,
-                             int64_t ldw, int64_t n, int s, uint64_t* partial, void* S, hipStream_t st);
+// The sequence S_i = U^T A^i V, i < L (L >= 1), and A^L V into Wlast when not
+// null. Workspace: w0, w1 (n x s each), p0, p1 ((4 * ntiles + 64) * s * s uint64 each),
+// counter (one int64). Steps are replayed from a hipGraph in batches of
+// `batch` iterations (0: no graph).
+hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+                           int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
+                           void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st);
 
 // Strided copy of an n x s block (ld_in -> ld_out) of dtype elements.
 hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,

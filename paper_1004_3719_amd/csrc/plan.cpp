@@ -455,6 +455,17 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
                                 H.choff.size() * 4 + H.rowp.size() * 4 + H.perm.size() * 4 + H.swidth.size() * 4 +
                                 H.bval.size() * vb + H.boffs.size() * 4);
   out->max_tile_entries = H.max_tile_entries;
+  out->tile_cost.resize(H.tiles.size());
+  for (size_t t = 0; t < H.tiles.size(); ++t) {
+    const Tile& T = H.tiles[t];
+    uint64_t words = 0;
+    if (tile_kind(T.kind) == TK_SELL)
+      for (uint32_t k = 0; k < T.ne; ++k) words += (uint64_t)H.swidth[T.aux + k] * WAVE;
+    else
+      words = T.ne;
+    uint64_t rows = tile_kind(T.kind) == TK_LONG ? 1 : tile_rows(T.kind);
+    out->tile_cost[t] = (uint32_t)std::min<uint64_t>(UINT32_MAX, words + rows * tile_nd(T.kind) + rows);
+  }
   out->n_ent = (int64_t)H.ent.size();
   out->n_val = (int64_t)H.val.size();
   out->n_choff = (int64_t)H.choff.size();

@@ -1,79 +1,377 @@
-// Projection U^T W of the block-Wiedemann sequence (paper Section 3, step 1:
-// S_i = U^T A^i V) and a strided block copy.
+// Block-Wiedemann sequence S_i = U^T A^i V (paper Section 3, step 1; Section
+// 3.1) and the projection U^T W it is made of.
+//
+// One launch per iteration i covers the whole tile table. Workgroup g < ntiles
+// computes its tile's rows of W_{i+1} = A W_i (the same tile code as the
+// products) and then the s x s partial sum of U^T W_{i+1} over those rows.
+// Workgroup ntiles reduces the partials of iteration i, written by the
+// previous launch, into S_i. Partials are double-buffered by iteration parity,
+// so launch i reads one parity while writing the other. The launches of a
+// batch of iterations are captured into a hipGraph and replayed; the
+// iteration number comes from a device counter that the last node of the
+// graph advances, so the same graph serves every batch.
 #include "launch.h"
 #include "tiles.h"
 
 namespace ffx {
 
-constexpr int PROJ_WG = 512;
-int proj_partials() { return PROJ_WG; }
+// --------------------------------------------------------------- helpers ---
+// Row of index q (0 <= q < tile_rows) of a tile, or >= nrows for a padding slot.
+__device__ inline uint32_t tile_row(const DevMat& A, const Tile& T, uint32_t q) {
+  switch (tile_kind(T.kind)) {
+    case TK_SELL: return (T.kind & TF_SORTED) ? A.perm[T.row0 + q] : T.row0 + q;
+    default: return T.row0 + q;
+  }
+}
 
-// Each lane owns one column b of W and all s columns a of U for a strided set
-// of rows, and accumulates U[k][a]*W[k][b] with the same delayed reduction as
-// the products. Residues of the lanes meet in LDS; one partial per workgroup.
-template <class AR, typename Tv, int S>
-__global__ __launch_bounds__(256) void k_proj_partial(DevMat A, const Tv* __restrict__ U, int64_t ldu,
-                                                      const Tv* __restrict__ W, int64_t ldw, int64_t n, int s,
-                                                      uint64_t* __restrict__ partial) {
-  __shared__ uint64_t red[256 * S];
-  const int tid = threadIdx.x;
-  const int b = tid % S, rsub = tid / S, rpw = 256 / S;
-  LaneAcc<AR, S> acc;
+// Sum over the tile's rows of U[row][a] * W[row][b] for the s*s pairs (a, b),
+// into out[a*s + b] as residues (mod m) in uint64. Thread t takes pair
+// t % (s*s) and every (256/(s*s))-th row.
+template <class AR, typename Tv>
+__device__ inline void tile_projection(const DevMat& A, const Tile& T, const Tv* __restrict__ U, int64_t ldu,
+                                       const Tv* W, int64_t ldw, int s, uint64_t* red /* LDS [256] */,
+                                       uint64_t* __restrict__ out) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t ss = (uint32_t)(s * s);
+  const uint32_t pair = tid % ss, grp = tid / ss, ngrp = TILE_THREADS / ss;
+  const uint32_t a = pair / s, b = pair % s;
+  const uint32_t nq = tile_kind(T.kind) == TK_LONG ? 1u : tile_rows(T.kind);
+  LaneAcc<AR, 1> acc;
   acc.init(A);
-  if (b < s) {
-    for (int64_t k = (int64_t)blockIdx.x * rpw + rsub; k < n; k += (int64_t)gridDim.x * rpw) {
-      uint32_t w = (uint32_t)W[k * ldw + b];
-      const Tv* ur = U + k * ldu;
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-        if (a < s) acc.a[a] += AR::mul((uint32_t)ur[a], w);
+  if (grp < ngrp) {
+    for (uint32_t q = grp; q < nq; q += ngrp) {
+      uint32_t row = tile_row(A, T, q);
+      if (row >= A.nrows) continue;
+      acc.a[0] += AR::mul((uint32_t)U[(int64_t)row * ldu + a], (uint32_t)W[(int64_t)row * ldw + b]);
       acc.tick(A);
     }
   }
-#pragma unroll
-  for (int a = 0; a < S; ++a) red[(rsub * S + a) * S + b] = (b < s && a < s) ? AR::reduce(acc.a[a], A) : 0u;
+  red[tid] = (grp < ngrp) ? (uint64_t)AR::reduce(acc.a[0], A) : 0ull;
   __syncthreads();
-  if (tid < S * S) {
-    const int a = tid / S, bb = tid % S;
-    uint64_t t = 0;
-    for (int q = 0; q < rpw; ++q) t += red[(q * S + a) * S + bb];
-    if (a < s && bb < s) partial[(int64_t)blockIdx.x * s * s + a * s + bb] = t;
+  if (tid < ss) {
+    uint64_t t = 0;  // at most 256 residues: below 2^39
+    for (uint32_t q = 0; q < ngrp; ++q) t += red[q * ss + tid];
+    out[tid] = t;
   }
 }
 
+// out[pair] = sum of part[g][pair] over g = first, first + stride, ... < nparts,
+// reduced mod m when `reduce` (else left as a sum of residues). Each input is
+// below 2^40, and at most 2^20 inputs are added.
+__device__ inline uint64_t fold_partials(const DevMat& A, const uint64_t* __restrict__ part, uint32_t first,
+                                         uint32_t stride, uint32_t nparts, int s, uint64_t* red /* LDS [256] */,
+                                         uint32_t* pair_out) {
+  const uint32_t tid = threadIdx.x, ss = (uint32_t)(s * s);
+  const uint32_t pair = tid % ss, grp = tid / ss, ngrp = TILE_THREADS / ss;
+  uint64_t acc = 0;
+  if (grp < ngrp)
+    for (uint32_t g = first + grp * stride; g < nparts; g += ngrp * stride) acc += part[(int64_t)g * ss + pair];
+  red[tid] = grp < ngrp ? (uint64_t)mod_u64(acc, A.m, A.mu) : 0ull;
+  __syncthreads();
+  uint64_t t = 0;
+  if (tid < ss)
+    for (uint32_t q = 0; q < ngrp; ++q) t += red[q * ss + tid];
+  *pair_out = tid;
+  return t;
+}
+
+// One 64-row SELL slice by a whole workgroup, for s > 1: the slice's S passes
+// (RPW = 64/S rows each, lane = (row, component)) are split over the 4 waves,
+// so a launch has four times the waves of one-slice-per-wave. Every wave reads
+// the full slice column (entry words and values, lane = row) and keeps the
+// passes it owns. With PROJ the slice also adds U^T W_{i+1} over its rows: a
+// lane holds W_{i+1}[row][c] and U[row][c]; the U values of the row's other
+// components come by shuffle, so out[a*s + c] gets sum_row U[row][a] W[row][c].
+template <class AR, typename Tv, int S, bool PROJ>
+__device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t slice, const Tv* __restrict__ X,
+                                     int64_t ldx, Tv* __restrict__ Y, int64_t ldy, int s, const Tv* __restrict__ U,
+                                     int64_t ldu, uint64_t* __restrict__ out, uint64_t* red /* LDS [4][256] */) {
+  using Acc = typename AR::Acc;
+  constexpr int RPW = WAVE / S;
+  constexpr int NW = TILE_THREADS / WAVE;
+  constexpr int PPW = (S + NW - 1) / NW;  // passes per wave
+  constexpr int UC = 4;
+  const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const uint32_t comp = lane % S, sub = lane / S;
+  const bool cok = (int)comp < s;
+  const bool live = slice < T.ne;
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < slice && live; ++k) off += A.swidth[T.aux + k];
+  const uint32_t width = live ? A.swidth[T.aux + slice] : 0u;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
+  const uint32_t* choff = A.choff + T.c0 + off;
+  uint32_t prow[PPW];
+  bool pok[PPW];
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    int p = (int)wave * PPW + q;
+    uint32_t slot = slice * WAVE + p * RPW + sub;
+    prow[q] = (!live || p >= S) ? 0xFFFFFFFFu : (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
+    pok[q] = prow[q] < A.nrows;
+  }
+  LaneAcc<AR, PPW> acc;
+  acc.init(A);
+  const uint32_t nd = tile_nd(T.kind), rows_in_tile = tile_rows(T.kind);
+  for (uint32_t d = 0; d < nd && live; ++d) {
+    const int32_t o = A.boffs[T.boff + d];
+#pragma unroll
+    for (int q = 0; q < PPW; ++q) {
+      uint32_t slot = slice * WAVE + ((int)wave * PPW + q) * RPW + sub;
+      int64_t col = (int64_t)prow[q] + o;
+      bool ok = pok[q] && col >= 0 && col < (int64_t)A.ncols && cok;
+      uint32_t v = ok ? ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot) : 0u;
+      uint32_t x = ok ? (uint32_t)X[col * ldx + comp] : 0u;
+      acc.a[q] += AR::mul(v, x);
+    }
+    acc.tick(A);
+  }
+  for (uint32_t j0 = 0; j0 < width; j0 += UC) {
+    uint32_t w[UC], v[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) w[u] = j0 + u < width ? __builtin_nontemporal_load(ent + (size_t)(j0 + u) * WAVE) : PAD_WORD;
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      uint32_t tag = w[u] >> TAG_SHIFT;
+      uint64_t gm = __ballot(tag == TAG_GEN);
+      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      if (j0 + u >= width) break;
+      uint32_t xv[PPW], wp[PPW], vp[PPW];
+#pragma unroll
+      for (int q = 0; q < PPW; ++q) {
+        int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
+        wp[q] = (uint32_t)__shfl((int)w[u], src);
+        vp[q] = (uint32_t)__shfl((int)v[u], src);
+        uint32_t tag = wp[q] >> TAG_SHIFT;
+        xv[q] = (tag != TAG_PAD && cok && pok[q]) ? (uint32_t)X[(int64_t)(wp[q] & COL_MASK) * ldx + comp] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < PPW; ++q) acc.a[q] += term<AR>(wp[q] >> TAG_SHIFT, vp[q], xv[q], A.m);
+      acc.tick(A);
+    }
+  }
+  uint32_t r[PPW];
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    r[q] = AR::reduce(acc.a[q], A);
+    if (pok[q] && cok) Y[(int64_t)prow[q] * ldy + comp] = (Tv)r[q];
+  }
+  if constexpr (PROJ) {
+    LaneAcc<AR, S> pj;  // pj.a[a]: sum over this lane's rows of U[row][a] * W[row][comp]
+    pj.init(A);
+#pragma unroll
+    for (int q = 0; q < PPW; ++q) {
+      uint32_t u = (pok[q] && cok) ? (uint32_t)U[(int64_t)prow[q] * ldu + comp] : 0u;
+      uint32_t w = (pok[q] && cok) ? r[q] : 0u;
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        uint32_t ua = (uint32_t)__shfl((int)u, (int)(sub * S) + a);
+        pj.a[a] += AR::mul(ua, w);
+      }
+      pj.tick(A);
+    }
+    pj.to_residues(A);
+    // sum over the RPW lanes of the same component (lane bits above log2 S)
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      Acc t = pj.a[a];
+      for (int o = S; o < WAVE; o <<= 1) t += shfl_xor_acc(t, o, WAVE);
+      pj.a[a] = t;
+    }
+    if (sub == 0) {
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+        if (a < s && cok) red[wave * 256 + a * s + comp] = (uint64_t)AR::reduce(pj.a[a], A);
+    }
+    __syncthreads();
+    const uint32_t ss = (uint32_t)(s * s);
+    if (threadIdx.x < ss) {
+      uint64_t t = 0;
+      for (int q = 0; q < NW; ++q) t += red[q * 256 + threadIdx.x];
+      out[threadIdx.x] = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------- kernels -----
+struct SeqArgs {
+  const void* U;
+  int64_t ldu;
+  void* W[2];          // W_i lives in W[i & 1] (except W_0 = V)
+  const void* V;
+  int64_t ldv;
+  uint64_t* part[2];   // [4*ntiles][s*s] partial sums, by parity
+  uint64_t* mid[2];    // [NMID][s*s] folded partial sums, by parity
+  void* S;             // L*s*s entries
+  const int64_t* base; // device counter: iteration number of node 0 of this batch
+  int64_t L;
+  int32_t s;
+  int32_t last_w;      // write W_{i+1} even at i = L-1 (into Wlast)
+  void* Wlast;
+};
+
+// Projection of V into the partials of iteration 0.
+template <class AR, typename Tv>
+__global__ __launch_bounds__(TILE_THREADS) void k_seq_first(DevMat A, SeqArgs q) {
+  __shared__ uint64_t red[TILE_THREADS];
+  const Tile T = A.tiles[blockIdx.x];
+  const int64_t ss = (int64_t)q.s * q.s;
+  uint64_t* out = q.part[0] + (int64_t)blockIdx.x * SELL_SLICES * ss;
+  tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, (const Tv*)q.V, q.ldv, q.s, red, out);
+  for (int64_t k = ss + threadIdx.x; k < SELL_SLICES * ss; k += TILE_THREADS) out[k] = 0;
+}
+
+// Iteration i = *base + j. Four workgroups per tile (one per SELL slice; for
+// the other tile kinds only the first works), then NMID workgroups that fold
+// the partials of W_i into NMID sums (mid, by parity), then one workgroup that
+// turns the sums of iteration i-1 into S_{i-1}.
+constexpr uint32_t NMID = 64;
+
+template <class AR, typename Tv, int S>
+__global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int64_t i = *q.base + j;
+  if (i >= q.L) return;
+  const int s = q.s;
+  const int64_t ss = (int64_t)s * s;
+  const uint32_t nparts = A.ntiles * SELL_SLICES;
+  if (blockIdx.x >= nparts) {
+    const uint32_t r = blockIdx.x - nparts;
+    uint32_t pair;
+    if (r < NMID) {  // stage 1 for iteration i
+      uint64_t t = fold_partials(A, q.part[i & 1], r, NMID, nparts, s, (uint64_t*)lds, &pair);
+      if (pair < ss) q.mid[i & 1][r * ss + pair] = t;
+    } else if (i > 0) {  // stage 2 for iteration i-1
+      uint64_t t = fold_partials(A, q.mid[(i - 1) & 1], 0, 1, NMID, s, (uint64_t*)lds, &pair);
+      if (pair < ss) ((Tv*)q.S)[(i - 1) * ss + pair] = (Tv)mod_u64(t, A.m, A.mu);
+    }
+    return;
+  }
+  const bool last = i + 1 == q.L;
+  if (last && !q.last_w) return;
+  const Tv* Win = i == 0 ? (const Tv*)q.V : (const Tv*)q.W[i & 1];
+  const int64_t ldin = i == 0 ? q.ldv : s;
+  Tv* Wout = last ? (Tv*)q.Wlast : (Tv*)q.W[(i + 1) & 1];
+  const uint32_t t = blockIdx.x / SELL_SLICES, slice = blockIdx.x % SELL_SLICES;
+  const Tile T = A.tiles[t];
+  uint64_t* out = q.part[(i + 1) & 1] + (int64_t)blockIdx.x * ss;
+  if (tile_kind(T.kind) == TK_SELL) {
+    if (last) sell_slice_rc<AR, Tv, S, false>(A, T, slice, Win, ldin, Wout, s, s, nullptr, 0, nullptr, nullptr);
+    else sell_slice_rc<AR, Tv, S, true>(A, T, slice, Win, ldin, Wout, s, s, (const Tv*)q.U, q.ldu, out,
+                                        (uint64_t*)lds);
+    return;
+  }
+  if (slice != 0) {  // idle slice of a STREAM/LONG tile: an empty partial
+    if (!last && threadIdx.x < ss) out[threadIdx.x] = 0;
+    return;
+  }
+  if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tv, Tv, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+  else stream_tile_s<AR, Tv, Tv, S>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+  if (last) return;  // W_L only: no partials needed
+  // the projection reads back only rows this workgroup wrote: a workgroup barrier orders them
+  __syncthreads();
+  tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, Wout, s, s, (uint64_t*)lds, out);
+}
+
+// S_{L-1} from the sums of the last iteration.
 template <typename Tv>
-__global__ __launch_bounds__(256) void k_proj_final(DevMat A, const uint64_t* __restrict__ partial, int nparts, int s,
-                                                    Tv* __restrict__ S) {
-  const int t = threadIdx.x;
-  if (t >= s * s) return;
-  uint64_t acc = 0;  // nparts * 256 * m < 2^49
-  for (int q = 0; q < nparts; ++q) acc += partial[(int64_t)q * s * s + t];
-  S[t] = (Tv)mod_u64(acc, A.m, A.mu);
+__global__ __launch_bounds__(TILE_THREADS) void k_seq_finish(DevMat A, SeqArgs q) {
+  __shared__ uint64_t red[TILE_THREADS];
+  const int64_t i = q.L - 1;
+  const int64_t ss = (int64_t)q.s * q.s;
+  uint32_t pair;
+  uint64_t t = fold_partials(A, q.mid[i & 1], 0, 1, NMID, q.s, red, &pair);
+  if (pair < ss) ((Tv*)q.S)[i * ss + pair] = (Tv)mod_u64(t, A.m, A.mu);
+}
+
+__global__ void k_seq_counter(int64_t* base, int64_t add, int set) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base = set ? add : *base + add;
 }
 
 template <class AR, typename Tv>
-static hipError_t proj_go(const DevMat& A, const void* U, int64_t ldu, const void* W, int64_t ldw, int64_t n, int s,
-                          uint64_t* partial, void* S, hipStream_t st) {
-  const Tv* u = (const Tv*)U;
-  const Tv* w = (const Tv*)W;
-  dim3 g(PROJ_WG), b(256);
-  if (s <= 1) hipLaunchKernelGGL((k_proj_partial<AR, Tv, 1>), g, b, 0, st, A, u, ldu, w, ldw, n, s, partial);
-  else if (s <= 2) hipLaunchKernelGGL((k_proj_partial<AR, Tv, 2>), g, b, 0, st, A, u, ldu, w, ldw, n, s, partial);
-  else if (s <= 4) hipLaunchKernelGGL((k_proj_partial<AR, Tv, 4>), g, b, 0, st, A, u, ldu, w, ldw, n, s, partial);
-  else if (s <= 8) hipLaunchKernelGGL((k_proj_partial<AR, Tv, 8>), g, b, 0, st, A, u, ldu, w, ldw, n, s, partial);
-  else hipLaunchKernelGGL((k_proj_partial<AR, Tv, 16>), g, b, 0, st, A, u, ldu, w, ldw, n, s, partial);
-  hipLaunchKernelGGL((k_proj_final<Tv>), dim3(1), dim3(256), 0, st, A, partial, PROJ_WG, s, (Tv*)S);
+static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int batch, hipStream_t user) {
+  const int s = q.s;
+  const int S = s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;  // the step always runs the multi-vector tiles
+  size_t lds = tiles_lds_bytes<AR>(mte, S);
+  if (lds < SELL_SLICES * TILE_THREADS * sizeof(uint64_t)) lds = SELL_SLICES * TILE_THREADS * sizeof(uint64_t);
+  int64_t* base = const_cast<int64_t*>(q.base);
+  auto step = [&](hipStream_t st, int32_t j) {
+    dim3 g(A.ntiles * SELL_SLICES + NMID + 1), b(TILE_THREADS);
+    switch (S) {
+      case 2: hipLaunchKernelGGL((k_seq_step<AR, Tv, 2>), g, b, lds, st, A, q, j); break;
+      case 4: hipLaunchKernelGGL((k_seq_step<AR, Tv, 4>), g, b, lds, st, A, q, j); break;
+      case 8: hipLaunchKernelGGL((k_seq_step<AR, Tv, 8>), g, b, lds, st, A, q, j); break;
+      default: hipLaunchKernelGGL((k_seq_step<AR, Tv, 16>), g, b, lds, st, A, q, j); break;
+    }
+  };
+  hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, user, base, (int64_t)0, 1);
+  hipLaunchKernelGGL((k_seq_first<AR, Tv>), dim3(A.ntiles), dim3(TILE_THREADS), 0, user, A, q);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t L = q.L;
+  int64_t nbatch = batch > 0 ? L / batch : 0;
+  if (nbatch >= 2) {
+    // capture one batch on a private stream, replay it on the caller's stream
+    hipStream_t cs;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int32_t j = 0; j < batch; ++j) step(cs, j);
+      hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, cs, base, (int64_t)batch, 0);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int64_t r = 0; r < nbatch && e == hipSuccess; ++r) e = hipGraphLaunch(exec, user);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return e;
+  } else {
+    nbatch = 0;
+  }
+  // the remaining iterations, launched directly (the counter holds nbatch*batch)
+  for (int64_t i = nbatch * batch; i < L; ++i) step(user, (int32_t)(i - nbatch * batch));
+  hipLaunchKernelGGL((k_seq_finish<Tv>), dim3(1), dim3(TILE_THREADS), 0, user, A, q);
   return hipGetLastError();
 }
 
-hipError_t launch_projection(bool small, const DevMat& A, ffx_dtype dt, const void* U, int64_t ldu, const void* W,
-                             int64_t ldw, int64_t n, int s, uint64_t* partial, void* S, hipStream_t st) {
+hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+                           int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
+                           void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st) {
+  SeqArgs q;
+  // the fold buffers live at the end of the partial buffers
+  const int64_t ss = (int64_t)s * s;
+  q.mid[0] = p0 + (int64_t)A.ntiles * SELL_SLICES * ss;
+  q.mid[1] = p1 + (int64_t)A.ntiles * SELL_SLICES * ss;
+  q.U = U;
+  q.ldu = ldu;
+  q.W[0] = w0;
+  q.W[1] = w1;
+  q.V = V;
+  q.ldv = ldv;
+  q.part[0] = p0;
+  q.part[1] = p1;
+  q.S = S;
+  q.base = counter;
+  q.L = L;
+  q.s = s;
+  q.last_w = Wlast ? 1 : 0;
+  q.Wlast = Wlast;
   if (small) {
-    if (dt == FFX_I32) return proj_go<ArSmall, int32_t>(A, U, ldu, W, ldw, n, s, partial, S, st);
-    return proj_go<ArSmall, int64_t>(A, U, ldu, W, ldw, n, s, partial, S, st);
+    if (dt == FFX_I32) return seq_go<ArSmall, int32_t>(A, mte, q, batch, st);
+    return seq_go<ArSmall, int64_t>(A, mte, q, batch, st);
   }
-  if (dt == FFX_I32) return proj_go<ArBig<true>, int32_t>(A, U, ldu, W, ldw, n, s, partial, S, st);
-  return proj_go<ArBig<true>, int64_t>(A, U, ldu, W, ldw, n, s, partial, S, st);
+  if (chunk) {
+    if (dt == FFX_I32) return seq_go<ArBig<true>, int32_t>(A, mte, q, batch, st);
+    return seq_go<ArBig<true>, int64_t>(A, mte, q, batch, st);
+  }
+  if (dt == FFX_I32) return seq_go<ArBig<false>, int32_t>(A, mte, q, batch, st);
+  return seq_go<ArBig<false>, int64_t>(A, mte, q, batch, st);
 }
 
 template <typename Tv>

@@ -313,6 +313,87 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
   write_row<Tv, S>(A, Y, ldy, row, r, s, alpha, beta);
 }
 
+// SELL with s > 1 vectors: lane (r, c) of a pass handles component c of row
+// r, so the S lanes of one row gather one contiguous piece of X (one cache
+// line for s = 8 int64) instead of S separate lookups per lane. The entry word
+// and value of each row are loaded once per slice column with lane = row and
+// broadcast to the pass lanes with a shuffle.
+template <class AR, typename Tx, typename Tv, int S>
+__device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
+                                    Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta) {
+  constexpr int RPW = WAVE / S;  // rows per pass; S passes cover the slice
+  constexpr int UC = 4;          // slice columns loaded together
+  const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const uint32_t nsl = T.ne;
+  if (wave >= nsl) return;
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < wave; ++k) off += A.swidth[T.aux + k];
+  const uint32_t width = A.swidth[T.aux + wave];
+  const uint32_t comp = lane % S, sub = lane / S;
+  const bool cok = (int)comp < s;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
+  const uint32_t* choff = A.choff + T.c0 + off;
+  uint32_t prow[S];  // row of each pass
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    uint32_t slot = wave * WAVE + p * RPW + sub;
+    prow[p] = (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
+  }
+  LaneAcc<AR, S> acc;  // acc.a[p]: pass p
+  acc.init(A);
+  // band part
+  const uint32_t nd = tile_nd(T.kind), rows_in_tile = tile_rows(T.kind);
+  for (uint32_t d = 0; d < nd; ++d) {
+    const int32_t o = A.boffs[T.boff + d];
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      uint32_t slot = wave * WAVE + p * RPW + sub;
+      int64_t col = (int64_t)prow[p] + o;
+      bool ok = prow[p] < A.nrows && col >= 0 && col < (int64_t)A.ncols && cok;
+      uint32_t v = ok ? ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot) : 0u;
+      uint32_t x = ok ? (uint32_t)X[col * ldx + comp] : 0u;
+      acc.a[p] += AR::mul(v, x);
+    }
+    acc.tick(A);
+  }
+  for (uint32_t j0 = 0; j0 < width; j0 += UC) {
+    uint32_t w[UC], v[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) w[u] = j0 + u < width ? __builtin_nontemporal_load(ent + (size_t)(j0 + u) * WAVE) : PAD_WORD;
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      uint32_t tag = w[u] >> TAG_SHIFT;
+      uint64_t gm = __ballot(tag == TAG_GEN);
+      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      if (j0 + u >= width) break;
+      uint32_t xv[S], wp[S], vp[S];
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        int src = p * RPW + (int)sub;
+        wp[p] = (uint32_t)__shfl((int)w[u], src);
+        vp[p] = (uint32_t)__shfl((int)v[u], src);
+        uint32_t tag = wp[p] >> TAG_SHIFT;
+        xv[p] = (tag != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(wp[p] & COL_MASK) * ldx + comp] : 0u;
+      }
+#pragma unroll
+      for (int p = 0; p < S; ++p) acc.a[p] += term<AR>(wp[p] >> TAG_SHIFT, vp[p], xv[p], A.m);
+      acc.tick(A);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    if (prow[p] < A.nrows && cok) {
+      uint32_t r = AR::reduce(acc.a[p], A);
+      Tv* yr = Y + (int64_t)prow[p] * ldy + comp;
+      uint32_t yo = beta ? (uint32_t)*yr : 0u;
+      *yr = (Tv)((alpha == 1 && beta == 0) ? r : axpby(alpha, r, beta, yo, A.m, A.mu));
+    }
+  }
+}
+
 // ------------------------------- LONG tile ---------------------------------
 template <class AR, typename Tx, typename Tv, int S, int U>
 __device__ inline void long_tile(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
@@ -525,7 +606,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
   extern __shared__ __align__(16) unsigned char lds[];
   const Tile T = A.tiles[blockIdx.x];
   switch (tile_kind(T.kind)) {
-    case TK_SELL: sell_tile<AR, Tx, Tv, S, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta); break;
+    case TK_SELL:
+      if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta);
+      else sell_tile_rc<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta);
+      break;
     case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 1)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
     default:
       if constexpr (S == 1) stream_tile_1<AR, Tx, Tv, U>(A, T, X, ldx, Y, ldy, alpha, beta, lds);

@@ -47,6 +47,11 @@ class MatrixInfo(ctypes.Structure):
                 ("format_blocks", ctypes.c_int64 * NUM_FORMATS)]
 
 
+class BatchParams(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("max_chunk", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -73,6 +78,16 @@ _SIGS = {
     "ffx_sequence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_void_p]),
+    "ffx_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(BatchParams),
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ffx_batch_spmm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "ffx_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p,
+                                      ctypes.POINTER(BatchParams)]),
+    "ffx_batch_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchParams)]),
+    "ffx_batch_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchParams)]),
+    "ffx_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ffx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "ffx_last_error": (ctypes.c_char_p, []),
     "ffx_version": (ctypes.c_char_p, []),
@@ -283,3 +298,68 @@ class Matrix:
 
 def version():
     return lib().ffx_version().decode()
+
+
+class Batch:
+    """Many matrices (same modulus) with their own numbers of right-hand sides, one launch (ffx_batch)."""
+
+    def __init__(self, mats, s, wg_per_cu=0, order=0, max_chunk=8, use_graph=True):
+        self.mats = list(mats)  # the handles must outlive the batch
+        self.s = [int(v) for v in s]
+        n = len(self.mats)
+        hs = (ctypes.c_void_p * n)(*[m.handle.value for m in self.mats])
+        ss = (ctypes.c_int32 * n)(*self.s)
+        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)))
+        h = ctypes.c_void_p()
+        _check(lib().ffx_batch_create(n, hs, ss, ctypes.byref(p), None, ctypes.byref(h)))
+        self._h = h
+
+    def _operands(self, Xs, Ys):
+        n = len(self.mats)
+        if len(Xs) != n or len(Ys) != n:
+            raise ValueError("one X and one Y per matrix")
+        xp, yp, lx, ly = [], [], [], []
+        for k, (X, Y, M) in enumerate(zip(Xs, Ys, self.mats)):
+            inf = M.info()
+            px, sx, ldx = _block(X, inf["ncols"], "X[%d]" % k)
+            py, sy, ldy = _block(Y, inf["nrows"], "Y[%d]" % k)
+            if sx != self.s[k] or sy != self.s[k]:
+                raise ValueError("matrix %d: expected %d right-hand sides" % (k, self.s[k]))
+            xp.append(px)
+            yp.append(py)
+            lx.append(ldx)
+            ly.append(ldy)
+        return ((ctypes.c_void_p * n)(*xp), (ctypes.c_int64 * n)(*lx), (ctypes.c_void_p * n)(*yp),
+                (ctypes.c_int64 * n)(*ly), _dt(Xs[0]))
+
+    def spmm(self, Xs, Ys, stream=None):
+        X, lx, Y, ly, dt = self._operands(Xs, Ys)
+        _check(lib().ffx_batch_spmm(self._h, X, lx, Y, ly, dt, _stream(stream)))
+        return Ys
+
+    def tune(self, Xs, Ys, reps=3, cache_path=None, stream=None):
+        X, lx, Y, ly, dt = self._operands(Xs, Ys)
+        p = BatchParams()
+        _check(lib().ffx_batch_tune(self._h, X, lx, Y, ly, dt, int(reps),
+                                    cache_path.encode() if cache_path else None, _stream(stream), ctypes.byref(p)))
+        return dict(wg_per_cu=p.wg_per_cu, order=p.order, max_chunk=p.max_chunk, use_graph=p.use_graph)
+
+    def params(self):
+        p = BatchParams()
+        _check(lib().ffx_batch_get_params(self._h, ctypes.byref(p)))
+        return dict(wg_per_cu=p.wg_per_cu, order=p.order, max_chunk=p.max_chunk, use_graph=p.use_graph)
+
+    def set_params(self, wg_per_cu=0, order=0, max_chunk=8, use_graph=True):
+        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)))
+        _check(lib().ffx_batch_set_params(self._h, ctypes.byref(p)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().ffx_batch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

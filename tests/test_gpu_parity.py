@@ -328,3 +328,21 @@ def test_compact_x_and_unroll(dev, orc, ffx, compact, acc, tile_entries):
         assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, 17, 19, y0))
     xt = vec(14, 3, A.nrows, A.m)
     assert np.array_equal(M.spmv_t(tdev(xt, dev)).cpu().numpy(), orc.spmv_t(A, xt))
+
+
+@pytest.mark.parametrize("fmt", ["STREAM", "SELL", "SELL_SORTED", "BAND_STREAM", "BAND_SELL_SORTED"])
+@pytest.mark.parametrize("s,m", [(2, 65521), (5, 2**31 - 1), (16, 32749)])
+def test_sequence_formats(dev, orc, ffx, fmt, s, m):
+    """The sequence through the graph path (L >= 128) on every tile kind, with long rows and a band."""
+    sp = synth.c2_spec(n=3000, kmax=600)
+    A = synth.rows(sp)
+    A.m = m
+    L = 150
+    U = vec(15, s, A.nrows, m, s)
+    V = vec(16, s, A.nrows, m, s)
+    note("sequence formats", fmt, s, m)
+    M = ffx.from_synth(A, fixed_format=fmt)
+    S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), L, want_last=True)
+    So, Wo = orc.sequence(A, U, V, L, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
