@@ -220,6 +220,62 @@ ffx_status ffx_batch_get_params(ffx_batch B, ffx_batch_params* params);
 ffx_status ffx_batch_set_params(ffx_batch B, const ffx_batch_params* params);
 ffx_status ffx_batch_destroy(ffx_batch B);
 
+/* ------------------------------------------------------------------------
+ * Learned format selection. The paper's chooser is a hand heuristic whose
+ * thresholds "vary according to the architecture" and need tuning (Section
+ * 2.4, "Heuristic format chooser"). Here a small network predicts, from 32
+ * features of a row block, the log2 time of each of the FFX_NUM_FORMATS
+ * formats, and the block takes the predicted fastest. It is trained on
+ * timings the library measures (ffx_matrix_block_times) with the library's
+ * own forward, backward and Adam kernels. It only chooses formats: results
+ * never depend on it, and a build with FFX_SEL_LEARNED falls back to the
+ * heuristic when the model file is missing, corrupt or predicts non-finite
+ * values.
+ * ------------------------------------------------------------------------ */
+#define FFX_SELECTOR_FEATURES 32
+#define FFX_SELECTOR_PARAMS 6662
+
+typedef struct ffx_selector_s* ffx_selector;
+
+/* A network with He-uniform weights drawn from `seed`, zero biases, and
+ * identity input standardisation (mean 0, scale 1). */
+ffx_status ffx_selector_create(uint64_t seed, ffx_selector* out);
+/* Host copies of the 6,662 parameters (W1 64x32, b1, W2 64x64, b2, W3 6x64,
+ * b3, row-major) and of the 32 input means and scales (x' = (x-mean)*scale).
+ * Any pointer may be NULL to leave that part unchanged / unread. */
+ffx_status ffx_selector_set_params(ffx_selector S, const float* theta, const float* mean, const float* scale);
+ffx_status ffx_selector_get_params(ffx_selector S, float* theta, float* mean, float* scale);
+/* out (device, n x 6) <- predictions for X (device, n x 32 raw features). */
+ffx_status ffx_selector_predict(ffx_selector S, const float* X, int64_t n, float* out, void* stream);
+/* grad (device, 6,662) <- gradient of loss = sum(M*(f(X)-T)^2)/(2n) over the n
+ * samples; T and M are device n x 6 (M is 0/1). *loss (host) when not NULL;
+ * the call then waits for the stream. */
+ffx_status ffx_selector_gradient(ffx_selector S, const float* X, const float* T, const float* M, int64_t n,
+                                 float* grad, double* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the gradient of that loss. */
+ffx_status ffx_selector_train_step(ffx_selector S, const float* X, const float* T, const float* M, int64_t n, float lr,
+                                   double* loss, void* stream);
+/* A checksummed binary file of the parameters and standardisation. */
+ffx_status ffx_selector_save(ffx_selector S, const char* path);
+ffx_status ffx_selector_load(const char* path, ffx_selector* out);
+ffx_status ffx_selector_destroy(ffx_selector S);
+
+/* The 32 features of each row block of a host CSR matrix, as the builder
+ * computes them (opts: block_rows, tile_entries, split_pm1); out (host)
+ * receives min(cap, nblocks) rows of 32 floats. Returns the block count in
+ * *nblocks when not NULL. */
+ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                              const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts, float* out,
+                              int64_t cap, int64_t* nblocks);
+
+/* Time of each row block of A in its stored format, in microseconds per
+ * product (host array, nblocks floats): the block's tiles are launched
+ * `reps` times over in one grid large enough to fill the GPU, timed with HIP
+ * events, and the time divided by the repetitions. x: ncols entries of
+ * dtype (device). The outputs written meanwhile are the product's rows. */
+ffx_status ffx_matrix_block_times(ffx_matrix A, const void* x, void* y, ffx_dtype dtype, int32_t reps, float* us_out,
+                                  void* stream);
+
 /* Status name and the calling thread's last error message. */
 const char* ffx_status_str(ffx_status st);
 const char* ffx_last_error(void);

@@ -4,6 +4,6 @@ The compute path is libffx.so (hand-written HIP kernels behind the C ABI of
 include/ffx.h); `ffx` is its ctypes binding. Importing this package does not
 load the library; the first call does, and raises if it was not built.
 """
-from .ffx import (FORMATS, Batch, FfxError, Matrix, build_opts, lib, version)  # noqa: F401
+from .ffx import (FORMATS, Batch, FfxError, Matrix, Selector, block_features, build_opts, lib, version)  # noqa: F401
 
-__all__ = ["Matrix", "Batch", "FfxError", "FORMATS", "build_opts", "lib", "version"]
+__all__ = ["Matrix", "Batch", "Selector", "FfxError", "FORMATS", "block_features", "build_opts", "lib", "version"]

@@ -196,8 +196,16 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
   check_block("y", Y, nout, s, ldy);
   check_disjoint("x", X, nin, ldx, "y", Y, nout, ldy, s, dt);
   if (nout == 0) return;
-  if (trans && !M->has_t)
-    fail(FFX_EUNSUPPORTED, "transpose product without a stored A^T (build with build_transpose = 1)");
+  if (trans && !M->has_t) {  // scatter the entries of A with 64-bit integer atomics
+    warm_pool(st);
+    unsigned long long* acc = nullptr;
+    size_t bytes = (size_t)nout * s * sizeof(uint64_t);
+    if (hipMallocAsync((void**)&acc, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes", bytes);
+    hipError_t e = launch_transpose_scatter(M->md.small(), M->A.dm, dt, X, ldx, Y, ldy, s, alpha, beta, acc, st);
+    (void)hipFreeAsync(acc, st);
+    FFX_HIP(e);
+    return;
+  }
   const Encoded& E = trans ? M->AT : M->A;
   const int ak = arith_kind(*M);
   if (s == 1 && M->compact_x && nin > 0) {
@@ -397,6 +405,75 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
     hipError_t e = launch_sequence(A->md.small(), A->chunk, E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
                                    Wlast, ws[0], ws[1], (uint64_t*)ws[2], (uint64_t*)ws[3], (int64_t*)ws[4], batch, st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
+    FFX_HIP(e);
+  });
+}
+
+ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                              const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts, float* out,
+                              int64_t cap, int64_t* nblocks) {
+  return guard([&] {
+    if (cap > 0 && !out) fail(FFX_EINVAL, "out is NULL");
+    RCsr A = reduce_csr(nrows, ncols, rowptr, colidx, vals, val_type, m);
+    PlanOpts po = plan_opts(opts);
+    const int64_t BR = po.block_rows, nb = (nrows + BR - 1) / BR;
+    for (int64_t b = 0; b < nb && b < cap; ++b) {
+      BlockStats st = block_stats(A, b * BR, std::min(nrows, (b + 1) * BR), m, po);
+      std::memcpy(out + b * NUM_FEATURES, st.feat, sizeof(float) * NUM_FEATURES);
+    }
+    if (nblocks) *nblocks = nb;
+  });
+}
+
+ffx_status ffx_matrix_block_times(ffx_matrix M, const void* x, void* y, ffx_dtype dtype, int32_t reps, float* us_out,
+                                  void* stream) {
+  return guard([&] {
+    if (!M || !us_out) fail(FFX_EINVAL, "NULL argument");
+    check_dtype(dtype);
+    const int64_t nin = M->info.ncols, nout = M->info.nrows;
+    check_block("x", x, nin, 1, 1);
+    check_block("y", y, nout, 1, 1);
+    check_disjoint("x", x, nin, 1, "y", y, nout, 1, 1, dtype);
+    hipStream_t st = (hipStream_t)stream;
+    const Encoded& E = M->A;
+    const int ak = arith_kind(*M);
+    if (reps < 1) reps = 1;
+    uint16_t* x16 = nullptr;
+    if (M->compact_x && nin > 0) {
+      warm_pool(st);
+      if (hipMallocAsync((void**)&x16, (size_t)nin * 2, st) != hipSuccess) fail(FFX_ENOMEM, "x copy");
+      FFX_HIP(launch_compact_x(dtype, x, 1, x16, nin, st));
+    }
+    hipEvent_t e0, e1;
+    FFX_HIP(hipEventCreate(&e0));
+    FFX_HIP(hipEventCreate(&e1));
+    hipError_t e = hipSuccess;
+    const int64_t nb = (int64_t)E.block_fmt.size();
+    for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
+      uint32_t t0 = E.block_tile0[b], nt = E.block_tile0[b + 1] - t0;
+      if (nt == 0) {
+        us_out[b] = 0.f;
+        continue;
+      }
+      DevMat sub = E.dm;
+      sub.tiles += t0;
+      sub.ntiles = nt;
+      // enough copies of the block to fill the GPU several times over
+      uint32_t R = std::max<uint32_t>((uint32_t)reps, (8192 + nt - 1) / nt);
+      uint32_t grid = std::min<uint64_t>((uint64_t)R * nt, 1u << 30) / nt * nt;
+      R = grid / nt;
+      e = launch_tiles(ak, sub, E.max_tile_entries, dtype, x, 1, y, 1, 1, 1, 0, st, x16, grid);  // warm
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = launch_tiles(ak, sub, E.max_tile_entries, dtype, x, 1, y, 1, 1, 1, 0, st, x16, grid);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      us_out[b] = ms * 1000.f / (float)R;
+    }
+    if (x16) (void)hipFreeAsync(x16, st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     FFX_HIP(e);
   });
 }

@@ -78,6 +78,7 @@ struct Encoded {
   int64_t max_tile_entries = 0;  // largest STREAM tile (sizes the LDS of a launch)
   std::vector<int32_t> block_fmt;
   std::vector<uint32_t> tile_cost;  // per tile: entry words read (with padding) plus band slots
+  std::vector<uint32_t> block_tile0;  // first tile of each block, plus the tile count at the end
   int64_t format_blocks[FFX_NUM_FORMATS] = {0, 0, 0, 0, 0, 0};
   // sizes (elements) of each device array, for the batched concatenation
   int64_t n_ent = 0, n_val = 0, n_choff = 0, n_rowp = 0, n_perm = 0, n_swidth = 0, n_bval = 0, n_boffs = 0;
@@ -97,7 +98,9 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
             const std::vector<int32_t>* forced_formats = nullptr);
 
 // Learned selector hook: fills fmt for the blocks, returns false to fall back.
-bool learned_formats(const std::string& model_path, const std::vector<BlockStats>& blocks, std::vector<int32_t>& fmt);
+bool learned_formats(const std::string& model_path, const std::vector<BlockStats>& blocks, std::vector<int32_t>& fmt,
+                     hipStream_t stream);
+int matrix_arith_kind(const ffx_matrix_s& M);
 
 }  // namespace ffx
 

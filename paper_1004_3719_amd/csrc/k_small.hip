@@ -4,9 +4,10 @@
 
 namespace ffx {
 hipError_t launch_tiles_small(const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
-                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16) {
-  if (dt == FFX_I32) return launch_tiles_t<ArSmall, int32_t>(A, mte, X, ldx, Y, ldy, s, alpha, beta, st, x16);
-  return launch_tiles_t<ArSmall, int64_t>(A, mte, X, ldx, Y, ldy, s, alpha, beta, st, x16);
+                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                              uint32_t nb) {
+  if (dt == FFX_I32) return launch_tiles_t<ArSmall, int32_t>(A, mte, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+  return launch_tiles_t<ArSmall, int64_t>(A, mte, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
 }
 
 hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st) {

@@ -11,25 +11,28 @@ namespace ffx {
 enum ArithKind { AK_SMALL = 0, AK_BIG, AK_BIG_CH, AK_F64_16, AK_F64_16_CH, AK_F64_32, AK_F64_32_CH, AK_COUNT };
 
 hipError_t launch_tiles_small(const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
-                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16);
+                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                              uint32_t nblocks);
 hipError_t launch_tiles_big(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx,
-                            void* Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st);
+                            void* Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st,
+                            uint32_t nblocks);
 hipError_t launch_tiles_f64(bool v16, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X,
                             int64_t ldx, void* Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st,
-                            const uint16_t* x16);
+                            const uint16_t* x16, uint32_t nblocks);
 
-// x16: a 16-bit copy of X (only for s = 1 and m <= 65536), or null.
+// x16: a 16-bit copy of X (only for s = 1 and m <= 65536), or null. nblocks:
+// the grid size (0: one workgroup per tile; larger grids repeat the tiles).
 inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
                                int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st,
-                               const uint16_t* x16 = nullptr) {
+                               const uint16_t* x16 = nullptr, uint32_t nb = 0) {
   switch (ak) {
-    case AK_SMALL: return launch_tiles_small(A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16);
-    case AK_BIG: return launch_tiles_big(false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st);
-    case AK_BIG_CH: return launch_tiles_big(true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st);
-    case AK_F64_16: return launch_tiles_f64(true, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16);
-    case AK_F64_16_CH: return launch_tiles_f64(true, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16);
-    case AK_F64_32: return launch_tiles_f64(false, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr);
-    default: return launch_tiles_f64(false, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr);
+    case AK_SMALL: return launch_tiles_small(A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    case AK_BIG: return launch_tiles_big(false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nb);
+    case AK_BIG_CH: return launch_tiles_big(true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nb);
+    case AK_F64_16: return launch_tiles_f64(true, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    case AK_F64_16_CH: return launch_tiles_f64(true, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    case AK_F64_32: return launch_tiles_f64(false, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
+    default: return launch_tiles_f64(false, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
   }
 }
 
@@ -43,6 +46,12 @@ hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* 
 hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
                            void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st);
+
+// Y = alpha*A^T*X + beta*Y by scattering the entries of A (no stored A^T);
+// acc is workspace of ncols * s uint64.
+hipError_t launch_transpose_scatter(bool small, const DevMat& A, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
+                                    int64_t ldy, int s, uint32_t alpha, uint32_t beta, unsigned long long* acc,
+                                    hipStream_t st);
 
 // Strided copy of an n x s block (ld_in -> ld_out) of dtype elements.
 hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,

@@ -360,7 +360,7 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
     std::fill(fmt.begin(), fmt.end(), o.fixed_format);
     chosen = true;
   } else if (o.selector == FFX_SEL_LEARNED) {
-    chosen = learned_formats(o.model_path, stats, fmt);
+    chosen = learned_formats(o.model_path, stats, fmt, stream);
   }
   if (!chosen)
     for (int64_t b = 0; b < nblocks; ++b) fmt[b] = heuristic_format(stats[b], o);
@@ -368,7 +368,9 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   out->block_fmt = fmt;
   std::fill(out->format_blocks, out->format_blocks + FFX_NUM_FORMATS, 0);
   static const std::vector<int32_t> no_band;
+  out->block_tile0.assign(nblocks + 1, 0);
   for (int64_t b = 0; b < nblocks; ++b) {
+    out->block_tile0[b] = (uint32_t)H.tiles.size();
     int f = fmt[b];
     if (f < 0 || f >= FFX_NUM_FORMATS) fail(FFX_EINVAL, "format %d for block %lld", f, (long long)b);
     out->format_blocks[f]++;
@@ -382,6 +384,7 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
     if (base == FFX_FMT_STREAM) encode_stream(R, r0, r1 - r0, boff, o.tile_entries, H);
     else encode_sell(R, r0, r1 - r0, A.nrows, base == FFX_FMT_SELL_SORTED, boff, H);
   }
+  out->block_tile0[nblocks] = (uint32_t)H.tiles.size();
   if (H.ent.size() >= UINT32_MAX || H.val.size() >= UINT32_MAX || H.bval.size() >= UINT32_MAX)
     fail(FFX_EUNSUPPORTED, "encoded matrix exceeds 2^32 words in one array");
 

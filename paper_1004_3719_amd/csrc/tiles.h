@@ -604,7 +604,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
                                                         Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha,
                                                         uint32_t beta) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const Tile T = A.tiles[blockIdx.x];
+  // a grid larger than the tile table repeats it (per-block timing)
+  const Tile T = A.tiles[blockIdx.x % A.ntiles];
   switch (tile_kind(T.kind)) {
     case TK_SELL:
       if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta);
@@ -641,32 +642,33 @@ inline int unroll_for(int64_t max_tile_entries) {
 }
 
 template <class AR, typename Tx, typename Tv, int U>
-static void launch_s1(const DevMat& A, size_t lds, const Tx* x, int64_t ldx, Tv* y, int64_t ldy, uint32_t alpha,
-                      uint32_t beta, hipStream_t st) {
-  hipLaunchKernelGGL((k_tiles<AR, Tx, Tv, 1, U>), dim3(A.ntiles), dim3(TILE_THREADS), lds, st, A, x, ldx, y, ldy, 1,
-                     alpha, beta);
+static void launch_s1(const DevMat& A, dim3 grid, size_t lds, const Tx* x, int64_t ldx, Tv* y, int64_t ldy,
+                      uint32_t alpha, uint32_t beta, hipStream_t st) {
+  hipLaunchKernelGGL((k_tiles<AR, Tx, Tv, 1, U>), grid, dim3(TILE_THREADS), lds, st, A, x, ldx, y, ldy, 1, alpha,
+                     beta);
 }
 
 // x16: when not null, a 16-bit copy of the one vector (s must be 1)
 template <class AR, typename Tv>
 hipError_t launch_tiles_t(const DevMat& A, int64_t max_tile_entries, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                          int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16) {
+                          int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                          uint32_t nblocks = 0) {
   if (A.ntiles == 0) return hipSuccess;
   const int S = s <= 1 ? 1 : s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;
   size_t lds = tiles_lds_bytes<AR>(max_tile_entries, S);
-  dim3 grid(A.ntiles), block(TILE_THREADS);
+  dim3 grid(nblocks ? nblocks : A.ntiles), block(TILE_THREADS);
   const Tv* x = (const Tv*)X;
   Tv* y = (Tv*)Y;
   if (S == 1) {
     const int U = unroll_for(max_tile_entries);
     if (x16) {
-      if (U == 1) launch_s1<AR, uint16_t, Tv, 1>(A, lds, x16, 1, y, ldy, alpha, beta, st);
-      else if (U == 2) launch_s1<AR, uint16_t, Tv, 2>(A, lds, x16, 1, y, ldy, alpha, beta, st);
-      else launch_s1<AR, uint16_t, Tv, 4>(A, lds, x16, 1, y, ldy, alpha, beta, st);
+      if (U == 1) launch_s1<AR, uint16_t, Tv, 1>(A, grid, lds, x16, 1, y, ldy, alpha, beta, st);
+      else if (U == 2) launch_s1<AR, uint16_t, Tv, 2>(A, grid, lds, x16, 1, y, ldy, alpha, beta, st);
+      else launch_s1<AR, uint16_t, Tv, 4>(A, grid, lds, x16, 1, y, ldy, alpha, beta, st);
     } else {
-      if (U == 1) launch_s1<AR, Tv, Tv, 1>(A, lds, x, ldx, y, ldy, alpha, beta, st);
-      else if (U == 2) launch_s1<AR, Tv, Tv, 2>(A, lds, x, ldx, y, ldy, alpha, beta, st);
-      else launch_s1<AR, Tv, Tv, 4>(A, lds, x, ldx, y, ldy, alpha, beta, st);
+      if (U == 1) launch_s1<AR, Tv, Tv, 1>(A, grid, lds, x, ldx, y, ldy, alpha, beta, st);
+      else if (U == 2) launch_s1<AR, Tv, Tv, 2>(A, grid, lds, x, ldx, y, ldy, alpha, beta, st);
+      else launch_s1<AR, Tv, Tv, 4>(A, grid, lds, x, ldx, y, ldy, alpha, beta, st);
     }
     return hipGetLastError();
   }

@@ -88,6 +88,25 @@ _SIGS = {
     "ffx_batch_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchParams)]),
     "ffx_batch_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchParams)]),
     "ffx_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ffx_selector_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
+    "ffx_selector_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ffx_selector_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ffx_selector_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "ffx_selector_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_void_p]),
+    "ffx_selector_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int64, ctypes.c_float, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.c_void_p]),
+    "ffx_selector_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "ffx_selector_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ffx_selector_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ffx_block_features": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(BuildOpts),
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "ffx_matrix_block_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "ffx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "ffx_last_error": (ctypes.c_char_p, []),
     "ffx_version": (ctypes.c_char_p, []),
@@ -229,6 +248,19 @@ class Matrix:
         d["format_blocks"] = {FORMATS[f]: int(I.format_blocks[f]) for f in range(NUM_FORMATS)}
         return d
 
+    def block_times(self, x, reps=4, y=None, stream=None):
+        """Microseconds per product of each row block in its stored format (ffx_matrix_block_times)."""
+        import torch
+        inf = self.info()
+        px, _, _ = _block(x, inf["ncols"], "x")
+        if y is None:
+            y = torch.empty(inf["nrows"], dtype=x.dtype, device=x.device)
+        py, _, _ = _block(y, inf["nrows"], "y")
+        out = np.zeros(max(1, inf["nblocks"]), np.float32)
+        _check(lib().ffx_matrix_block_times(self._h, ctypes.c_void_p(px), ctypes.c_void_p(py), _dt(x), int(reps),
+                                            out.ctypes.data, _stream(stream)))
+        return out[:inf["nblocks"]]
+
     def block_formats(self, transpose=False):
         n = self.info()["nblocks"]
         out = np.zeros(max(1, n), np.int32)
@@ -356,6 +388,90 @@ class Batch:
     def close(self):
         if self._h is not None and self._h.value:
             _check(lib().ffx_batch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+NFEAT, NPARAM = 32, 6662
+
+
+def block_features(nrows, ncols, rowptr, col, val, m, **opts):
+    """The builder's 32 features of every row block (ffx_block_features), as an (nblocks, 32) array."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    rp = rp - rp[0]
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.int64)
+    o = build_opts(**opts)
+    nb = ctypes.c_int64()
+    _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
+                                    int(m), ctypes.byref(o), None, 0, ctypes.byref(nb)))
+    out = np.zeros((max(1, nb.value), NFEAT), np.float32)
+    _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
+                                    int(m), ctypes.byref(o), out.ctypes.data, nb.value, None))
+    return out[:nb.value]
+
+
+class Selector:
+    """The format-selection network on the device (ffx_selector)."""
+
+    def __init__(self, seed=0, handle=None):
+        if handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().ffx_selector_create(int(seed) & (2**64 - 1), ctypes.byref(h)))
+            handle = h
+        self._h = handle
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        _check(lib().ffx_selector_load(path.encode(), ctypes.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path):
+        _check(lib().ffx_selector_save(self._h, path.encode()))
+
+    def get_params(self):
+        th = np.zeros(NPARAM, np.float32)
+        mu = np.zeros(NFEAT, np.float32)
+        sc = np.zeros(NFEAT, np.float32)
+        _check(lib().ffx_selector_get_params(self._h, th.ctypes.data, mu.ctypes.data, sc.ctypes.data))
+        return th, mu, sc
+
+    def set_params(self, theta=None, mean=None, scale=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (theta, mean, scale)]
+        _check(lib().ffx_selector_set_params(self._h, *[None if a is None else a.ctypes.data for a in arrs]))
+
+    def predict(self, X, stream=None):
+        import torch
+        out = torch.empty((X.shape[0], 6), dtype=torch.float32, device=X.device)
+        _check(lib().ffx_selector_predict(self._h, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def gradient(self, X, T, M, stream=None):
+        import torch
+        g = torch.empty(NPARAM, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        _check(lib().ffx_selector_gradient(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                           ctypes.c_void_p(M.data_ptr()), X.shape[0], ctypes.c_void_p(g.data_ptr()),
+                                           ctypes.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, X, T, M, lr=1e-3, want_loss=False, stream=None):
+        loss = ctypes.c_double()
+        _check(lib().ffx_selector_train_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                             ctypes.c_void_p(M.data_ptr()), X.shape[0], float(lr),
+                                             ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(lib().ffx_selector_destroy(self._h))
         self._h = None
 
     def __del__(self):

@@ -1,0 +1,127 @@
+"""Training and evaluation of the learned per-block format selector.
+
+Labels come from the library itself: every training matrix is built once per
+format (all blocks forced to that format) and each block is timed on the GPU
+with ffx_matrix_block_times; the label of (block, format) is log2 of that
+time in microseconds. Features are the builder's own 32 block features
+(ffx_block_features). The network is trained with the library's forward,
+backward and Adam kernels (Selector.train_step); nothing here computes a
+gradient. Input standardisation (mean, scale) is taken from the training
+features and stored with the model.
+
+The paper's chooser is a hand heuristic whose thresholds need tuning per
+machine (Section 2.4, "Heuristic format chooser"); this replaces the tuning by
+measurement. Whatever the network predicts, products are unchanged: it only
+picks formats.
+"""
+import time
+
+import numpy as np
+
+from .ffx import FORMATS, Matrix, Selector, block_features
+
+NF = len(FORMATS)
+
+
+def block_labels(A, x_dev, reps=4, opts=None):
+    """(features (nb x 32), log2 microseconds (nb x 6)) of the row blocks of A, a Csr-like object with
+    nrows, ncols, rowptr, col, val, m."""
+    opts = dict(opts or {})
+    F = block_features(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
+    T = np.zeros((F.shape[0], NF), np.float32)
+    for f in range(NF):
+        M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, fixed_format=f, **opts)
+        t = M.block_times(x_dev, reps=reps)
+        M.close()
+        T[:, f] = np.log2(np.maximum(t, 1e-3))
+    return F, T
+
+
+def standardisation(X):
+    mean = X.mean(axis=0).astype(np.float32)
+    sd = X.std(axis=0)
+    scale = np.where(sd > 1e-6, 1.0 / np.maximum(sd, 1e-6), 1.0).astype(np.float32)
+    return mean, scale
+
+
+def fit(X, T, M=None, epochs=60, batch=512, lr=2e-3, seed=0, device="cuda:0", val=None, log=None):
+    """Train a Selector on features X and log-time targets T (numpy); M masks missing labels.
+    Returns (selector, history)."""
+    import torch
+    dev = torch.device(device)
+    if M is None:
+        M = np.ones_like(T)
+    mean, scale = standardisation(X)
+    S = Selector(seed=seed)
+    S.set_params(mean=mean, scale=scale)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(dev)
+    Td = torch.from_numpy(np.ascontiguousarray(T, np.float32)).to(dev)
+    Md = torch.from_numpy(np.ascontiguousarray(M, np.float32)).to(dev)
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(dev)
+        for b0 in range(0, n, batch):
+            idx = perm[b0:b0 + batch]
+            if idx.numel() < 2:
+                continue
+            step_lr = lr * (0.5 * (1 + np.cos(np.pi * ep / epochs)))  # cosine decay
+            S.train_step(Xd[idx].contiguous(), Td[idx].contiguous(), Md[idx].contiguous(), lr=step_lr)
+        if ep % 10 == 9 or ep == epochs - 1:
+            loss, _ = S.gradient(Xd, Td, Md)
+            rec = {"epoch": ep + 1, "train_loss": loss}
+            if val is not None:
+                Xv, Tv = val
+                Xvd = torch.from_numpy(np.ascontiguousarray(Xv, np.float32)).to(dev)
+                Tvd = torch.from_numpy(np.ascontiguousarray(Tv, np.float32)).to(dev)
+                lv, _ = S.gradient(Xvd, Tvd, torch.ones_like(Tvd))
+                rec["val_loss"] = lv
+            hist.append(rec)
+            if log:
+                log(rec)
+    return S, hist
+
+
+def choose(S, X, device="cuda:0"):
+    """Predicted fastest format per row (argmin of the predicted log times)."""
+    import torch
+    P = S.predict(torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(torch.device(device))).cpu().numpy()
+    return P.argmin(axis=1), P
+
+
+def time_product(M, x, y, reps=10):
+    """Median microseconds of y = A x with HIP events."""
+    import torch
+    for _ in range(2):
+        M.spmv(x, y=y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        M.spmv(x, y=y)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    return float(np.median(ts))
+
+
+def evaluate(A, model_path, x, reps=10):
+    """Whole-product time with the heuristic's and the learned formats (and whether the results agree)."""
+    import torch
+    y1 = torch.empty(A.nrows, dtype=x.dtype, device=x.device)
+    y2 = torch.empty_like(y1)
+    t0 = time.perf_counter()
+    Mh = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m)
+    Ml = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, selector="learned", model_path=model_path)
+    build_s = time.perf_counter() - t0
+    th = time_product(Mh, x, y1, reps)
+    tl = time_product(Ml, x, y2, reps)
+    same = bool(torch.equal(y1, y2))
+    out = {"heuristic_us": th, "learned_us": tl, "same_result": same, "build_s": build_s,
+           "heuristic_formats": Mh.info()["format_blocks"], "learned_formats": Ml.info()["format_blocks"]}
+    Mh.close()
+    Ml.close()
+    return out

@@ -346,3 +346,24 @@ def test_sequence_formats(dev, orc, ffx, fmt, s, m):
     So, Wo = orc.sequence(A, U, V, L, want_last=True)
     assert np.array_equal(S.cpu().numpy(), So)
     assert np.array_equal(W.cpu().numpy(), Wo)
+
+
+@pytest.mark.parametrize("m,fmt", [(65521, None), (32749, "SELL_SORTED"), (2**31 - 1, "BAND_STREAM"), (2, "STREAM")])
+@pytest.mark.parametrize("s", [1, 3, 8])
+def test_transpose_without_stored_transpose(dev, orc, ffx, m, fmt, s):
+    """A^T X by scattering A's entries with 64-bit integer atomics (no A^T built)."""
+    sp = synth.c2_spec(n=30_000, kmax=3000)
+    A = synth.rows(sp)
+    A.m = m
+    note("scatter transpose", m, fmt, s)
+    M = ffx.from_synth(A, fixed_format=fmt)
+    assert not M.info()["has_transpose"]
+    X = vec(17, s, A.nrows, m, s)
+    Y0 = vec(18, s, A.ncols, m, s)
+    Yd = tdev(Y0, dev, torch.int64)
+    M.spmm_t(tdev(X, dev, torch.int64), alpha=5 % m, beta=7 % m, Y=Yd)
+    assert np.array_equal(Yd.cpu().numpy(), orc.spmm_t(A, X, 5 % m, 7 % m, Y0))
+    for _ in range(3):  # order-free: repeated scatters agree bit for bit
+        Yd2 = tdev(Y0, dev, torch.int64)
+        M.spmm_t(tdev(X, dev, torch.int64), alpha=5 % m, beta=7 % m, Y=Yd2)
+        assert torch.equal(Yd, Yd2)

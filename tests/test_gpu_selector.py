@@ -1,0 +1,138 @@
+"""GPU checks of the learned selector: the network kernels against the fp64 reference, the model
+file, the heuristic fallback, and that the selector never changes a product."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp_ref as R
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, 32)).astype(np.float32)
+    T = rng.normal(size=(n, 6)).astype(np.float32)
+    M = (rng.random(size=(n, 6)) < 0.85).astype(np.float32)
+    return X, T, M
+
+
+def test_forward_and_gradient_match_reference(dev):
+    from paper_1004_3719_amd import Selector
+    S = Selector(seed=7)
+    theta, mean, scale = S.get_params()
+    theta = theta + np.random.default_rng(3).normal(scale=0.05, size=theta.shape).astype(np.float32)
+    S.set_params(theta=theta)
+    X, T, M = data(512, 1)
+    Xd, Td, Md = (torch.from_numpy(a).to(dev) for a in (X, T, M))
+    out = S.predict(Xd).cpu().numpy()
+    ref, _ = R.forward(theta.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(out - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+    loss, g = S.gradient(Xd, Td, Md)
+    Lr, gr = R.loss_grad(theta.astype(np.float64), X, T, M)
+    g = g.cpu().numpy()
+    assert abs(loss - Lr) <= 1e-4 * abs(Lr)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    assert np.max(np.abs(g - gr)) <= 1e-4 * np.max(np.abs(gr)) + 1e-7
+
+
+def test_standardisation_is_applied(dev):
+    from paper_1004_3719_amd import Selector
+    S = Selector(seed=8)
+    theta, _, _ = S.get_params()
+    rng = np.random.default_rng(5)
+    mean = rng.normal(size=32).astype(np.float32)
+    scale = (0.5 + rng.random(size=32)).astype(np.float32)
+    S.set_params(mean=mean, scale=scale)
+    X, _, _ = data(64, 2)
+    out = S.predict(torch.from_numpy(X).to(dev)).cpu().numpy()
+    ref, _ = R.forward(theta.astype(np.float64), (X.astype(np.float64) - mean) * scale)
+    assert np.max(np.abs(out - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_adam_steps_match_reference(dev):
+    from paper_1004_3719_amd import Selector
+    S = Selector(seed=9)
+    theta0, _, _ = S.get_params()
+    X, T, M = data(256, 3)
+    Xd, Td, Md = (torch.from_numpy(a).to(dev) for a in (X, T, M))
+    opt = R.Adam(R.NPARAM, lr=1e-3)
+    th = theta0.astype(np.float64)
+    for _ in range(3):
+        S.train_step(Xd, Td, Md, lr=1e-3)
+        _, g = R.loss_grad(th, X, T, M)
+        th = opt.step(th, g)
+    got, _, _ = S.get_params()
+    # Adam moves each weight by about lr per step; compare the moves
+    assert np.max(np.abs((got - theta0) - (th - theta0))) <= 2e-5
+
+
+def test_training_reduces_loss(dev):
+    from paper_1004_3719_amd import Selector
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(2048, 32)).astype(np.float32)
+    W = rng.normal(size=(32, 6)).astype(np.float32) / 6
+    T = (np.tanh(X @ W) + 0.1 * X[:, :6]).astype(np.float32)
+    M = np.ones_like(T)
+    Xd, Td, Md = (torch.from_numpy(a).to(dev) for a in (X, T, M))
+    S = Selector(seed=1)
+    l0 = S.train_step(Xd, Td, Md, lr=3e-3, want_loss=True)
+    for _ in range(300):
+        S.train_step(Xd, Td, Md, lr=3e-3)
+    l1, _ = S.gradient(Xd, Td, Md)
+    assert l1 < 0.2 * l0
+
+
+def test_model_file_roundtrip_and_fallback(dev, tmp_path):
+    from paper_1004_3719_amd import FfxError, Matrix, Selector
+    S = Selector(seed=11)
+    path = str(tmp_path / "sel.bin")
+    S.save(path)
+    S2 = Selector.load(path)
+    a, b = S.get_params(), S2.get_params()
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    bad = str(tmp_path / "bad.bin")
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 0xFF
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(FfxError):
+        Selector.load(bad)
+    A = synth.c2(n=50_000)
+    heur = Matrix.from_synth(A).block_formats()
+    for p in [bad, str(tmp_path / "missing.bin")]:  # corrupt or missing model: the heuristic's formats
+        assert np.array_equal(Matrix.from_synth(A, selector="learned", model_path=p).block_formats(), heur)
+
+
+def test_learned_selection_never_changes_a_result(dev, tmp_path):
+    from paper_1004_3719_amd import Matrix, Selector
+    A = synth.c2(n=80_000)
+    x = synth.vector(21, 1, A.ncols, 0, A.m - 1)
+    want = oracle.get().spmv(A, x)
+    xd = torch.from_numpy(x.astype(np.int32)).to(dev)
+    for seed in range(4):  # arbitrary networks pick arbitrary formats
+        path = str(tmp_path / ("s%d.bin" % seed))
+        Selector(seed=100 + seed).save(path)
+        M = Matrix.from_synth(A, selector="learned", model_path=path)
+        assert np.array_equal(M.spmv(xd).cpu().numpy(), want), M.info()["format_blocks"]
+
+
+def test_block_times(dev):
+    from paper_1004_3719_amd import Matrix
+    A = synth.c2(n=40_000)
+    x = torch.from_numpy(synth.vector(22, 1, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
+    M = Matrix.from_synth(A)
+    t = M.block_times(x, reps=4)
+    assert t.shape == (M.info()["nblocks"],) and np.all(t > 0) and np.all(np.isfinite(t))
+    y = M.spmv(x)
+    assert np.array_equal(y.cpu().numpy(), oracle.get().spmv(A, x.cpu().numpy()))
