@@ -1,17 +1,27 @@
-"""Benchmark: exact y = A x mod m on the large power-law matrix, one GPU.
+"""Benchmarks of the exact sparse products on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--acc int64|fp64] [--selector heuristic|learned]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c1|c3|c4|c5] ...
 
-A step is one product y = A x mod 32749 over the whole 2,000,000-row matrix
-(power-law rows, a 5-diagonal band, 60% of entries +-1), with A, x and y
-resident in HBM. Prints one JSON line. The roofline object prices the tile
-kernel's algorithmic bytes against the MI355X HBM peak; the cpu_baseline
-object times the plain C oracle on the host on a bounded sample of the same
-products (and checks the GPU result on that sample bit for bit).
+Default (c2): a step is one product y = A x mod 32749 over the 2,000,000-row
+power-law matrix (truncated Zipf(1.8) rows, a 5-diagonal band, 60% of entries
++-1), with A, x and y resident in HBM. Prints one JSON line with the roofline
+of the product kernel (algorithmic bytes over its HIP-event time against the
+8 TB/s HBM peak) and a CPU baseline: the plain C oracle, one thread, on the
+host, on repeated full products (checking the GPU result bit for bit).
+
+Other configurations print the same kind of line:
+  c1  n = 10,000, 10 per row, m = 65521: A x and A^T x (latency-bound);
+  c3  block-Wiedemann sequence U^T A^i V, n = 200,000, s = 8, m = 2^31-1,
+      L = 50,003, one hipGraph-replayed fused step per iteration;
+  c4  256 uneven matrices with 1..16 right-hand sides, one persistent batched
+      launch (tuned) against back-to-back per-matrix launches;
+  c5  learned format selection: train on measured block timings, evaluate the
+      whole-product time on held-out matrices against the plain heuristic.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -22,8 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "exact nnz·vec/s (bit-exact) + HBM GB/s % peak; learned/batched vs plain"
+UNIT = "nnz·vec/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "k_big.hip", "k_f64.hip"]
+KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "launch.h"]  # the one-vector product kernel
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def kernel_hash():
@@ -34,10 +49,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def counters_traffic(path, khash):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they match the kernel."""
+def counters_traffic(name, khash):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if taken on these kernel sources."""
     try:
-        with open(path) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -46,32 +61,32 @@ def counters_traffic(path, khash):
     return d.get("bytes_per_launch")
 
 
-def algorithmic_bytes(A, m):
-    """Bytes one y = A x must move in a CSR whose +-1 entries carry no value: 4 B per column index,
+def algorithmic_bytes(A, m, vec_bytes=4, s=1):
+    """Bytes one product must move in a CSR whose +-1 entries carry no value: 4 B per column index,
     2 B (m < 2^16) or 4 B per other value, 4 B per row pointer, x read once, y written once."""
     r = np.mod(A.val, m)
     n_gen = int(np.count_nonzero((r != 0) & (r != 1) & (r != m - 1)))
     vb = 2 if m < 2**16 else 4
-    return 4 * A.nnz + vb * n_gen + 4 * (A.nrows + 1) + 4 * A.ncols + 4 * A.nrows
+    return 4 * A.nnz + vb * n_gen + 4 * (A.nrows + 1) + vec_bytes * s * (A.ncols + A.nrows)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
-    ap.add_argument("--selector", default="heuristic", choices=["heuristic", "learned"])
-    ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
-    ap.add_argument("--tile-entries", type=int, default=0)
-    ap.add_argument("--fixed-format", default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def line(value, ms, args, dtype, config, roofline, cpu, extra=None):
+    out = {"metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
+           "cpu_baseline": cpu}
+    if extra:
+        out.update(extra)
+    print(json.dumps(out), flush=True)
 
+
+def event_pairs(n):
+    import torch
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+
+# --------------------------------------------------------------------- c2 / c1
+def bench_spmv(args, big=True):
     import torch
 
     import synth
@@ -79,28 +94,25 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    A = synth.c2()
+    A = synth.c2() if big else synth.c1()
     m = A.m
     x_np = synth.vector(synth.SEED0 + 1, 1, A.ncols, 0, m - 1)
-    print("[bench] generated n=%d nnz=%d in %.1fs" % (A.nrows, A.nnz, time.time() - t0), file=sys.stderr, flush=True)
+    log("generated n=%d nnz=%d in %.1fs" % (A.nrows, A.nnz, time.time() - t0))
     t0 = time.time()
-    opts = dict(acc=args.acc, selector=args.selector, tile_entries=args.tile_entries, fixed_format=args.fixed_format)
+    opts = dict(acc=args.acc, selector=args.selector, tile_entries=args.tile_entries, fixed_format=args.fixed_format,
+                build_transpose=not big)
     if args.selector == "learned":
         opts["model_path"] = args.model
     M = Matrix.from_synth(A, **opts)
     info = M.info()
-    print("[bench] built in %.1fs: %s" % (time.time() - t0, info["format_blocks"]), file=sys.stderr, flush=True)
+    log("built in %.1fs: %s" % (time.time() - t0, info["format_blocks"]))
     x = torch.from_numpy(x_np.astype(np.int32)).to(dev)
     y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-
     for _ in range(args.warmup):
         M.spmv(x, y=y)
     torch.cuda.synchronize()
-
-    # per-launch kernel time with HIP events on the launch stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
+    ev = event_pairs(args.steps)
     t_start = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
@@ -109,20 +121,27 @@ def main():
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ms_per_step = (t_end - t_start) * 1e3 / args.steps
-    print("[bench] %d steps: %.4f ms/step wall, %.4f ms/kernel" % (args.steps, ms_per_step, kernel_ms),
-          file=sys.stderr, flush=True)
-
+    ms = (t_end - t_start) * 1e3 / args.steps
+    log("%d steps: %.4f ms/step wall, %.4f ms/launch (events)" % (args.steps, ms, kernel_ms))
+    extra = {}
+    if not big:  # the plain configuration also times A^T x
+        yt = torch.empty(A.ncols, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup):
+            M.spmv_t(x, y=yt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            M.spmv_t(x, y=yt)
+        torch.cuda.synchronize()
+        extra["transpose_ms_per_step"] = round((time.perf_counter() - t1) * 1e3 / args.steps, 5)
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
     khash = kernel_hash()
-    traffic = counters_traffic(os.path.join(ROOT, "profiles", "spmv_powerlaw_2M_counters.json"), khash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_tiles<ArSmall,int,1>", "kernel_ms": round(kernel_ms, 5),
-                "algorithmic_bytes": int(b_alg),
-                "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows)}
-
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counters_traffic("spmv_powerlaw_2M_counters.json" if big else "none", khash),
+                "kernel": "k_tiles (one-vector tiles)", "kernel_ms": round(kernel_ms, 5),
+                "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows)}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -135,22 +154,230 @@ def main():
             t_cpu += time.perf_counter() - t1
             reps += 1
             exact = exact and bool(np.array_equal(got, want))
-        cpu = {"value": round(A.nnz * reps / t_cpu, 1), "unit": "nnz·vec/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(A.nnz * reps / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
                "sample": "%d full products y = A x over the same matrix (single thread)" % reps,
                "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
         if not exact:
-            print("[bench] GPU result differs from the oracle", file=sys.stderr, flush=True)
+            log("GPU result differs from the oracle")
+    workload = ("power-law hybrid SpMV mod 32749: n=2,000,000, truncated Zipf(1.8) rows on [1,5000] + diagonals "
+                "-2..2, 60% +-1, x int32") if big else "plain SpMV mod 65521: n=10,000, 10 nnz/row, x int32"
+    config = {"workload": workload, "n": A.nrows, "nnz": A.nnz, "m": m, "acc": args.acc, "selector": args.selector,
+              "formats": info["format_blocks"], "kernel_hash": khash}
+    line(A.nnz / (ms * 1e-3), ms, args, args.acc, config, roofline, cpu, extra)
 
-    value = A.nnz / (ms_per_step * 1e-3)
-    out = {"metric": METRIC, "value": round(value, 1), "unit": "nnz·vec/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": args.acc, "data": "synthetic",
-           "config": {"workload": "power-law hybrid SpMV mod 32749: n=2,000,000, truncated Zipf(1.8) rows on "
-                                  "[1,5000] + diagonals -2..2, 60% +-1, x int32",
-                      "n": A.nrows, "nnz": A.nnz, "m": m, "acc": args.acc, "selector": args.selector,
-                      "formats": info["format_blocks"], "kernel_hash": khash},
-           "roofline": roofline, "cpu_baseline": cpu}
-    print(json.dumps(out))
+
+# ---------------------------------------------------------------------- c3
+def bench_sequence(args):
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix
+
+    dev = torch.device("cuda:0")
+    A = synth.c3()
+    U, V = synth.c3_blocks()
+    L = args.seq_length or synth.c3_length(A.nrows, 8)
+    M = Matrix.from_synth(A)
+    Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
+    M.sequence(Ud, Vd, 4)  # warm
+    torch.cuda.synchronize()
+    a, b = event_pairs(1)[0]
+    t0 = time.perf_counter()
+    a.record()
+    S = M.sequence(Ud, Vd, L)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = a.elapsed_time(b)
+    per_iter_ms = ev_ms / L
+    work = A.nnz * 8 * L
+    # survey per-iteration bytes: A (col 4 B + val 4 B + row pointers), W read and written, U read
+    b_iter = A.nnz * 8 + 4 * (A.nrows + 1) + 3 * A.nrows * 8 * 8
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        Lc, t_cpu = 0, 0.0
+        Lc = 2
+        t1 = time.perf_counter()
+        So = orc.sequence(A, U, V, Lc)
+        t_cpu = time.perf_counter() - t1
+        exact = bool(np.array_equal(S[:Lc].cpu().numpy(), So))
+        cpu = {"value": round(A.nnz * 8 * Lc / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": "sequence prefix i = 0..%d at full size (single thread)" % (Lc - 1),
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+    roofline = {"bound": "hbm", "achieved": round(b_iter / (per_iter_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(b_iter / (per_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": None, "kernel": "k_seq_step", "kernel_ms": round(per_iter_ms, 5),
+                "algorithmic_bytes": int(b_iter)}
+    config = {"workload": "block-Wiedemann sequence U^T A^i V mod 2^31-1: n=200,000, 15 nnz/row, s=8 int64, "
+                          "L=%d" % L, "n": A.nrows, "nnz": A.nnz, "s": 8, "L": L}
+    args.steps, args.warmup = L, 1
+    line(work / (ev_ms * 1e-3), per_iter_ms, args, "int64", config, roofline, cpu,
+         {"wall_seconds": round(wall, 3)})
+
+
+# ---------------------------------------------------------------------- c4
+def bench_batch(args):
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Batch, Matrix
+
+    dev = torch.device("cuda:0")
+    count = args.batch_count
+    t0 = time.time()
+    mats, Ms, Xs, Ys, S, work = [], [], [], [], [], 0
+    for k in range(count):
+        A = synth.c4_matrix(k)
+        Ms.append(Matrix.from_synth(A))
+        Xs.append(torch.from_numpy(synth.c4_rhs(k, A).astype(np.int32)).to(dev))
+        Ys.append(torch.empty((A.nrows, A.s), dtype=torch.int32, device=dev))
+        S.append(A.s)
+        work += A.nnz * A.s
+        mats.append(A if k < 8 else None)  # keep a few for the exactness check
+    log("built %d matrices in %.1fs, sum nnz*s = %.4g" % (count, time.time() - t0, work))
+
+    def ev_time(f, reps):
+        f()
+        torch.cuda.synchronize()
+        a, b = event_pairs(1)[0]
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def per_matrix():
+        for M, X, Y in zip(Ms, Xs, Ys):
+            M.spmm(X, Y=Y)
+
+    t_per = ev_time(per_matrix, args.steps)
+    B = Batch(Ms, S)
+    t_default = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
+    best = B.tune(Xs, Ys, reps=3)
+    t_batch = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        t_cpu, w_cpu, exact = 0.0, 0, True
+        for k, A in enumerate(mats):
+            if A is None:
+                continue
+            t1 = time.perf_counter()
+            want = orc.spmm(A, synth.c4_rhs(k, A))
+            t_cpu += time.perf_counter() - t1
+            w_cpu += A.nnz * A.s
+            exact = exact and bool(np.array_equal(Ys[k].cpu().numpy(), want))
+        cpu = {"value": round(w_cpu / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": "the first 8 matrices of the batch (single thread)", "seconds": round(t_cpu, 2),
+               "gpu_result_bit_exact": exact}
+    config = {"workload": "256 uneven matrices mod 65521, n log-uniform [2000, 500000], 3..60 nnz/row, "
+                          "uniform/banded/block-diagonal, 70% +-1, 1..16 int32 right-hand sides",
+              "count": count, "sum_nnz_times_s": work, "tuned": best}
+    extra = {"per_matrix_ms": round(t_per, 4), "batch_untuned_ms": round(t_default, 4),
+             "batch_speedup_vs_per_matrix": round(t_per / t_batch, 3)}
+    line(work / (t_batch * 1e-3), t_batch, args, "int64", config, None, cpu, extra)
+
+
+# ---------------------------------------------------------------------- c5
+def bench_selector(args):
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix, selector_train as ST
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(args.seed)
+    BR = 4096
+    Xs, Ts = [], []
+    t0 = time.time()
+    for k in range(args.train_mats):
+        sp, p = synth.c5_spec(k)
+        nb = max(1, sp.nrows // BR)
+        b0 = int(rng.integers(0, max(1, nb - args.train_blocks + 1)))
+        r0, r1 = b0 * BR, min(sp.nrows, (b0 + args.train_blocks) * BR)
+        A = synth.rows(sp, r0, r1)
+        A.m = synth.M_C5
+        x = torch.from_numpy(synth.vector(k, 7, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
+        F, T = ST.block_labels(A, x, reps=4)
+        Xs.append(F)
+        Ts.append(T)
+        if k % 100 == 99:
+            log("labels: %d matrices, %d blocks, %.0fs" % (k + 1, sum(len(f) for f in Xs), time.time() - t0))
+    X = np.concatenate(Xs)
+    T = np.concatenate(Ts)
+    log("training on %d blocks" % len(X))
+    nval = max(1, len(X) // 10)
+    S, hist = ST.fit(X[nval:], T[nval:], epochs=args.epochs, lr=args.lr, seed=args.seed, val=(X[:nval], T[:nval]),
+                     log=lambda r: log(json.dumps(r)))
+    model = args.model_out
+    os.makedirs(os.path.dirname(model), exist_ok=True)
+    S.save(model)
+    # held-out matrices: whole-product time, heuristic vs learned
+    tot_h, tot_l, same, nev = 0.0, 0.0, True, 0
+    for k in range(1800, 1800 + args.eval_mats):
+        sp, p = synth.c5_spec(k)
+        r1 = min(sp.nrows, args.eval_rows) if args.eval_rows else sp.nrows
+        A = synth.rows(sp, 0, r1)
+        A.m = synth.M_C5
+        x = torch.from_numpy(synth.vector(k, 8, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
+        r = ST.evaluate(A, model, x)
+        tot_h += r["heuristic_us"]
+        tot_l += r["learned_us"]
+        same = same and r["same_result"]
+        nev += 1
+    log("held-out: heuristic %.1f us, learned %.1f us, identical results %s" % (tot_h, tot_l, same))
+    config = {"workload": "learned format selection mod 65521: %d training matrices x %d blocks, %d held-out "
+                          "matrices (first %s rows), 32->64->64->6 FP32" % (args.train_mats, args.train_blocks, nev,
+                                                                           args.eval_rows or "all"),
+              "train_blocks": int(len(X)), "history": hist[-1:]}
+    extra = {"heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
+             "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4), "results_identical": same}
+    args.steps, args.warmup = nev, 0
+    line(0.0, tot_l / 1e3, args, "fp32 network / int64 products", config, None, None, extra)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
+    ap.add_argument("--selector", default="heuristic", choices=["heuristic", "learned"])
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
+    ap.add_argument("--tile-entries", type=int, default=0)
+    ap.add_argument("--fixed-format", default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seq-length", type=int, default=0)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--train-mats", type=int, default=1800)
+    ap.add_argument("--train-blocks", type=int, default=4)
+    ap.add_argument("--eval-mats", type=int, default=200)
+    ap.add_argument("--eval-rows", type=int, default=0)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--model-out", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.config == "c2":
+        bench_spmv(args, big=True)
+    elif args.config == "c1":
+        bench_spmv(args, big=False)
+    elif args.config == "c3":
+        bench_sequence(args)
+    elif args.config == "c4":
+        args.steps = min(args.steps, 10)
+        bench_batch(args)
+    else:
+        bench_selector(args)
 
 
 if __name__ == "__main__":

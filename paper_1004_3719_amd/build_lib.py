@@ -27,8 +27,8 @@ def _compile(src):
     cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = DEVICE_FLAGS
-    else:
-        cmd[1:1] = ["-x", "hip", *DEVICE_FLAGS]
+    else:  # host code: OpenMP for the planner
+        cmd[1:1] = ["-x", "hip", "-fopenmp", *DEVICE_FLAGS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
@@ -42,7 +42,7 @@ def build(verbose=True, jobs=None):
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-fopenmp", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])

@@ -56,33 +56,53 @@ RCsr reduce_csr(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32
     if (colidx[k] < 0 || colidx[k] >= ncols)
       fail(FFX_EINVAL, "column index %d at entry %lld outside [0, %lld)", colidx[k], (long long)k, (long long)ncols);
 
+  // two passes over the rows, both in parallel: kept entries per row, then the entries
   RCsr out;
   out.nrows = nrows;
   out.ncols = ncols;
-  out.rp.resize(nrows + 1);
-  out.col.reserve(nnz);
-  out.val.reserve(nnz);
-  out.rp[0] = 0;
-  std::vector<std::pair<uint32_t, uint32_t>> tmp;
-  for (int64_t i = 0; i < nrows; ++i) {
+  out.rp.assign(nrows + 1, 0);
+  auto row_entries = [&](int64_t i, std::vector<std::pair<uint32_t, uint32_t>>& tmp) {
     int64_t a = rowptr[i], b = rowptr[i + 1];
+    tmp.clear();
     bool sorted = true;
     for (int64_t k = a + 1; k < b; ++k)
       if (colidx[k] <= colidx[k - 1]) { sorted = false; break; }
     if (sorted) {
       for (int64_t k = a; k < b; ++k) {
         uint32_t r = canon_i64(raw_value(vals, vt, k), m);
-        if (r) {
-          out.col.push_back((uint32_t)colidx[k]);
-          out.val.push_back(r);
-        }
+        if (r) tmp.emplace_back((uint32_t)colidx[k], r);
       }
     } else {
-      tmp.clear();
-      for (int64_t k = a; k < b; ++k) tmp.emplace_back((uint32_t)colidx[k], canon_i64(raw_value(vals, vt, k), m));
-      finish_row(tmp, m, out);
+      std::vector<std::pair<uint32_t, uint32_t>> raw;
+      for (int64_t k = a; k < b; ++k) raw.emplace_back((uint32_t)colidx[k], canon_i64(raw_value(vals, vt, k), m));
+      RCsr one;
+      finish_row(raw, m, one);
+      for (size_t q = 0; q < one.col.size(); ++q) tmp.emplace_back(one.col[q], one.val[q]);
     }
-    out.rp[i + 1] = (int64_t)out.col.size();
+  };
+#pragma omp parallel
+  {
+    std::vector<std::pair<uint32_t, uint32_t>> tmp;
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < nrows; ++i) {
+      row_entries(i, tmp);
+      out.rp[i + 1] = (int64_t)tmp.size();
+    }
+  }
+  for (int64_t i = 0; i < nrows; ++i) out.rp[i + 1] += out.rp[i];
+  out.col.resize(out.rp[nrows]);
+  out.val.resize(out.rp[nrows]);
+#pragma omp parallel
+  {
+    std::vector<std::pair<uint32_t, uint32_t>> tmp;
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < nrows; ++i) {
+      row_entries(i, tmp);
+      for (size_t q = 0; q < tmp.size(); ++q) {
+        out.col[out.rp[i] + q] = tmp[q].first;
+        out.val[out.rp[i] + q] = tmp[q].second;
+      }
+    }
   }
   return out;
 }

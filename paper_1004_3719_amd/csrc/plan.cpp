@@ -343,12 +343,46 @@ size_t add_part(std::vector<size_t>& offs, size_t& total, size_t n) {
 
 }  // namespace
 
+// Appends part P (one block encoded from offset 0) to G, moving its offsets.
+static void merge_part(HostEnc& G, const HostEnc& P) {
+  const uint32_t o_ent = (uint32_t)G.ent.size(), o_val = (uint32_t)G.val.size(), o_choff = (uint32_t)G.choff.size(),
+                 o_rowp = (uint32_t)G.rowp.size(), o_perm = (uint32_t)G.perm.size(),
+                 o_sw = (uint32_t)G.swidth.size(), o_bval = (uint32_t)G.bval.size(),
+                 o_boffs = (uint32_t)G.boffs.size();
+  for (Tile T : P.tiles) {
+    T.e0 += o_ent;
+    T.c0 += o_choff;
+    T.b0 += o_bval;
+    T.boff += o_boffs;
+    if (tile_kind(T.kind) == TK_STREAM) T.aux += o_rowp;
+    if (tile_kind(T.kind) == TK_SELL) {
+      T.aux += o_sw;
+      if (T.kind & TF_SORTED) T.row0 += o_perm;
+    }
+    G.tiles.push_back(T);
+  }
+  G.ent.insert(G.ent.end(), P.ent.begin(), P.ent.end());
+  G.val.insert(G.val.end(), P.val.begin(), P.val.end());
+  for (uint32_t c : P.choff) G.choff.push_back(c + o_val);
+  for (uint32_t r : P.rowp) G.rowp.push_back(r + o_ent);
+  G.perm.insert(G.perm.end(), P.perm.begin(), P.perm.end());
+  G.swidth.insert(G.swidth.end(), P.swidth.begin(), P.swidth.end());
+  G.bval.insert(G.bval.end(), P.bval.begin(), P.bval.end());
+  G.boffs.insert(G.boffs.end(), P.boffs.begin(), P.boffs.end());
+  G.max_tile_entries = std::max(G.max_tile_entries, P.max_tile_entries);
+  G.max_row_terms = std::max(G.max_row_terms, P.max_row_terms);
+  G.n_plus += P.n_plus;
+  G.n_minus += P.n_minus;
+  G.n_band += P.n_band;
+  G.nnz += P.nnz;
+}
+
 void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t stream, Encoded* out,
             const std::vector<int32_t>* forced) {
-  HostEnc H;
   const int64_t BR = o.block_rows;
   int64_t nblocks = (A.nrows + BR - 1) / BR;
   std::vector<BlockStats> stats(nblocks);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t b = 0; b < nblocks; ++b) stats[b] = block_stats(A, b * BR, std::min(A.nrows, (b + 1) * BR), md.m, o);
   std::vector<int32_t> fmt(nblocks, FFX_FMT_STREAM);
   bool chosen = false;
@@ -364,25 +398,35 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   }
   if (!chosen)
     for (int64_t b = 0; b < nblocks; ++b) fmt[b] = heuristic_format(stats[b], o);
+  for (int64_t b = 0; b < nblocks; ++b)
+    if (fmt[b] < 0 || fmt[b] >= FFX_NUM_FORMATS) fail(FFX_EINVAL, "format %d for block %lld", fmt[b], (long long)b);
 
   out->block_fmt = fmt;
   std::fill(out->format_blocks, out->format_blocks + FFX_NUM_FORMATS, 0);
+  for (int64_t b = 0; b < nblocks; ++b) out->format_blocks[fmt[b]]++;
+  // every block is encoded on its own (in parallel), then the parts are merged in order
+  std::vector<HostEnc> parts(nblocks);
   static const std::vector<int32_t> no_band;
-  out->block_tile0.assign(nblocks + 1, 0);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t b = 0; b < nblocks; ++b) {
-    out->block_tile0[b] = (uint32_t)H.tiles.size();
-    int f = fmt[b];
-    if (f < 0 || f >= FFX_NUM_FORMATS) fail(FFX_EINVAL, "format %d for block %lld", f, (long long)b);
-    out->format_blocks[f]++;
+    const int f = fmt[b];
+    HostEnc& P = parts[b];
     int64_t r0 = b * BR, r1 = std::min(A.nrows, (b + 1) * BR);
     bool band = f >= FFX_FMT_BAND_STREAM;
     const std::vector<int32_t>& offs = band ? stats[b].band_offsets : no_band;
-    uint32_t boff = (uint32_t)H.boffs.size();
-    H.boffs.insert(H.boffs.end(), offs.begin(), offs.end());
-    BlockRows R = split_block(A, r0, r1, offs, md.m, o.split_pm1, H);
+    P.boffs.assign(offs.begin(), offs.end());
+    BlockRows R = split_block(A, r0, r1, offs, md.m, o.split_pm1, P);
     int base = band ? f - FFX_FMT_BAND_STREAM : f;
-    if (base == FFX_FMT_STREAM) encode_stream(R, r0, r1 - r0, boff, o.tile_entries, H);
-    else encode_sell(R, r0, r1 - r0, A.nrows, base == FFX_FMT_SELL_SORTED, boff, H);
+    if (base == FFX_FMT_STREAM) encode_stream(R, r0, r1 - r0, 0, o.tile_entries, P);
+    else encode_sell(R, r0, r1 - r0, A.nrows, base == FFX_FMT_SELL_SORTED, 0, P);
+  }
+  HostEnc H;
+  out->block_tile0.assign(nblocks + 1, 0);
+  for (int64_t b = 0; b < nblocks; ++b) {
+    out->block_tile0[b] = (uint32_t)H.tiles.size();
+    merge_part(H, parts[b]);
+    HostEnc().tiles.swap(parts[b].tiles);  // free as we go
+    parts[b] = HostEnc();
   }
   out->block_tile0[nblocks] = (uint32_t)H.tiles.size();
   if (H.ent.size() >= UINT32_MAX || H.val.size() >= UINT32_MAX || H.bval.size() >= UINT32_MAX)
