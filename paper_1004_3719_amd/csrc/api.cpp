@@ -49,7 +49,18 @@ static int arith_kind(const ffx_matrix_s& M) {
     return M.chunk ? AK_F64_32_CH : AK_F64_32;
   }
   if (small) return AK_SMALL;
+  if (M.md.m == 2147483647u) return AK_M31;
   return M.chunk ? AK_BIG_CH : AK_BIG;
+}
+
+// Integer class of the sequence, whatever the product path of the matrix. The
+// projection U^T W adds products of two residues over many rows, so for m >
+// 65536 it always needs the reductions of the chunked class (or the folding
+// class of 2^31 - 1), even where no matrix row does.
+static int seq_kind(const ffx_matrix_s& M) {
+  if (M.md.small()) return AK_SMALL;
+  if (M.md.m == 2147483647u) return AK_M31;
+  return AK_BIG_CH;
 }
 
 int matrix_arith_kind(const ffx_matrix_s& M) { return arith_kind(M); }
@@ -402,7 +413,7 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
         fail(FFX_ENOMEM, "sequence workspace allocation failed");
       }
     const int batch = L >= 128 ? 64 : 0;
-    hipError_t e = launch_sequence(A->md.small(), A->chunk, E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
+    hipError_t e = launch_sequence(seq_kind(*A), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
                                    Wlast, ws[0], ws[1], (uint64_t*)ws[2], (uint64_t*)ws[3], (int64_t*)ws[4], batch, st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
     FFX_HIP(e);

@@ -103,6 +103,7 @@ static hipError_t batch_launch(int ak, ffx_dtype dt, const DevMat* mats, const B
     case AK_SMALL: go(ArSmall{}); break;
     case AK_BIG: go(ArBig<false>{}); break;
     case AK_BIG_CH: go(ArBig<true>{}); break;
+    case AK_M31: go(ArM31{}); break;
     case AK_F64_16: go(ArF64<uint16_t, false>{}); break;
     case AK_F64_16_CH: go(ArF64<uint16_t, true>{}); break;
     case AK_F64_32: go(ArF64<uint32_t, false>{}); break;

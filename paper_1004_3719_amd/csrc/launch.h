@@ -7,13 +7,15 @@ namespace ffx {
 
 // Accumulator classes (see tiles.h): integer for m <= 65536; 64-bit integer
 // for larger m, with or without reductions inside a row; exact doubles with
-// 16- or 32-bit stored values, with or without reductions inside a row.
-enum ArithKind { AK_SMALL = 0, AK_BIG, AK_BIG_CH, AK_F64_16, AK_F64_16_CH, AK_F64_32, AK_F64_32_CH, AK_COUNT };
+// 16- or 32-bit stored values, with or without reductions inside a row; the
+// folding integer class of m = 2^31 - 1.
+enum ArithKind { AK_SMALL = 0, AK_BIG, AK_BIG_CH, AK_F64_16, AK_F64_16_CH, AK_F64_32, AK_F64_32_CH, AK_M31, AK_COUNT };
 
 hipError_t launch_tiles_small(const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
                               int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
                               uint32_t nblocks);
-hipError_t launch_tiles_big(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx,
+// ak: AK_BIG, AK_BIG_CH or AK_M31
+hipError_t launch_tiles_big(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx,
                             void* Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st,
                             uint32_t nblocks);
 hipError_t launch_tiles_f64(bool v16, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X,
@@ -27,8 +29,9 @@ inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype d
                                const uint16_t* x16 = nullptr, uint32_t nb = 0) {
   switch (ak) {
     case AK_SMALL: return launch_tiles_small(A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
-    case AK_BIG: return launch_tiles_big(false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nb);
-    case AK_BIG_CH: return launch_tiles_big(true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nb);
+    case AK_BIG:
+    case AK_BIG_CH:
+    case AK_M31: return launch_tiles_big(ak, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nb);
     case AK_F64_16: return launch_tiles_f64(true, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
     case AK_F64_16_CH: return launch_tiles_f64(true, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
     case AK_F64_32: return launch_tiles_f64(false, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
@@ -43,7 +46,8 @@ hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* 
 // null. Workspace: w0, w1 (n x s each), p0, p1 ((4 * ntiles + 64) * s * s uint64 each),
 // counter (one int64). Steps are replayed from a hipGraph in batches of
 // `batch` iterations (0: no graph).
-hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+// ak: an integer class (AK_SMALL, AK_BIG, AK_BIG_CH or AK_M31).
+hipError_t launch_sequence(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
                            void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st);
 

@@ -340,7 +340,7 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   return hipGetLastError();
 }
 
-hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+hipError_t launch_sequence(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
                            void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st) {
   SeqArgs q;
@@ -362,16 +362,17 @@ hipError_t launch_sequence(bool small, bool chunk, const DevMat& A, int64_t mte,
   q.s = s;
   q.last_w = Wlast ? 1 : 0;
   q.Wlast = Wlast;
-  if (small) {
-    if (dt == FFX_I32) return seq_go<ArSmall, int32_t>(A, mte, q, batch, st);
-    return seq_go<ArSmall, int64_t>(A, mte, q, batch, st);
+  auto go = [&](auto ar) -> hipError_t {
+    using AR = decltype(ar);
+    if (dt == FFX_I32) return seq_go<AR, int32_t>(A, mte, q, batch, st);
+    return seq_go<AR, int64_t>(A, mte, q, batch, st);
+  };
+  switch (ak) {
+    case AK_SMALL: return go(ArSmall{});
+    case AK_M31: return go(ArM31{});
+    case AK_BIG_CH: return go(ArBig<true>{});
+    default: return go(ArBig<false>{});
   }
-  if (chunk) {
-    if (dt == FFX_I32) return seq_go<ArBig<true>, int32_t>(A, mte, q, batch, st);
-    return seq_go<ArBig<true>, int64_t>(A, mte, q, batch, st);
-  }
-  if (dt == FFX_I32) return seq_go<ArBig<false>, int32_t>(A, mte, q, batch, st);
-  return seq_go<ArBig<false>, int64_t>(A, mte, q, batch, st);
 }
 
 template <typename Tv>

@@ -59,6 +59,26 @@ struct ArBig {
   __device__ static inline uint32_t reduce(Acc a, const DevMat& A) { return mod_u64(a, A.m, A.mu); }
   __device__ static inline Acc from_residue(uint32_t r) { return r; }
 };
+// m = 2^31 - 1: since 2^31 = 1 (mod m), a product below 2^62 folds below
+// 2^32 with one shift and one add, so a row needs no reduction inside it (a
+// row of at most 2^30 + 64 folded terms stays below 2^63).
+struct ArM31 {
+  using ValT = uint32_t;
+  using Acc = uint64_t;
+  using Prod = uint64_t;
+  static constexpr bool CHUNK = false;
+  static constexpr uint64_t M = 0x7FFFFFFFull;
+  __device__ static inline Prod mul(uint32_t v, uint32_t x) {
+    uint64_t p = (uint64_t)v * x;
+    return (p & M) + (p >> 31);
+  }
+  __device__ static inline uint32_t reduce(Acc a, const DevMat&) {
+    a = (a & M) + (a >> 31);  // below 2^32 + 2^31 for a < 2^63
+    a = (a & M) + (a >> 31);  // at most M + 2
+    return (uint32_t)(a >= M ? a - M : a);
+  }
+  __device__ static inline Acc from_residue(uint32_t r) { return r; }
+};
 // exact doubles: integers up to 2^53 add exactly.
 template <typename V, bool CH>
 struct ArF64 {

@@ -225,6 +225,27 @@ def test_sequence_prefix_full_size(dev, orc, ffx):
     assert np.array_equal(S2, orc.sequence(A, U, W6, 4))
 
 
+@pytest.mark.parametrize("m", [2**31 - 1, 2**31 - 19, 3_000_017])
+@pytest.mark.parametrize("s", [8, 16])
+def test_sequence_projection_bound(dev, orc, ffx, m, s):
+    """Rows of at most two entries (no row needs a reduction) but every value, U and V entry is
+    m-1: the projection U^T W sums thousands of largest-size products and must reduce itself."""
+    n = 3000
+    rng = np.random.default_rng(31)
+    lens = rng.integers(0, 3, n)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]).astype(np.int32)
+    A = synth.Csr(n, n, rp, cols, np.full(int(lens.sum()), -1, np.int64), m=m)
+    U = np.full((n, s), m - 1, np.int64)
+    V = np.full((n, s), m - 1, np.int64)
+    note("sequence projection bound", m, s)
+    for fmt in ("STREAM", "SELL"):
+        M = ffx.from_synth(A, fixed_format=fmt)
+        S = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), 5).cpu().numpy()
+        assert np.array_equal(S, orc.sequence(A, U, V, 5)), fmt
+
+
 # ---------------------------------------------------------- edge cases -----
 def test_degenerate_shapes(dev, orc, ffx):
     note("degenerate shapes")
