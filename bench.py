@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "exact nnz·vec/s (bit-exact) + HBM GB/s % peak; learned/batched vs plain"
 UNIT = "nnz·vec/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "launch.h"]  # the one-vector product kernel
+KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "launch.h"]  # the one-vector product kernels
 
 
 def log(*a):
@@ -85,6 +85,44 @@ def event_pairs(n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
 
+def copy_calibration(mib):
+    """A plain elementwise copy (mib MiB read, mib MiB written), three times: the reference
+    kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    src = torch.ones(mib * 2**18, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.add(src, 1, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def pmc_summary(fetch_csv, write_csv, mib, out_path, command):
+    """HBM bytes per product launch from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB
+    per dispatch), each scaled by what the same counter reads for the calibration copy."""
+    import csv
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        with open(path) as f:
+            rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
+        copy = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
+        copy = [v for v in copy if v > 0.5 * mib * 1024]
+        tiles = [float(r["Counter_Value"]) for r in rows if "k_tiles" in r["Kernel_Name"]]
+        u16 = [float(r["Counter_Value"]) for r in rows if "k_to_u16" in r["Kernel_Name"]]
+        if not copy or not tiles:
+            raise SystemExit("%s: no calibration copy or product dispatch in %s" % (counter, path))
+        scale = mib * 1024 / float(np.mean(copy))
+        res[counter] = {"copy_kib": round(float(np.mean(copy)), 1), "scale": round(scale, 4),
+                        "k_tiles_kib": round(float(np.mean(tiles)), 1),
+                        "k_to_u16_kib": round(float(np.mean(u16)), 1) if u16 else 0.0, "dispatches": len(tiles)}
+    bpl = sum((v["k_tiles_kib"] + v["k_to_u16_kib"]) * 1024 * v["scale"] for v in res.values())
+    out = {"kernel": "k_to_u16 + k_tiles, one product of the 2,000,000-row power-law matrix",
+           "kernel_hash": kernel_hash(), "counters": res, "bytes_per_launch": int(round(bpl)), "command": command}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 # --------------------------------------------------------------------- c2 / c1
 def bench_spmv(args, big=True):
     import torch
@@ -109,6 +147,8 @@ def bench_spmv(args, big=True):
     x = torch.from_numpy(x_np.astype(np.int32)).to(dev)
     y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    if args.copy_mib:
+        copy_calibration(args.copy_mib)
     for _ in range(args.warmup):
         M.spmv(x, y=y)
     torch.cuda.synchronize()
@@ -140,7 +180,8 @@ def bench_spmv(args, big=True):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counters_traffic("spmv_powerlaw_2M_counters.json" if big else "none", khash),
-                "kernel": "k_tiles (one-vector tiles)", "kernel_ms": round(kernel_ms, 5),
+                "kernel": "k_to_u16 + k_tiles (the product's launches)" if m <= 65536 and A.ncols * 4 > 2**20 else "k_tiles",
+                "kernel_ms": round(kernel_ms, 5),
                 "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows)}
     cpu = None
     if not args.no_cpu_baseline:
@@ -197,8 +238,10 @@ def bench_sequence(args):
     if not args.no_cpu_baseline:
         import oracle
         orc = oracle.get()
-        Lc, t_cpu = 0, 0.0
-        Lc = 2
+        t1 = time.perf_counter()
+        orc.sequence(A, U, V, 2)  # calibrates the sample length
+        per = (time.perf_counter() - t1) / 2
+        Lc = int(min(L, max(2, args.cpu_seconds / per)))
         t1 = time.perf_counter()
         So = orc.sequence(A, U, V, Lc)
         t_cpu = time.perf_counter() - t1
@@ -227,7 +270,7 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     count = args.batch_count
     t0 = time.time()
-    mats, Ms, Xs, Ys, S, work = [], [], [], [], [], 0
+    mats, Ms, Xs, Ys, S, work, b_alg = [], [], [], [], [], 0, 0
     for k in range(count):
         A = synth.c4_matrix(k)
         Ms.append(Matrix.from_synth(A))
@@ -235,7 +278,8 @@ def bench_batch(args):
         Ys.append(torch.empty((A.nrows, A.s), dtype=torch.int32, device=dev))
         S.append(A.s)
         work += A.nnz * A.s
-        mats.append(A if k < 8 else None)  # keep a few for the exactness check
+        b_alg += algorithmic_bytes(A, A.m, 4, A.s)
+        mats.append(A if k < 64 else None)  # kept for the CPU baseline and the exactness check
     log("built %d matrices in %.1fs, sum nnz*s = %.4g" % (count, time.time() - t0, work))
 
     def ev_time(f, reps):
@@ -254,6 +298,10 @@ def bench_batch(args):
             M.spmm(X, Y=Y)
 
     t_per = ev_time(per_matrix, args.steps)
+    # the same launches without host gaps: each matrix timed alone on the GPU, summed
+    t_per_gpu = 0.0
+    for M, X, Y in zip(Ms, Xs, Ys):
+        t_per_gpu += ev_time(lambda: M.spmm(X, Y=Y), 3)
     B = Batch(Ms, S)
     t_default = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
     best = B.tune(Xs, Ys, reps=3)
@@ -264,22 +312,27 @@ def bench_batch(args):
         orc = oracle.get()
         t_cpu, w_cpu, exact = 0.0, 0, True
         for k, A in enumerate(mats):
-            if A is None:
-                continue
+            if A is None or (t_cpu >= args.cpu_seconds and k >= 8):
+                break
             t1 = time.perf_counter()
             want = orc.spmm(A, synth.c4_rhs(k, A))
             t_cpu += time.perf_counter() - t1
             w_cpu += A.nnz * A.s
             exact = exact and bool(np.array_equal(Ys[k].cpu().numpy(), want))
         cpu = {"value": round(w_cpu / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
-               "sample": "the first 8 matrices of the batch (single thread)", "seconds": round(t_cpu, 2),
-               "gpu_result_bit_exact": exact}
+               "sample": "the first %d matrices of the batch, all right-hand sides (single thread)" % (k + 1),
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
     config = {"workload": "256 uneven matrices mod 65521, n log-uniform [2000, 500000], 3..60 nnz/row, "
                           "uniform/banded/block-diagonal, 70% +-1, 1..16 int32 right-hand sides",
               "count": count, "sum_nnz_times_s": work, "tuned": best}
-    extra = {"per_matrix_ms": round(t_per, 4), "batch_untuned_ms": round(t_default, 4),
-             "batch_speedup_vs_per_matrix": round(t_per / t_batch, 3)}
-    line(work / (t_batch * 1e-3), t_batch, args, "int64", config, None, cpu, extra)
+    extra = {"per_matrix_ms": round(t_per, 4), "per_matrix_gpu_sum_ms": round(t_per_gpu, 4),
+             "batch_untuned_ms": round(t_default, 4), "batch_speedup_vs_per_matrix": round(t_per / t_batch, 3),
+             "batch_speedup_vs_per_matrix_gpu_sum": round(t_per_gpu / t_batch, 3)}
+    achieved = b_alg / (t_batch * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch (persistent)",
+                "kernel_ms": round(t_batch, 5), "algorithmic_bytes": int(b_alg)}
+    line(work / (t_batch * 1e-3), t_batch, args, "int64", config, roofline, cpu, extra)
 
 
 # ---------------------------------------------------------------------- c5
@@ -363,7 +416,16 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--model-out", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
+    ap.add_argument("--copy-mib", type=int, default=0, help="run a calibration copy of this size first (counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of two rocprofv3 --pmc runs and exit (no GPU)")
+    ap.add_argument("--pmc-mib", type=int, default=512)
+    ap.add_argument("--pmc-command", default="")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_mib,
+                    os.path.join(ROOT, "profiles", "spmv_powerlaw_2M_counters.json"), args.pmc_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)

@@ -57,6 +57,10 @@ static int arith_kind(const ffx_matrix_s& M) {
 // projection U^T W adds products of two residues over many rows, so for m >
 // 65536 it always needs the reductions of the chunked class (or the folding
 // class of 2^31 - 1), even where no matrix row does.
+static bool only_sell(const Encoded& E) {
+  return E.format_blocks[FFX_FMT_STREAM] == 0 && E.format_blocks[FFX_FMT_BAND_STREAM] == 0;
+}
+
 static int seq_kind(const ffx_matrix_s& M) {
   if (M.md.small()) return AK_SMALL;
   if (M.md.m == 2147483647u) return AK_M31;
@@ -413,7 +417,7 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
         fail(FFX_ENOMEM, "sequence workspace allocation failed");
       }
     const int batch = L >= 128 ? 64 : 0;
-    hipError_t e = launch_sequence(seq_kind(*A), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
+    hipError_t e = launch_sequence(seq_kind(*A), only_sell(E), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
                                    Wlast, ws[0], ws[1], (uint64_t*)ws[2], (uint64_t*)ws[3], (int64_t*)ws[4], batch, st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
     FFX_HIP(e);

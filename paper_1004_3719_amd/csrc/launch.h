@@ -46,8 +46,9 @@ hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* 
 // null. Workspace: w0, w1 (n x s each), p0, p1 ((4 * ntiles + 64) * s * s uint64 each),
 // counter (one int64). Steps are replayed from a hipGraph in batches of
 // `batch` iterations (0: no graph).
-// ak: an integer class (AK_SMALL, AK_BIG, AK_BIG_CH or AK_M31).
-hipError_t launch_sequence(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+// ak: an integer class (AK_SMALL, AK_BIG, AK_BIG_CH or AK_M31); only_sell: the
+// matrix has SELL tiles only.
+hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
                            void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st);
 

@@ -439,7 +439,8 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   size_t total = 0;
   add_part<Tile>(offs, total, H.tiles.size());
   add_part<uint32_t>(offs, total, H.ent.size());
-  size_t o_val = total; offs.push_back(o_val); total += (H.val.size() * vb + 255) / 256 * 256;
+  // 16 spare bytes: a lane reads its values with one 12- or 16-byte load
+  size_t o_val = total; offs.push_back(o_val); total += (H.val.size() * vb + 16 + 255) / 256 * 256;
   add_part<uint32_t>(offs, total, H.choff.size());
   add_part<uint32_t>(offs, total, H.rowp.size());
   add_part<uint32_t>(offs, total, H.perm.size());

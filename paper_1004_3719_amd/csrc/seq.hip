@@ -90,7 +90,7 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
   constexpr int RPW = WAVE / S;
   constexpr int NW = TILE_THREADS / WAVE;
   constexpr int PPW = (S + NW - 1) / NW;  // passes per wave
-  constexpr int UC = 4;
+  constexpr int UC = PPW >= 4 ? 4 : 8;  // slice columns loaded together
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t comp = lane % S, sub = lane / S;
   const bool cok = (int)comp < s;
@@ -135,20 +135,26 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
       uint64_t gm = __ballot(tag == TAG_GEN);
       v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
     }
+    // every gather of the UC columns is issued before the first term is added
+    // (columns past the width hold padding words and add nothing)
+    uint32_t xv[UC][PPW];
 #pragma unroll
-    for (int u = 0; u < UC; ++u) {
-      if (j0 + u >= width) break;
-      uint32_t xv[PPW], wp[PPW], vp[PPW];
+    for (int u = 0; u < UC; ++u)
 #pragma unroll
       for (int q = 0; q < PPW; ++q) {
         int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
-        wp[q] = (uint32_t)__shfl((int)w[u], src);
-        vp[q] = (uint32_t)__shfl((int)v[u], src);
-        uint32_t tag = wp[q] >> TAG_SHIFT;
-        xv[q] = (tag != TAG_PAD && cok && pok[q]) ? (uint32_t)X[(int64_t)(wp[q] & COL_MASK) * ldx + comp] : 0u;
+        uint32_t wp = (uint32_t)__shfl((int)w[u], src);
+        xv[u][q] = ((wp >> TAG_SHIFT) != TAG_PAD && cok && pok[q]) ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp]
+                                                                     : 0u;
       }
 #pragma unroll
-      for (int q = 0; q < PPW; ++q) acc.a[q] += term<AR>(wp[q] >> TAG_SHIFT, vp[q], xv[q], A.m);
+    for (int u = 0; u < UC; ++u) {
+#pragma unroll
+      for (int q = 0; q < PPW; ++q) {
+        int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
+        uint32_t wp = (uint32_t)__shfl((int)w[u], src), vp = (uint32_t)__shfl((int)v[u], src);
+        acc.a[q] += term<AR>(wp >> TAG_SHIFT, vp, xv[u][q], A.m);
+      }
       acc.tick(A);
     }
   }
@@ -229,7 +235,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_first(DevMat A, SeqArgs q)
 // turns the sums of iteration i-1 into S_{i-1}.
 constexpr uint32_t NMID = 64;
 
-template <class AR, typename Tv, int S>
+// ONLY_SELL: the matrix has SELL tiles only, and the kernel is built without
+// the STREAM/LONG path, whose registers would otherwise set the occupancy.
+template <class AR, typename Tv, int S, bool ONLY_SELL>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int64_t i = *q.base + j;
@@ -263,16 +271,18 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
                                         (uint64_t*)lds);
     return;
   }
-  if (slice != 0) {  // idle slice of a STREAM/LONG tile: an empty partial
-    if (!last && threadIdx.x < ss) out[threadIdx.x] = 0;
-    return;
+  if constexpr (!ONLY_SELL) {
+    if (slice != 0) {  // idle slice of a STREAM/LONG tile: an empty partial
+      if (!last && threadIdx.x < ss) out[threadIdx.x] = 0;
+      return;
+    }
+    if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tv, Tv, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+    else stream_tile_s<AR, Tv, Tv, S>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+    if (last) return;  // W_L only: no partials needed
+    // the projection reads back only rows this workgroup wrote: a workgroup barrier orders them
+    __syncthreads();
+    tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, Wout, s, s, (uint64_t*)lds, out);
   }
-  if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tv, Tv, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
-  else stream_tile_s<AR, Tv, Tv, S>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
-  if (last) return;  // W_L only: no partials needed
-  // the projection reads back only rows this workgroup wrote: a workgroup barrier orders them
-  __syncthreads();
-  tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, Wout, s, s, (uint64_t*)lds, out);
 }
 
 // S_{L-1} from the sums of the last iteration.
@@ -290,7 +300,7 @@ __global__ void k_seq_counter(int64_t* base, int64_t add, int set) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *base = set ? add : *base + add;
 }
 
-template <class AR, typename Tv>
+template <class AR, typename Tv, bool ONLY_SELL>
 static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int batch, hipStream_t user) {
   const int s = q.s;
   const int S = s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;  // the step always runs the multi-vector tiles
@@ -300,10 +310,10 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   auto step = [&](hipStream_t st, int32_t j) {
     dim3 g(A.ntiles * SELL_SLICES + NMID + 1), b(TILE_THREADS);
     switch (S) {
-      case 2: hipLaunchKernelGGL((k_seq_step<AR, Tv, 2>), g, b, lds, st, A, q, j); break;
-      case 4: hipLaunchKernelGGL((k_seq_step<AR, Tv, 4>), g, b, lds, st, A, q, j); break;
-      case 8: hipLaunchKernelGGL((k_seq_step<AR, Tv, 8>), g, b, lds, st, A, q, j); break;
-      default: hipLaunchKernelGGL((k_seq_step<AR, Tv, 16>), g, b, lds, st, A, q, j); break;
+      case 2: hipLaunchKernelGGL((k_seq_step<AR, Tv, 2, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 4: hipLaunchKernelGGL((k_seq_step<AR, Tv, 4, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 8: hipLaunchKernelGGL((k_seq_step<AR, Tv, 8, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      default: hipLaunchKernelGGL((k_seq_step<AR, Tv, 16, ONLY_SELL>), g, b, lds, st, A, q, j); break;
     }
   };
   hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, user, base, (int64_t)0, 1);
@@ -340,7 +350,7 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   return hipGetLastError();
 }
 
-hipError_t launch_sequence(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
+hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
                            void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st) {
   SeqArgs q;
@@ -364,8 +374,12 @@ hipError_t launch_sequence(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, c
   q.Wlast = Wlast;
   auto go = [&](auto ar) -> hipError_t {
     using AR = decltype(ar);
-    if (dt == FFX_I32) return seq_go<AR, int32_t>(A, mte, q, batch, st);
-    return seq_go<AR, int64_t>(A, mte, q, batch, st);
+    if (only_sell) {
+      if (dt == FFX_I32) return seq_go<AR, int32_t, true>(A, mte, q, batch, st);
+      return seq_go<AR, int64_t, true>(A, mte, q, batch, st);
+    }
+    if (dt == FFX_I32) return seq_go<AR, int32_t, false>(A, mte, q, batch, st);
+    return seq_go<AR, int64_t, false>(A, mte, q, batch, st);
   };
   switch (ak) {
     case AK_SMALL: return go(ArSmall{});

@@ -164,11 +164,15 @@ __device__ inline void write_row(const DevMat& A, Tv* Y, int64_t ldy, uint32_t r
 // Adds the band terms of one row (diagonals d = first, first+step, ...). The
 // x address depends only on the row and the offset, never on the stored value
 // (absent entries hold 0), so all loads of a batch are issued together.
-constexpr int BAND_BATCH = 8;
+// Diagonals per batch: 16 gathers in flight per lane whatever S (more would
+// only cost registers).
+template <int S>
+constexpr int band_batch() { return S >= 16 ? 1 : 16 / S > 8 ? 8 : 16 / S; }
 template <class AR, typename Tx, int S>
 __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>& acc, uint32_t row, uint32_t slot,
                                   uint32_t rows_in_tile, uint32_t first, uint32_t step, const Tx* X, int64_t ldx,
                                   int s) {
+  constexpr int BAND_BATCH = band_batch<S>();
   const uint32_t nd = tile_nd(T.kind);
   for (uint32_t d0 = first; d0 < nd; d0 += BAND_BATCH * step) {
     uint32_t v[BAND_BATCH];
@@ -270,15 +274,45 @@ struct Chunk4 {
   __device__ inline void load_gathers(const DevMat& A, const Tx* X, int64_t ldx, int s) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t idx = vo[u];
+      uint32_t idx = vo[u], g = 0;
 #pragma unroll
-      for (int k = 0; k < WIDE; ++k) idx += lanes_below(__ballot((w[u][k] >> TAG_SHIFT) == TAG_GEN));
+      for (int k = 0; k < WIDE; ++k) {
+        bool gen = (w[u][k] >> TAG_SHIFT) == TAG_GEN;
+        idx += lanes_below(__ballot(gen));
+        g += gen ? 1u : 0u;
+      }
+      // the lane's general values are consecutive from idx: one 12- or 16-byte load
+      uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, j = 0;
+      if constexpr (sizeof(typename AR::ValT) == 2) {
+        if (g) {
+          const uint32_t* p = (const uint32_t*)A.val + (idx >> 1);
+          q0 = __builtin_nontemporal_load(p);
+          q1 = __builtin_nontemporal_load(p + 1);
+          q2 = __builtin_nontemporal_load(p + 2);
+        }
+        j = idx & 1u;
+      } else {
+        if (g) {
+          const uint32_t* p = (const uint32_t*)A.val + idx;
+          q0 = __builtin_nontemporal_load(p);
+          q1 = __builtin_nontemporal_load(p + 1);
+          q2 = __builtin_nontemporal_load(p + 2);
+          q3 = __builtin_nontemporal_load(p + 3);
+        }
+      }
 #pragma unroll
       for (int k = 0; k < WIDE; ++k) {
         uint32_t tag = w[u][k] >> TAG_SHIFT;
         bool gen = tag == TAG_GEN;
-        v[u][k] = gen ? ldval<typename AR::ValT>(A.val, idx) : 0u;
-        idx += gen ? 1u : 0u;
+        uint32_t val;
+        if constexpr (sizeof(typename AR::ValT) == 2) {
+          uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
+          val = (d >> ((j & 1u) * 16)) & 0xffffu;
+        } else {
+          val = j == 0 ? q0 : j == 1 ? q1 : j == 2 ? q2 : q3;
+        }
+        v[u][k] = gen ? val : 0u;
+        j += gen ? 1u : 0u;
         const Tx* xr = X + (int64_t)(w[u][k] & COL_MASK) * ldx;
 #pragma unroll
         for (int c = 0; c < S; ++c) xv[u][k][c] = (tag != TAG_PAD && c < s) ? (uint32_t)xr[c] : 0u;
@@ -341,8 +375,8 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
 template <class AR, typename Tx, typename Tv, int S>
 __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                     Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta) {
-  constexpr int RPW = WAVE / S;  // rows per pass; S passes cover the slice
-  constexpr int UC = 4;          // slice columns loaded together
+  constexpr int RPW = WAVE / S;            // rows per pass; S passes cover the slice
+  constexpr int UC = S >= 16 ? 1 : 16 / S;  // slice columns loaded together (16 gathers in flight)
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t nsl = T.ne;
   if (wave >= nsl) return;
@@ -386,20 +420,24 @@ __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __
       uint64_t gm = __ballot(tag == TAG_GEN);
       v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
     }
+    // every gather of the UC columns is issued before the first term is added
+    // (columns past the width hold padding words and add nothing)
+    uint32_t xv[UC][S];
+#pragma unroll
+    for (int u = 0; u < UC; ++u)
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        uint32_t wp = (uint32_t)__shfl((int)w[u], p * RPW + (int)sub);
+        xv[u][p] = ((wp >> TAG_SHIFT) != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp] : 0u;
+      }
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
-      if (j0 + u >= width) break;
-      uint32_t xv[S], wp[S], vp[S];
 #pragma unroll
       for (int p = 0; p < S; ++p) {
         int src = p * RPW + (int)sub;
-        wp[p] = (uint32_t)__shfl((int)w[u], src);
-        vp[p] = (uint32_t)__shfl((int)v[u], src);
-        uint32_t tag = wp[p] >> TAG_SHIFT;
-        xv[p] = (tag != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(wp[p] & COL_MASK) * ldx + comp] : 0u;
+        uint32_t wp = (uint32_t)__shfl((int)w[u], src), vp = (uint32_t)__shfl((int)v[u], src);
+        acc.a[p] += term<AR>(wp >> TAG_SHIFT, vp, xv[u][p], A.m);
       }
-#pragma unroll
-      for (int p = 0; p < S; ++p) acc.a[p] += term<AR>(wp[p] >> TAG_SHIFT, vp[p], xv[p], A.m);
       acc.tick(A);
     }
   }
@@ -604,13 +642,27 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* _
   LaneAcc<AR, S> acc;
   acc.init(A);
   band_terms<AR, Tx, S>(A, T, acc, row, tid, nr, 0, 1, X, ldx, s);
-  for (uint32_t k = kb; k < ke; ++k) {
-    uint32_t w = sw[k], tag = w >> TAG_SHIFT, v = sv[k];
-    const Tx* xr = X + (int64_t)(w & COL_MASK) * ldx;
+  // EU entries of the row at a time: their gathers are all issued before the
+  // first term is added (16 in flight per lane)
+  constexpr int EU = S >= 16 ? 1 : 16 / S;
+  for (uint32_t k0 = kb; k0 < ke; k0 += EU) {
+    uint32_t w[EU], xv[EU][S];
 #pragma unroll
-    for (int c = 0; c < S; ++c)
-      if (c < s) acc.a[c] += term<AR>(tag, v, (uint32_t)xr[c], A.m);
-    acc.tick(A);
+    for (int e = 0; e < EU; ++e) {
+      w[e] = k0 + e < ke ? sw[k0 + e] : PAD_WORD;
+      const Tx* xr = X + (int64_t)(w[e] & COL_MASK) * ldx;
+      const bool live = (w[e] >> TAG_SHIFT) != TAG_PAD;
+#pragma unroll
+      for (int c = 0; c < S; ++c) xv[e][c] = (live && c < s) ? (uint32_t)xr[c] : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < EU; ++e) {
+      const uint32_t tag = w[e] >> TAG_SHIFT, v = k0 + e < ke ? sv[k0 + e] : 0u;
+#pragma unroll
+      for (int c = 0; c < S; ++c)
+        if (c < s) acc.a[c] += term<AR>(tag, v, xv[e][c], A.m);
+      acc.tick(A);
+    }
   }
   uint32_t r[S];
 #pragma unroll
@@ -642,6 +694,37 @@ template <typename Tv>
 __global__ void k_to_u16(const Tv* __restrict__ x, int64_t ldx, uint16_t* __restrict__ out, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (uint16_t)x[i * ldx];
+}
+
+// Contiguous x with 16-byte alignment: eight residues per thread, read with
+// 16-byte loads and written with one 16-byte store.
+template <typename Tv>
+__global__ void k_to_u16_x8(const Tv* __restrict__ x, uint16_t* __restrict__ out, int64_t n) {
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, base = t * 8;
+  if (base + 8 <= n) {
+    constexpr int NV = (int)(8 * sizeof(Tv) / 16);  // 16-byte loads per thread
+    constexpr int PER = 16 / (int)sizeof(Tv);       // residues per load
+    uint32_t r[8];
+    const u32x4_t* src = (const u32x4_t*)(x + base);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      u32x4_t q = __builtin_nontemporal_load(src + k);
+      if constexpr (PER == 4) {
+        r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
+      } else {  // two int64 residues: their low words
+        r[2 * k] = q.x; r[2 * k + 1] = q.z;
+      }
+    }
+    u32x4_t o;
+    o.x = (r[0] & 0xffffu) | (r[1] << 16);
+    o.y = (r[2] & 0xffffu) | (r[3] << 16);
+    o.z = (r[4] & 0xffffu) | (r[5] << 16);
+    o.w = (r[6] & 0xffffu) | (r[7] << 16);
+    *(u32x4_t*)(out + base) = o;
+  } else {
+    for (int64_t i = base; i < n; ++i) out[i] = (uint16_t)x[i];
+  }
 }
 
 // Dynamic LDS of one launch.
@@ -705,6 +788,12 @@ hipError_t launch_tiles_t(const DevMat& A, int64_t max_tile_entries, const void*
 template <typename Tv>
 hipError_t launch_to_u16(const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if (ldx == 1 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)out & 15) == 0) {
+    int64_t threads = (n + 7) / 8;
+    hipLaunchKernelGGL((k_to_u16_x8<Tv>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, (const Tv*)X,
+                       out, n);
+    return hipGetLastError();
+  }
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
   hipLaunchKernelGGL((k_to_u16<Tv>), dim3(blocks), dim3(256), 0, st, (const Tv*)X, ldx, out, n);
   return hipGetLastError();
