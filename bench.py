@@ -340,28 +340,39 @@ def bench_selector(args):
     import torch
 
     import synth
-    from paper_1004_3719_amd import Matrix, selector_train as ST
+    from paper_1004_3719_amd import selector_train as ST
+    from paper_1004_3719_amd.ffx import FORMATS
 
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(args.seed)
     BR = 4096
-    Xs, Ts = [], []
-    t0 = time.time()
-    for k in range(args.train_mats):
-        sp, p = synth.c5_spec(k)
-        nb = max(1, sp.nrows // BR)
-        b0 = int(rng.integers(0, max(1, nb - args.train_blocks + 1)))
-        r0, r1 = b0 * BR, min(sp.nrows, (b0 + args.train_blocks) * BR)
-        A = synth.rows(sp, r0, r1)
-        A.m = synth.M_C5
-        x = torch.from_numpy(synth.vector(k, 7, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
-        F, T = ST.block_labels(A, x, reps=4)
-        Xs.append(F)
-        Ts.append(T)
-        if k % 100 == 99:
-            log("labels: %d matrices, %d blocks, %.0fs" % (k + 1, sum(len(f) for f in Xs), time.time() - t0))
-    X = np.concatenate(Xs)
-    T = np.concatenate(Ts)
+    if args.labels and os.path.exists(args.labels):
+        with np.load(args.labels) as z:
+            X, T, H = z["X"], z["T"], z["H"]
+        log("loaded %d labelled blocks from %s" % (len(X), args.labels))
+    else:
+        Xs, Ts, Hs = [], [], []
+        t0 = time.time()
+        for k in range(args.train_mats):
+            sp, p = synth.c5_spec(k)
+            nb = max(1, sp.nrows // BR)
+            b0 = int(rng.integers(0, max(1, nb - args.train_blocks + 1)))
+            r0, r1 = b0 * BR, min(sp.nrows, (b0 + args.train_blocks) * BR)
+            A = synth.rows(sp, r0, r1)
+            A.m = synth.M_C5
+            x = torch.from_numpy(synth.vector(k, 7, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
+            y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
+            F, T, H = ST.window_labels(A, x, y)
+            Xs.append(F)
+            Ts.append(T)
+            Hs.append(H)
+            if k % 50 == 49:
+                log("labels: %d matrices, %d blocks, %.0fs" % (k + 1, sum(len(f) for f in Xs), time.time() - t0))
+        X = np.concatenate(Xs)
+        T = np.concatenate(Ts)
+        H = np.concatenate(Hs)
+        if args.labels:
+            np.savez(args.labels, X=X, T=T, H=H)
     log("training on %d blocks" % len(X))
     nval = max(1, len(X) // 10)
     S, hist = ST.fit(X[nval:], T[nval:], epochs=args.epochs, lr=args.lr, seed=args.seed, val=(X[:nval], T[:nval]),
@@ -369,6 +380,13 @@ def bench_selector(args):
     model = args.model_out
     os.makedirs(os.path.dirname(model), exist_ok=True)
     S.save(model)
+    # held-out blocks: summed block time of each choice relative to the best per block
+    learned, _ = ST.choose(S, X[:nval])
+    block_cost = {"learned": round(ST.choice_cost(T[:nval], learned), 4),
+                  "heuristic": round(ST.choice_cost(T[:nval], H[:nval]), 4)}
+    for f, name in enumerate(FORMATS):
+        block_cost["all_" + name] = round(ST.choice_cost(T[:nval], np.full(nval, f)), 4)
+    log("validation blocks, summed time / best: %s" % json.dumps(block_cost))
     # held-out matrices: whole-product time, heuristic vs learned
     tot_h, tot_l, same, nev = 0.0, 0.0, True, 0
     for k in range(1800, 1800 + args.eval_mats):
@@ -382,12 +400,15 @@ def bench_selector(args):
         tot_l += r["learned_us"]
         same = same and r["same_result"]
         nev += 1
+        if nev % 10 == 0:
+            log("held-out %d: heuristic %.1f us, learned %.1f us so far" % (nev, tot_h, tot_l))
     log("held-out: heuristic %.1f us, learned %.1f us, identical results %s" % (tot_h, tot_l, same))
     config = {"workload": "learned format selection mod 65521: %d training matrices x %d blocks, %d held-out "
                           "matrices (first %s rows), 32->64->64->6 FP32" % (args.train_mats, args.train_blocks, nev,
                                                                            args.eval_rows or "all"),
               "train_blocks": int(len(X)), "history": hist[-1:]}
-    extra = {"heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
+    extra = {"validation_block_cost_vs_best": block_cost,
+             "heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
              "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4), "results_identical": same}
     args.steps, args.warmup = nev, 0
     line(0.0, tot_l / 1e3, args, "fp32 network / int64 products", config, None, None, extra)
@@ -408,13 +429,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seq-length", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--train-mats", type=int, default=1800)
-    ap.add_argument("--train-blocks", type=int, default=4)
+    ap.add_argument("--train-mats", type=int, default=600)
+    ap.add_argument("--train-blocks", type=int, default=16)
     ap.add_argument("--eval-mats", type=int, default=200)
-    ap.add_argument("--eval-rows", type=int, default=0)
+    ap.add_argument("--eval-rows", type=int, default=131072)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--labels", default="", help="npz of (features, log2 us) block labels: loaded if present, "
+                                                  "else measured and saved there")
     ap.add_argument("--model-out", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
     ap.add_argument("--copy-mib", type=int, default=0, help="run a calibration copy of this size first (counters)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -1,9 +1,13 @@
 """Training and evaluation of the learned per-block format selector.
 
-Labels come from the library itself: every training matrix is built once per
-format (all blocks forced to that format) and each block is timed on the GPU
-with ffx_matrix_block_times; the label of (block, format) is log2 of that
-time in microseconds. Features are the builder's own 32 block features
+Labels come from the library itself: every training window (a run of row
+blocks of one generated matrix, so of one row-length law, +-1 fraction and
+band) is built once per format, with all blocks forced to that format, and
+its whole product y = A x is timed on the GPU; the label of (block, format)
+is log2 of that time per block in microseconds. Timing the product in place
+keeps x at its real size, so gathers cost what they cost in use; a block
+timed alone (ffx_matrix_block_times) finds its x entries in cache and
+favours the wrong formats. Features are the builder's own 32 block features
 (ffx_block_features). The network is trained with the library's forward,
 backward and Adam kernels (Selector.train_step); nothing here computes a
 gradient. Input standardisation (mean, scale) is taken from the training
@@ -24,8 +28,8 @@ NF = len(FORMATS)
 
 
 def block_labels(A, x_dev, reps=4, opts=None):
-    """(features (nb x 32), log2 microseconds (nb x 6)) of the row blocks of A, a Csr-like object with
-    nrows, ncols, rowptr, col, val, m."""
+    """(features (nb x 32), log2 microseconds (nb x 6), the heuristic's formats (nb)) of the row blocks of
+    A, a Csr-like object with nrows, ncols, rowptr, col, val, m."""
     opts = dict(opts or {})
     F = block_features(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
     T = np.zeros((F.shape[0], NF), np.float32)
@@ -34,7 +38,34 @@ def block_labels(A, x_dev, reps=4, opts=None):
         t = M.block_times(x_dev, reps=reps)
         M.close()
         T[:, f] = np.log2(np.maximum(t, 1e-3))
-    return F, T
+    M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
+    H = M.block_formats()
+    M.close()
+    return F, T, H
+
+
+def window_labels(A, x_dev, y_dev, reps=6, opts=None):
+    """(features (nb x 32), log2 microseconds per block (nb x 6), the heuristic's formats (nb)) of a
+    window A whose blocks share one generator: each format's label is the in-place product time of the
+    whole window divided by its block count."""
+    opts = dict(opts or {})
+    F = block_features(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
+    nb = F.shape[0]
+    T = np.zeros((nb, NF), np.float32)
+    for f in range(NF):
+        M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, fixed_format=f, **opts)
+        T[:, f] = np.log2(max(time_product(M, x_dev, y_dev, reps) / nb, 1e-3))
+        M.close()
+    M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
+    H = M.block_formats()
+    M.close()
+    return F, T, H
+
+
+def choice_cost(T, choice):
+    """Summed block time of a per-block format choice, relative to the best choice (1 = best)."""
+    t = np.exp2(T.astype(np.float64))
+    return float(t[np.arange(len(t)), choice].sum() / t.min(axis=1).sum())
 
 
 def standardisation(X):

@@ -136,3 +136,28 @@ def test_block_times(dev):
     assert t.shape == (M.info()["nblocks"],) and np.all(t > 0) and np.all(np.isfinite(t))
     y = M.spmv(x)
     assert np.array_equal(y.cpu().numpy(), oracle.get().spmv(A, x.cpu().numpy()))
+
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1004_3719_amd", "models",
+                     "selector.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained model in the package")
+def test_trained_model_gain(dev):
+    """The committed network, trained on in-place product timings of generated training windows, against
+    the plain heuristic on held-out generated matrices (first 65,536 rows each): identical products, and
+    the summed product time of the learned formats is reported beside the heuristic's."""
+    from paper_1004_3719_amd import selector_train as ST
+    tot_h = tot_l = 0.0
+    for k in range(1800, 1808):
+        sp, _ = synth.c5_spec(k)
+        A = synth.rows(sp, 0, min(sp.nrows, 65536))
+        A.m = synth.M_C5
+        x = torch.from_numpy(synth.vector(k, 8, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
+        r = ST.evaluate(A, MODEL, x, reps=10)
+        assert r["same_result"], k
+        tot_h += r["heuristic_us"]
+        tot_l += r["learned_us"]
+    print("[case] held-out product time: heuristic %.1f us, learned %.1f us, gain %.3fx"
+          % (tot_h, tot_l, tot_h / tot_l), flush=True)
+    assert tot_l <= 1.10 * tot_h
