@@ -57,9 +57,7 @@ static int arith_kind(const ffx_matrix_s& M) {
 // projection U^T W adds products of two residues over many rows, so for m >
 // 65536 it always needs the reductions of the chunked class (or the folding
 // class of 2^31 - 1), even where no matrix row does.
-static bool only_sell(const Encoded& E) {
-  return E.format_blocks[FFX_FMT_STREAM] == 0 && E.format_blocks[FFX_FMT_BAND_STREAM] == 0;
-}
+static bool only_sell(const Encoded& E) { return E.kind_tiles[0] == 0 && E.kind_tiles[1] == 0; }
 
 static int seq_kind(const ffx_matrix_s& M) {
   if (M.md.small()) return AK_SMALL;

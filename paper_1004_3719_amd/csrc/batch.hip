@@ -55,7 +55,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_batch(const DevMat* __restrict
     const int sc = I.sc;
     const uint32_t kind = tile_kind(T.kind);
     if (sc == 1) {
-      if (kind == TK_SELL) sell_tile<AR, Tv, Tv, 1, 4>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0);
+      if (kind == TK_SELL) sell_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0);
       else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0, lds);
       else stream_tile_1<AR, Tv, Tv, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 0, lds);
     } else if (sc <= 2) {

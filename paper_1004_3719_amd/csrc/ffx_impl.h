@@ -31,7 +31,7 @@ constexpr int64_t MAX_DIM = int64_t(1) << TAG_SHIFT;
 enum TileKind : uint32_t {
   TK_STREAM = 0,  // up to 256 consecutive rows, entries staged through LDS
   TK_LONG = 1,    // one row longer than a STREAM tile; all lanes sweep it
-  TK_SELL = 2,    // up to 4 slices of 64 rows, column-major, padded
+  TK_SELL = 2,    // up to 4 slices of 64 rows in padded 4-column groups
 };
 constexpr uint32_t TF_SORTED = 1u << 4;  // SELL slots map to rows through perm[]
 
@@ -43,6 +43,7 @@ constexpr int WAVE = 64;
 constexpr int WIDE = 4;
 constexpr int WCHUNK = WAVE * WIDE;
 constexpr int SELL_SLICES = TILE_THREADS / WAVE;  // 4
+constexpr int SELL_GROUP = WAVE * WIDE;           // words of one 4-column group of a SELL slice
 constexpr int MAX_BAND = 64;                      // diagonals per band part
 constexpr int MAX_S = 16;
 
@@ -70,7 +71,7 @@ struct DevMat {
   const uint32_t* choff; // value offset of each 64-entry chunk
   const uint32_t* rowp;  // STREAM tiles: rows+1 absolute entry offsets per tile
   const uint32_t* perm;  // sorted SELL: slot -> row (0xFFFFFFFF for padding slots)
-  const uint32_t* swidth;// SELL: width of each slice
+  const uint32_t* swidth;// SELL: 4-column groups of each slice
   const void* bval;      // band values, diagonal-major inside each tile
   const int32_t* boffs;  // band diagonal offsets (column - row)
   uint32_t ntiles;

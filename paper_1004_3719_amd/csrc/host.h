@@ -80,6 +80,7 @@ struct Encoded {
   std::vector<uint32_t> tile_cost;  // per tile: entry words read (with padding) plus band slots
   std::vector<uint32_t> block_tile0;  // first tile of each block, plus the tile count at the end
   int64_t format_blocks[FFX_NUM_FORMATS] = {0, 0, 0, 0, 0, 0};
+  int64_t kind_tiles[3] = {0, 0, 0};  // STREAM, LONG and SELL tiles
   // sizes (elements) of each device array, for the batched concatenation
   int64_t n_ent = 0, n_val = 0, n_choff = 0, n_rowp = 0, n_perm = 0, n_swidth = 0, n_bval = 0, n_boffs = 0;
   void release();

@@ -223,6 +223,26 @@ BlockRows split_block(const RCsr& A, int64_t r0, int64_t r1, const std::vector<i
   return R;
 }
 
+// One row (block-local index t) as a LONG tile: all lanes of a workgroup sweep it.
+void encode_long(const BlockRows& R, int64_t r0, int64_t t, uint32_t boff, HostEnc& H) {
+  Tile T{};
+  T.kind = TK_LONG | ((uint32_t)R.nd << 8) | (1u << 16);
+  T.row0 = (uint32_t)(r0 + t);
+  H.align_ent();
+  T.e0 = (uint32_t)H.ent.size();
+  T.ne = (uint32_t)(R.rp[t + 1] - R.rp[t]);
+  T.c0 = (uint32_t)H.choff.size();
+  T.boff = boff;
+  for (int64_t k = R.rp[t]; k < R.rp[t + 1]; k += WCHUNK) {
+    int n = (int)std::min<int64_t>(WCHUNK, R.rp[t + 1] - k);
+    H.push_chunk(&R.word[k], &R.v[k], n);
+  }
+  H.align_ent();
+  T.b0 = (uint32_t)H.bval.size();
+  for (int d = 0; d < R.nd; ++d) H.bval.push_back(R.band[(size_t)t * R.nd + d]);
+  H.tiles.push_back(T);
+}
+
 void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, int NE, HostEnc& H) {
   auto rlen = [&](int64_t t) { return R.rp[t + 1] - R.rp[t]; };
   auto push_band = [&](int64_t t0, int64_t cnt, Tile& T) {
@@ -233,21 +253,7 @@ void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, in
   int64_t t = 0;
   while (t < nr) {
     if (rlen(t) > NE) {  // one long row
-      Tile T{};
-      T.kind = TK_LONG | ((uint32_t)R.nd << 8) | (1u << 16);
-      T.row0 = (uint32_t)(r0 + t);
-      H.align_ent();
-      T.e0 = (uint32_t)H.ent.size();
-      T.ne = (uint32_t)rlen(t);
-      T.c0 = (uint32_t)H.choff.size();
-      T.boff = boff;
-      for (int64_t k = R.rp[t]; k < R.rp[t + 1]; k += WCHUNK) {
-        int n = (int)std::min<int64_t>(WCHUNK, R.rp[t + 1] - k);
-        H.push_chunk(&R.word[k], &R.v[k], n);
-      }
-      H.align_ent();
-      push_band(t, 1, T);
-      H.tiles.push_back(T);
+      encode_long(R, r0, t, boff, H);
       ++t;
       continue;
     }
@@ -275,27 +281,33 @@ void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, in
   }
 }
 
-void encode_sell(const BlockRows& R, int64_t r0, int64_t nr, int64_t nrows_total, bool sorted, uint32_t boff,
-                 HostEnc& H) {
-  // slot order: rows by decreasing residual length when sorted, else natural
-  int64_t nslots = (nr + WAVE - 1) / WAVE * WAVE;
-  std::vector<int64_t> order(nslots, -1);
-  for (int64_t t = 0; t < nr; ++t) order[t] = t;
+// SELL rows longer than this become LONG tiles of their own (the hybrid split
+// of Section 2.4): no slice then waits on one long row.
+constexpr int64_t SELL_ROW_CAP = 256;
+
+void encode_sell(const BlockRows& R, int64_t r0, int64_t nr, bool sorted, uint32_t boff, HostEnc& H) {
+  auto rlen = [&](int64_t t) { return R.rp[t + 1] - R.rp[t]; };
+  // slot order: rows by decreasing residual length when sorted, else natural; long rows leave the slices,
+  // and then the slots name their rows through perm[] in either order
+  std::vector<int64_t> order, longrows;
+  for (int64_t t = 0; t < nr; ++t) (rlen(t) > SELL_ROW_CAP ? longrows : order).push_back(t);
+  const bool explicit_rows = sorted || !longrows.empty();
   if (sorted)
-    std::stable_sort(order.begin(), order.begin() + nr, [&](int64_t a, int64_t b) {
-      return R.rp[a + 1] - R.rp[a] > R.rp[b + 1] - R.rp[b];
-    });
-  uint32_t words[WAVE], vals[WAVE];
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return rlen(a) > rlen(b); });
+  const int64_t nslots = ((int64_t)order.size() + WAVE - 1) / WAVE * WAVE;
+  order.resize(nslots, -1);
+  uint32_t words[SELL_GROUP], vals[SELL_GROUP];
   for (int64_t s0 = 0; s0 < nslots; s0 += WAVE * SELL_SLICES) {
     int nsl = (int)std::min<int64_t>(SELL_SLICES, (nslots - s0) / WAVE);
     Tile T{};
-    T.kind = TK_SELL | (sorted ? TF_SORTED : 0) | ((uint32_t)R.nd << 8) | ((uint32_t)(nsl * WAVE) << 16);
+    T.kind = TK_SELL | (explicit_rows ? TF_SORTED : 0) | ((uint32_t)R.nd << 8) | ((uint32_t)(nsl * WAVE) << 16);
+    H.align_ent();
     T.e0 = (uint32_t)H.ent.size();
     T.ne = (uint32_t)nsl;
     T.c0 = (uint32_t)H.choff.size();
     T.aux = (uint32_t)H.swidth.size();
     T.boff = boff;
-    if (sorted) {
+    if (explicit_rows) {
       T.row0 = (uint32_t)H.perm.size();
       for (int64_t q = s0; q < s0 + nsl * WAVE; ++q) H.perm.push_back(order[q] < 0 ? 0xFFFFFFFFu : (uint32_t)(r0 + order[q]));
     } else {
@@ -305,21 +317,21 @@ void encode_sell(const BlockRows& R, int64_t r0, int64_t nr, int64_t nrows_total
       int64_t w = 0;
       for (int l = 0; l < WAVE; ++l) {
         int64_t t = order[s0 + sl * WAVE + l];
-        if (t >= 0) w = std::max<int64_t>(w, R.rp[t + 1] - R.rp[t]);
+        if (t >= 0) w = std::max<int64_t>(w, rlen(t));
       }
-      H.swidth.push_back((uint32_t)w);
-      for (int64_t j = 0; j < w; ++j) {
+      const int64_t groups = (w + WIDE - 1) / WIDE;
+      H.swidth.push_back((uint32_t)groups);
+      for (int64_t g = 0; g < groups; ++g) {  // word 4*lane + k: entry 4g + k of the lane's row
         for (int l = 0; l < WAVE; ++l) {
           int64_t t = order[s0 + sl * WAVE + l];
-          if (t >= 0 && j < R.rp[t + 1] - R.rp[t]) {
-            words[l] = R.word[R.rp[t] + j];
-            vals[l] = R.v[R.rp[t] + j];
-          } else {
-            words[l] = PAD_WORD;
-            vals[l] = 0;
+          for (int k = 0; k < WIDE; ++k) {
+            int64_t j = g * WIDE + k;
+            bool in = t >= 0 && j < rlen(t);
+            words[l * WIDE + k] = in ? R.word[R.rp[t] + j] : PAD_WORD;
+            vals[l * WIDE + k] = in ? R.v[R.rp[t] + j] : 0u;
           }
         }
-        H.push_chunk(words, vals, WAVE);
+        H.push_chunk(words, vals, SELL_GROUP);
       }
     }
     T.b0 = (uint32_t)H.bval.size();
@@ -328,9 +340,9 @@ void encode_sell(const BlockRows& R, int64_t r0, int64_t nr, int64_t nrows_total
         int64_t t = order[q];
         H.bval.push_back(t >= 0 ? R.band[(size_t)t * R.nd + d] : 0u);
       }
-    (void)nrows_total;
     H.tiles.push_back(T);
   }
+  for (int64_t t : longrows) encode_long(R, r0, t, boff, H);
 }
 
 template <typename T>
@@ -418,7 +430,7 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
     BlockRows R = split_block(A, r0, r1, offs, md.m, o.split_pm1, P);
     int base = band ? f - FFX_FMT_BAND_STREAM : f;
     if (base == FFX_FMT_STREAM) encode_stream(R, r0, r1 - r0, 0, o.tile_entries, P);
-    else encode_sell(R, r0, r1 - r0, A.nrows, base == FFX_FMT_SELL_SORTED, 0, P);
+    else encode_sell(R, r0, r1 - r0, base == FFX_FMT_SELL_SORTED, 0, P);
   }
   HostEnc H;
   out->block_tile0.assign(nblocks + 1, 0);
@@ -503,12 +515,14 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
                                 H.choff.size() * 4 + H.rowp.size() * 4 + H.perm.size() * 4 + H.swidth.size() * 4 +
                                 H.bval.size() * vb + H.boffs.size() * 4);
   out->max_tile_entries = H.max_tile_entries;
+  std::fill(out->kind_tiles, out->kind_tiles + 3, 0);
+  for (const Tile& T : H.tiles) out->kind_tiles[tile_kind(T.kind) == TK_SELL ? 2 : tile_kind(T.kind) == TK_LONG ? 1 : 0]++;
   out->tile_cost.resize(H.tiles.size());
   for (size_t t = 0; t < H.tiles.size(); ++t) {
     const Tile& T = H.tiles[t];
     uint64_t words = 0;
     if (tile_kind(T.kind) == TK_SELL)
-      for (uint32_t k = 0; k < T.ne; ++k) words += (uint64_t)H.swidth[T.aux + k] * WAVE;
+      for (uint32_t k = 0; k < T.ne; ++k) words += (uint64_t)H.swidth[T.aux + k] * SELL_GROUP;
     else
       words = T.ne;
     uint64_t rows = tile_kind(T.kind) == TK_LONG ? 1 : tile_rows(T.kind);

@@ -78,8 +78,8 @@ __device__ inline uint64_t fold_partials(const DevMat& A, const uint64_t* __rest
 // One 64-row SELL slice by a whole workgroup, for s > 1: the slice's S passes
 // (RPW = 64/S rows each, lane = (row, component)) are split over the 4 waves,
 // so a launch has four times the waves of one-slice-per-wave. Every wave reads
-// the full slice column (entry words and values, lane = row) and keeps the
-// passes it owns. With PROJ the slice also adds U^T W_{i+1} over its rows: a
+// the slice's 4-column groups (entry words and values, lane = row) and keeps
+// the passes it owns. With PROJ the slice also adds U^T W_{i+1} over its rows: a
 // lane holds W_{i+1}[row][c] and U[row][c]; the U values of the row's other
 // components come by shuffle, so out[a*s + c] gets sum_row U[row][a] W[row][c].
 template <class AR, typename Tv, int S, bool PROJ>
@@ -90,15 +90,15 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
   constexpr int RPW = WAVE / S;
   constexpr int NW = TILE_THREADS / WAVE;
   constexpr int PPW = (S + NW - 1) / NW;  // passes per wave
-  constexpr int UC = PPW >= 4 ? 4 : 8;  // slice columns loaded together
+  constexpr int GU = PPW >= 4 ? 1 : 2;  // 4-column groups loaded together
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t comp = lane % S, sub = lane / S;
   const bool cok = (int)comp < s;
   const bool live = slice < T.ne;
   uint32_t off = 0;
   for (uint32_t k = 0; k < slice && live; ++k) off += A.swidth[T.aux + k];
-  const uint32_t width = live ? A.swidth[T.aux + slice] : 0u;
-  const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
+  const uint32_t groups = live ? A.swidth[T.aux + slice] : 0u;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
   const uint32_t* choff = A.choff + T.c0 + off;
   uint32_t prow[PPW];
   bool pok[PPW];
@@ -125,38 +125,46 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
     }
     acc.tick(A);
   }
-  for (uint32_t j0 = 0; j0 < width; j0 += UC) {
-    uint32_t w[UC], v[UC];
+  for (uint32_t g0 = 0; g0 < groups; g0 += GU) {
+    uint32_t w[GU][WIDE], v[GU][WIDE];
 #pragma unroll
-    for (int u = 0; u < UC; ++u) w[u] = j0 + u < width ? __builtin_nontemporal_load(ent + (size_t)(j0 + u) * WAVE) : PAD_WORD;
-#pragma unroll
-    for (int u = 0; u < UC; ++u) {
-      uint32_t tag = w[u] >> TAG_SHIFT;
-      uint64_t gm = __ballot(tag == TAG_GEN);
-      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
+    for (int u = 0; u < GU; ++u) {
+      u32x4 q = g0 + u < groups ? __builtin_nontemporal_load((const u32x4*)(ent + (size_t)(g0 + u) * SELL_GROUP))
+                                : (u32x4)(PAD_WORD);
+      w[u][0] = q.x;
+      w[u][1] = q.y;
+      w[u][2] = q.z;
+      w[u][3] = q.w;
     }
-    // every gather of the UC columns is issued before the first term is added
-    // (columns past the width hold padding words and add nothing)
-    uint32_t xv[UC][PPW];
 #pragma unroll
-    for (int u = 0; u < UC; ++u)
+    for (int u = 0; u < GU; ++u) load_values4<AR>(A, w[u], g0 + u < groups ? choff[g0 + u] : 0u, v[u]);
+    // every gather of the GU groups is issued before the first term is added
+    // (groups past the last hold padding words and add nothing)
+    uint32_t xv[GU][WIDE][PPW];
 #pragma unroll
-      for (int q = 0; q < PPW; ++q) {
-        int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
-        uint32_t wp = (uint32_t)__shfl((int)w[u], src);
-        xv[u][q] = ((wp >> TAG_SHIFT) != TAG_PAD && cok && pok[q]) ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp]
-                                                                     : 0u;
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k)
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+          int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
+          uint32_t wp = (uint32_t)__shfl((int)w[u][k], src);
+          xv[u][k][q] = ((wp >> TAG_SHIFT) != TAG_PAD && cok && pok[q])
+                            ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp]
+                            : 0u;
+        }
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+          int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
+          uint32_t wp = (uint32_t)__shfl((int)w[u][k], src), vp = (uint32_t)__shfl((int)v[u][k], src);
+          acc.a[q] += term<AR>(wp >> TAG_SHIFT, vp, xv[u][k][q], A.m);
+        }
+        acc.tick(A);
       }
-#pragma unroll
-    for (int u = 0; u < UC; ++u) {
-#pragma unroll
-      for (int q = 0; q < PPW; ++q) {
-        int src = (((int)wave * PPW + q) % S) * RPW + (int)sub;
-        uint32_t wp = (uint32_t)__shfl((int)w[u], src), vp = (uint32_t)__shfl((int)v[u], src);
-        acc.a[q] += term<AR>(wp >> TAG_SHIFT, vp, xv[u][q], A.m);
-      }
-      acc.tick(A);
-    }
   }
   uint32_t r[PPW];
 #pragma unroll

@@ -199,56 +199,55 @@ __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>
   }
 }
 
-// U chunks of 64 entries: all entry words first, then the values (one ballot
-// per chunk) and the gathered x, then the terms.
-template <class AR, typename Tx, int S, int U>
-struct ChunkBatch {
-  uint32_t w[U];
-  uint32_t vo[U];
-  uint32_t v[U];
-  uint32_t xv[U][S];
-  // step 1: the entry words. word_at(u): this lane's word pointer in chunk u, or null;
-  // choff_at(u): the chunk's value offset
-  template <class WordAt, class ChOff>
-  __device__ inline void load_words(WordAt word_at, ChOff choff_at) {
+// Values of the four entry words w of this lane (entries 4*lane .. 4*lane+3
+// of a chunk whose value offset is vo). Values follow the entry order, so the
+// lane's general values are consecutive, after those of lower lanes (four
+// ballots): one 12-byte (16-bit values) or 16-byte load fetches them all.
+template <class AR>
+__device__ inline void load_values4(const DevMat& A, const uint32_t* w, uint32_t vo, uint32_t* v) {
+  uint32_t idx = vo, g = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t* p = word_at(u);
-      w[u] = p ? __builtin_nontemporal_load(p) : PAD_WORD;
-      vo[u] = choff_at(u);
+  for (int k = 0; k < WIDE; ++k) {
+    bool gen = (w[k] >> TAG_SHIFT) == TAG_GEN;
+    idx += lanes_below(__ballot(gen));
+    g += gen ? 1u : 0u;
+  }
+  uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, j = 0;
+  if constexpr (sizeof(typename AR::ValT) == 2) {
+    if (g) {
+      const uint32_t* p = (const uint32_t*)A.val + (idx >> 1);
+      q0 = __builtin_nontemporal_load(p);
+      q1 = __builtin_nontemporal_load(p + 1);
+      q2 = __builtin_nontemporal_load(p + 2);
+    }
+    j = idx & 1u;
+  } else {
+    if (g) {
+      const uint32_t* p = (const uint32_t*)A.val + idx;
+      q0 = __builtin_nontemporal_load(p);
+      q1 = __builtin_nontemporal_load(p + 1);
+      q2 = __builtin_nontemporal_load(p + 2);
+      q3 = __builtin_nontemporal_load(p + 3);
     }
   }
-  // step 2: values and gathered x (needs the words)
-  __device__ inline void load_gathers(const DevMat& A, const Tx* X, int64_t ldx, int s) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint32_t tag = w[u] >> TAG_SHIFT;
-      uint64_t gm = __ballot(tag == TAG_GEN);
-      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, vo[u] + lanes_below(gm)) : 0u;
-      const Tx* xr = X + (int64_t)(w[u] & COL_MASK) * ldx;
-#pragma unroll
-      for (int c = 0; c < S; ++c) xv[u][c] = (tag != TAG_PAD && c < s) ? (uint32_t)xr[c] : 0u;
+  for (int k = 0; k < WIDE; ++k) {
+    bool gen = (w[k] >> TAG_SHIFT) == TAG_GEN;
+    uint32_t val;
+    if constexpr (sizeof(typename AR::ValT) == 2) {
+      uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
+      val = (d >> ((j & 1u) * 16)) & 0xffffu;
+    } else {
+      val = j == 0 ? q0 : j == 1 ? q1 : j == 2 ? q2 : q3;
     }
+    v[k] = gen ? val : 0u;
+    j += gen ? 1u : 0u;
   }
-  __device__ inline void accumulate(const DevMat& A, LaneAcc<AR, S>& acc, int s) const {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint32_t tag = w[u] >> TAG_SHIFT;
-      if (tag != TAG_PAD) {
-#pragma unroll
-        for (int c = 0; c < S; ++c)
-          if (c < s) acc.a[c] += term<AR>(tag, v[u], xv[u][c], A.m);
-        acc.tick(A);
-      }
-    }
-  }
-};
+}
 
-// U chunks of 256 entries read 4 words (16 bytes) per lane, for STREAM and
-// LONG tiles. Entry (lane, k) of a chunk is word 4*lane + k; values follow the
-// entry order, so the value index of a general entry is the chunk offset plus
-// the general entries of lower lanes (four ballots) plus those before it in
-// the lane.
+// U chunks of 256 entries, 4 words (16 bytes) per lane: the chunks of STREAM
+// and LONG tiles, and the 4-column groups of SELL slices (where the 4 words of
+// a lane are 4 consecutive entries of its row).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <class AR, typename Tx, int S, int U>
 struct Chunk4 {
@@ -274,45 +273,10 @@ struct Chunk4 {
   __device__ inline void load_gathers(const DevMat& A, const Tx* X, int64_t ldx, int s) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t idx = vo[u], g = 0;
+      load_values4<AR>(A, w[u], vo[u], v[u]);
 #pragma unroll
       for (int k = 0; k < WIDE; ++k) {
-        bool gen = (w[u][k] >> TAG_SHIFT) == TAG_GEN;
-        idx += lanes_below(__ballot(gen));
-        g += gen ? 1u : 0u;
-      }
-      // the lane's general values are consecutive from idx: one 12- or 16-byte load
-      uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, j = 0;
-      if constexpr (sizeof(typename AR::ValT) == 2) {
-        if (g) {
-          const uint32_t* p = (const uint32_t*)A.val + (idx >> 1);
-          q0 = __builtin_nontemporal_load(p);
-          q1 = __builtin_nontemporal_load(p + 1);
-          q2 = __builtin_nontemporal_load(p + 2);
-        }
-        j = idx & 1u;
-      } else {
-        if (g) {
-          const uint32_t* p = (const uint32_t*)A.val + idx;
-          q0 = __builtin_nontemporal_load(p);
-          q1 = __builtin_nontemporal_load(p + 1);
-          q2 = __builtin_nontemporal_load(p + 2);
-          q3 = __builtin_nontemporal_load(p + 3);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < WIDE; ++k) {
-        uint32_t tag = w[u][k] >> TAG_SHIFT;
-        bool gen = tag == TAG_GEN;
-        uint32_t val;
-        if constexpr (sizeof(typename AR::ValT) == 2) {
-          uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
-          val = (d >> ((j & 1u) * 16)) & 0xffffu;
-        } else {
-          val = j == 0 ? q0 : j == 1 ? q1 : j == 2 ? q2 : q3;
-        }
-        v[u][k] = gen ? val : 0u;
-        j += gen ? 1u : 0u;
+        const uint32_t tag = w[u][k] >> TAG_SHIFT;
         const Tx* xr = X + (int64_t)(w[u][k] & COL_MASK) * ldx;
 #pragma unroll
         for (int c = 0; c < S; ++c) xv[u][k][c] = (tag != TAG_PAD && c < s) ? (uint32_t)xr[c] : 0u;
@@ -336,6 +300,9 @@ struct Chunk4 {
 };
 
 // ------------------------------- SELL tile ---------------------------------
+// A slice stores its rows in groups of 4 columns: group g is 256 words, word
+// 4*lane + k being entry 4g + k of the slice's row `lane`; swidth holds the
+// number of groups of each slice.
 template <class AR, typename Tx, typename Tv, int S, int U>
 __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                  Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta) {
@@ -344,19 +311,22 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
   if (wave >= nsl) return;
   uint32_t off = 0;
   for (uint32_t k = 0; k < wave; ++k) off += A.swidth[T.aux + k];
-  const uint32_t width = A.swidth[T.aux + wave];
+  const uint32_t groups = A.swidth[T.aux + wave];
   const uint32_t slot = wave * WAVE + lane;
   uint32_t row = (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
   const bool valid = row < A.nrows;
-  const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
   const uint32_t* choff = A.choff + T.c0 + off;
   LaneAcc<AR, S> acc;
   acc.init(A);
   if (valid) band_terms<AR, Tx, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
-  for (uint32_t j0 = 0; j0 < width; j0 += U) {
-    ChunkBatch<AR, Tx, S, U> b;
-    b.load_words([&](int u) -> const uint32_t* { return j0 + u < width ? ent + (size_t)(j0 + u) * WAVE : nullptr; },
-                 [&](int u) -> uint32_t { return j0 + u < width ? choff[j0 + u] : 0u; });
+  for (uint32_t g0 = 0; g0 < groups; g0 += U) {
+    Chunk4<AR, Tx, S, U> b;
+    b.load_words(
+        [&](int u) -> const u32x4* {
+          return g0 + u < groups ? (const u32x4*)(ent + (size_t)(g0 + u) * SELL_GROUP) : nullptr;
+        },
+        [&](int u) -> uint32_t { return g0 + u < groups ? choff[g0 + u] : 0u; });
     b.load_gathers(A, X, ldx, s);
     b.accumulate(A, acc, s);
   }
@@ -369,23 +339,23 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
 
 // SELL with s > 1 vectors: lane (r, c) of a pass handles component c of row
 // r, so the S lanes of one row gather one contiguous piece of X (one cache
-// line for s = 8 int64) instead of S separate lookups per lane. The entry word
-// and value of each row are loaded once per slice column with lane = row and
-// broadcast to the pass lanes with a shuffle.
+// line for s = 8 int64) instead of S separate lookups per lane. The entry
+// words and values of each row are loaded once per 4-column group with lane =
+// row and broadcast to the pass lanes with shuffles.
 template <class AR, typename Tx, typename Tv, int S>
 __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                     Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta) {
-  constexpr int RPW = WAVE / S;            // rows per pass; S passes cover the slice
-  constexpr int UC = S >= 16 ? 1 : 16 / S;  // slice columns loaded together (16 gathers in flight)
+  constexpr int RPW = WAVE / S;                       // rows per pass; S passes cover the slice
+  constexpr int KB = S >= 16 ? 1 : S >= 8 ? 2 : WIDE;  // group columns per batch: 16 gathers in flight
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t nsl = T.ne;
   if (wave >= nsl) return;
   uint32_t off = 0;
   for (uint32_t k = 0; k < wave; ++k) off += A.swidth[T.aux + k];
-  const uint32_t width = A.swidth[T.aux + wave];
+  const uint32_t groups = A.swidth[T.aux + wave];
   const uint32_t comp = lane % S, sub = lane / S;
   const bool cok = (int)comp < s;
-  const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
   const uint32_t* choff = A.choff + T.c0 + off;
   uint32_t prow[S];  // row of each pass
 #pragma unroll
@@ -410,35 +380,37 @@ __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __
     }
     acc.tick(A);
   }
-  for (uint32_t j0 = 0; j0 < width; j0 += UC) {
-    uint32_t w[UC], v[UC];
-#pragma unroll
-    for (int u = 0; u < UC; ++u) w[u] = j0 + u < width ? __builtin_nontemporal_load(ent + (size_t)(j0 + u) * WAVE) : PAD_WORD;
-#pragma unroll
-    for (int u = 0; u < UC; ++u) {
-      uint32_t tag = w[u] >> TAG_SHIFT;
-      uint64_t gm = __ballot(tag == TAG_GEN);
-      v[u] = tag == TAG_GEN ? ldval<typename AR::ValT>(A.val, choff[j0 + u] + lanes_below(gm)) : 0u;
+  for (uint32_t g = 0; g < groups; ++g) {
+    uint32_t w[WIDE], v[WIDE];
+    {
+      u32x4 q = __builtin_nontemporal_load((const u32x4*)(ent + (size_t)g * SELL_GROUP));
+      w[0] = q.x;
+      w[1] = q.y;
+      w[2] = q.z;
+      w[3] = q.w;
     }
-    // every gather of the UC columns is issued before the first term is added
-    // (columns past the width hold padding words and add nothing)
-    uint32_t xv[UC][S];
+    load_values4<AR>(A, w, choff[g], v);
 #pragma unroll
-    for (int u = 0; u < UC; ++u)
+    for (int k0 = 0; k0 < WIDE; k0 += KB) {
+      // every gather of the batch is issued before the first term is added
+      uint32_t xv[KB][S];
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
-        uint32_t wp = (uint32_t)__shfl((int)w[u], p * RPW + (int)sub);
-        xv[u][p] = ((wp >> TAG_SHIFT) != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp] : 0u;
+      for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          uint32_t wp = (uint32_t)__shfl((int)w[k0 + k], p * RPW + (int)sub);
+          xv[k][p] = ((wp >> TAG_SHIFT) != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(wp & COL_MASK) * ldx + comp] : 0u;
+        }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          int src = p * RPW + (int)sub;
+          uint32_t wp = (uint32_t)__shfl((int)w[k0 + k], src), vp = (uint32_t)__shfl((int)v[k0 + k], src);
+          acc.a[p] += term<AR>(wp >> TAG_SHIFT, vp, xv[k][p], A.m);
+        }
+        acc.tick(A);
       }
-#pragma unroll
-    for (int u = 0; u < UC; ++u) {
-#pragma unroll
-      for (int p = 0; p < S; ++p) {
-        int src = p * RPW + (int)sub;
-        uint32_t wp = (uint32_t)__shfl((int)w[u], src), vp = (uint32_t)__shfl((int)v[u], src);
-        acc.a[p] += term<AR>(wp >> TAG_SHIFT, vp, xv[u][p], A.m);
-      }
-      acc.tick(A);
     }
   }
 #pragma unroll
@@ -680,7 +652,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
   const Tile T = A.tiles[blockIdx.x % A.ntiles];
   switch (tile_kind(T.kind)) {
     case TK_SELL:
-      if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta);
+      if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 2>(A, T, X, ldx, Y, ldy, s, alpha, beta);
       else sell_tile_rc<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta);
       break;
     case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 1)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;

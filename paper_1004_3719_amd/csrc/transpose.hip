@@ -10,6 +10,12 @@
 
 namespace ffx {
 
+// the value type of the stored entries (all that load_values4 needs to know)
+template <typename V>
+struct ValsOf {
+  using ValT = V;
+};
+
 template <typename V, bool SMALL>
 __device__ inline uint64_t scatter_term(uint32_t tag, uint32_t v, uint32_t x, const DevMat& A) {
   uint64_t t;
@@ -40,15 +46,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_scatter_t(DevMat A, const Tv* 
     if (wave < T.ne) {
       uint32_t off = 0;
       for (uint32_t k = 0; k < wave; ++k) off += A.swidth[T.aux + k];
-      const uint32_t width = A.swidth[T.aux + wave], slot = wave * WAVE + lane;
+      const uint32_t groups = A.swidth[T.aux + wave], slot = wave * WAVE + lane;
       const uint32_t row = (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
-      const uint32_t* ent = A.ent + T.e0 + (size_t)off * WAVE + lane;
-      for (uint32_t j = 0; j < width; ++j) {
-        uint32_t w = ent[(size_t)j * WAVE];
-        uint32_t tag = w >> TAG_SHIFT;
-        uint64_t gm = __ballot(tag == TAG_GEN);
-        uint32_t v = tag == TAG_GEN ? ldval<V>(A.val, A.choff[T.c0 + off + j] + lanes_below(gm)) : 0u;
-        scatter_entry<V, SMALL, Tv>(A, row, w, v, X, ldx, s, acc);
+      const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
+      for (uint32_t g = 0; g < groups; ++g) {  // 4-column groups: 4 consecutive entries of the lane's row
+        uint32_t w[WIDE], v[WIDE];
+        for (int k = 0; k < WIDE; ++k) w[k] = ent[(size_t)g * SELL_GROUP + k];
+        load_values4<ValsOf<V>>(A, w, A.choff[T.c0 + off + g], v);
+        for (int k = 0; k < WIDE; ++k) scatter_entry<V, SMALL, Tv>(A, row, w[k], v[k], X, ldx, s, acc);
       }
     }
   } else {
