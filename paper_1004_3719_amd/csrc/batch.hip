@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <type_traits>
 
 #include "host.h"
 #include "launch.h"
@@ -33,8 +34,20 @@ struct BatchOperand {
   int64_t ldx, ldy;
 };
 
-template <class AR, typename Tv>
-__global__ __launch_bounds__(TILE_THREADS) void k_batch(const DevMat* __restrict__ mats,
+// Right-hand-side column chunks fall in four classes (1, 2, 3..4, 5..8
+// columns), each with its own persistent kernel: a kernel holding every class's
+// tile paths would take the registers of the largest and run at 3 waves per
+// SIMD.
+constexpr int NCLS = 4;
+inline int chunk_class(int sc) { return sc <= 1 ? 0 : sc <= 2 ? 1 : sc <= 4 ? 2 : 3; }
+
+// 4 workgroups (4 waves per SIMD) for the m <= 65536 kernels: they fit 128
+// registers without spilling
+template <class AR>
+constexpr int batch_min_blocks() { return std::is_same<AR, ArSmall>::value ? 4 : 1; }
+
+template <class AR, typename Tv, int SC>
+__global__ __launch_bounds__(TILE_THREADS, batch_min_blocks<AR>()) void k_batch(const DevMat* __restrict__ mats,
                                                         const BatchOperand* __restrict__ ops,
                                                         const BatchItem* __restrict__ items, uint32_t nitems,
                                                         uint32_t* counter) {
@@ -54,50 +67,51 @@ __global__ __launch_bounds__(TILE_THREADS) void k_batch(const DevMat* __restrict
     Tv* Y = (Tv*)O.Y + I.c0;
     const int sc = I.sc;
     const uint32_t kind = tile_kind(T.kind);
-    if (sc == 1) {
+    if constexpr (SC == 1) {
       if (kind == TK_SELL) sell_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0);
       else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0, lds);
       else stream_tile_1<AR, Tv, Tv, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 0, lds);
-    } else if (sc <= 2) {
-      if (kind == TK_SELL) sell_tile_rc<AR, Tv, Tv, 2>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0);
-      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 2, 1>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
-      else stream_tile_s<AR, Tv, Tv, 2>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
-    } else if (sc <= 4) {
-      if (kind == TK_SELL) sell_tile_rc<AR, Tv, Tv, 4>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0);
-      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 4, 1>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
-      else stream_tile_s<AR, Tv, Tv, 4>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
     } else {
-      if (kind == TK_SELL) sell_tile_rc<AR, Tv, Tv, 8>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0);
-      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 8, 1>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
-      else stream_tile_s<AR, Tv, Tv, 8>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
+      if (kind == TK_SELL) sell_tile_rc<AR, Tv, Tv, SC>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0);
+      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, SC, 1>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
+      else stream_tile_s<AR, Tv, Tv, SC>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
     }
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
-__global__ void k_batch_reset(uint32_t* counter, uint32_t first) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = first;
+__global__ void k_batch_reset(uint32_t* counter, int n) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n) counter[threadIdx.x] = 0;
 }
 
 template <class AR>
-static size_t batch_lds(int64_t mte) {
-  size_t a = tiles_lds_bytes<AR>(mte, 1), b = tiles_lds_bytes<AR>(mte, 8);
-  return a > b ? a : b;
+static size_t batch_lds(int64_t mte, int sc) {
+  size_t a = tiles_lds_bytes<AR>(mte, sc);
+  return a < 16 ? 16 : a;
 }
 
-static hipError_t batch_launch(int ak, ffx_dtype dt, const DevMat* mats, const BatchOperand* ops,
-                               const BatchItem* items, uint32_t nitems, uint32_t* counter, int grid, int64_t mte,
-                               hipStream_t st) {
-  // every workgroup takes its first item from the counter too: start it at 0
+// One class's persistent launch over items [first, first + n).
+static hipError_t batch_launch_class(int ak, ffx_dtype dt, int cls, const DevMat* mats, const BatchOperand* ops,
+                                     const BatchItem* items, uint32_t n, uint32_t* counter, int grid, int64_t mte,
+                                     hipStream_t st) {
   auto go = [&](auto ar) {
     using AR = decltype(ar);
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter, 0u);
-    if (dt == FFX_I32)
-      hipLaunchKernelGGL((k_batch<AR, int32_t>), dim3(grid), dim3(TILE_THREADS), batch_lds<AR>(mte), st, mats, ops,
-                         items, nitems, counter);
-    else
-      hipLaunchKernelGGL((k_batch<AR, int64_t>), dim3(grid), dim3(TILE_THREADS), batch_lds<AR>(mte), st, mats, ops,
-                         items, nitems, counter);
+    auto launch = [&](auto tv, auto scv) {
+      using Tv = decltype(tv);
+      constexpr int SC = decltype(scv)::value;
+      hipLaunchKernelGGL((k_batch<AR, Tv, SC>), dim3(grid), dim3(TILE_THREADS), batch_lds<AR>(mte, SC), st, mats, ops,
+                         items, n, counter);
+    };
+    auto by_dt = [&](auto scv) {
+      if (dt == FFX_I32) launch(int32_t{}, scv);
+      else launch(int64_t{}, scv);
+    };
+    switch (cls) {
+      case 0: by_dt(std::integral_constant<int, 1>{}); break;
+      case 1: by_dt(std::integral_constant<int, 2>{}); break;
+      case 2: by_dt(std::integral_constant<int, 4>{}); break;
+      default: by_dt(std::integral_constant<int, 8>{}); break;
+    }
   };
   switch (ak) {
     case AK_SMALL: go(ArSmall{}); break;
@@ -128,8 +142,9 @@ struct ffx_batch_s {
   DevMat* d_mats = nullptr;
   BatchOperand* d_ops = nullptr;
   BatchItem* d_items = nullptr;
-  uint32_t* d_counter = nullptr;
+  uint32_t* d_counter = nullptr;  // one per chunk class
   uint32_t nitems = 0;
+  uint32_t cls_first[NCLS] = {0, 0, 0, 0}, cls_n[NCLS] = {0, 0, 0, 0};
   std::vector<BatchOperand> h_ops;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -162,13 +177,22 @@ static void batch_items(ffx_batch_s* B) {
         cost.push_back((uint64_t)tc[t] * (uint64_t)(sc + 3));
       }
   }
-  if (B->params.order == 0) {
-    std::vector<size_t> idx(items.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<BatchItem> sorted(items.size());
-    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
-    items.swap(sorted);
+  // by chunk class (each class is one kernel), then by decreasing cost when order == 0
+  std::vector<size_t> idx(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  const bool by_cost = B->params.order == 0;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+    int ca = chunk_class(items[a].sc), cb = chunk_class(items[b].sc);
+    if (ca != cb) return ca < cb;
+    return by_cost && cost[a] > cost[b];
+  });
+  std::vector<BatchItem> sorted(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
+  items.swap(sorted);
+  for (int c = 0; c < NCLS; ++c) B->cls_first[c] = B->cls_n[c] = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    int c = chunk_class(items[i].sc);
+    if (B->cls_n[c]++ == 0) B->cls_first[c] = (uint32_t)i;
   }
   if (B->d_items) (void)hipFree(B->d_items);
   B->d_items = nullptr;
@@ -202,19 +226,46 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
   // operand table: pageable host memory, so the copy is staged before the call returns
   FFX_HIP(hipMemcpyAsync(B->d_ops, B->h_ops.data(), B->h_ops.size() * sizeof(BatchOperand), hipMemcpyHostToDevice, st));
   const int wpc = B->params.wg_per_cu ? B->params.wg_per_cu : 4;
-  const int grid = (int)std::min<int64_t>((int64_t)B->ncu * wpc, B->nitems);
+  auto grid_of = [&](int c) { return (int)std::min<int64_t>((int64_t)B->ncu * wpc, B->cls_n[c]); };
+  auto launch_class = [&](int c, hipStream_t s) {
+    return batch_launch_class(B->ak, dt, c, B->d_mats, B->d_ops, B->d_items + B->cls_first[c], B->cls_n[c],
+                              B->d_counter + c, grid_of(c), B->mte, s);
+  };
   if (B->params.use_graph) {
     if (B->exec && B->graph_dt != (int)dt) B->drop_graph();
     if (!B->exec) {
+      // the classes are independent branches of one graph: their kernels share the GPU and their
+      // tails overlap
       B->graph_dt = (int)dt;
-      hipStream_t cs;
+      hipStream_t cs, br[NCLS] = {};
+      hipEvent_t ev0 = nullptr, evc[NCLS] = {};
       FFX_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      hipError_t e = hipSuccess;
+      for (int c = 0; c < NCLS && e == hipSuccess; ++c) {
+        e = hipStreamCreateWithFlags(&br[c], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&evc[c], hipEventDisableTiming);
+      }
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        (void)batch_launch(B->ak, dt, B->d_mats, B->d_ops, B->d_items, B->nitems, B->d_counter, grid, B->mte, cs);
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, cs, B->d_counter, NCLS);
+        hipError_t le = hipEventRecord(ev0, cs);
+        for (int c = 0; c < NCLS && le == hipSuccess; ++c) {
+          if (!B->cls_n[c]) continue;
+          le = hipStreamWaitEvent(br[c], ev0, 0);
+          if (le == hipSuccess) le = launch_class(c, br[c]);
+          if (le == hipSuccess) le = hipEventRecord(evc[c], br[c]);
+          if (le == hipSuccess) le = hipStreamWaitEvent(cs, evc[c], 0);
+        }
         e = hipStreamEndCapture(cs, &B->graph);
+        if (e == hipSuccess) e = le;
       }
       if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+      for (int c = 0; c < NCLS; ++c) {
+        if (evc[c]) (void)hipEventDestroy(evc[c]);
+        if (br[c]) (void)hipStreamDestroy(br[c]);
+      }
+      if (ev0) (void)hipEventDestroy(ev0);
       (void)hipStreamDestroy(cs);
       if (e != hipSuccess) {
         B->drop_graph();
@@ -224,7 +275,9 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
     FFX_HIP(hipGraphLaunch(B->exec, st));
     return;
   }
-  FFX_HIP(batch_launch(B->ak, dt, B->d_mats, B->d_ops, B->d_items, B->nitems, B->d_counter, grid, B->mte, st));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B->d_counter, NCLS);
+  for (int c = 0; c < NCLS; ++c)
+    if (B->cls_n[c]) FFX_HIP(launch_class(c, st));
 }
 
 template <class F>
@@ -333,7 +386,7 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
       FFX_HIP(hipMalloc(&B->d_mats, sizeof(DevMat) * count));
       FFX_HIP(hipMemcpy(B->d_mats, dm.data(), sizeof(DevMat) * count, hipMemcpyHostToDevice));
       FFX_HIP(hipMalloc(&B->d_ops, sizeof(BatchOperand) * count));
-      FFX_HIP(hipMalloc(&B->d_counter, sizeof(uint32_t)));
+      FFX_HIP(hipMalloc(&B->d_counter, NCLS * sizeof(uint32_t)));
       B->h_ops.resize(count);
       batch_items(B);
       (void)stream;
