@@ -405,18 +405,19 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
     }
     warm_pool(st);
     const Encoded& E = A->A;
-    size_t wbytes = (size_t)n * s * esize(dtype);
+    size_t wbytes = (size_t)n * s * sizeof(int32_t);  // W_i and U are kept as int32 residues
     size_t pbytes = ((size_t)std::max<int64_t>(E.ntiles, 1) * SELL_SLICES + 64) * s * s * sizeof(uint64_t);
-    void* ws[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t sizes[5] = {wbytes, wbytes, pbytes, pbytes, sizeof(int64_t)};
-    for (int q = 0; q < 5; ++q)
+    void* ws[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[6] = {wbytes, wbytes, wbytes, pbytes, pbytes, sizeof(int64_t)};
+    for (int q = 0; q < 6; ++q)
       if (hipMallocAsync(&ws[q], sizes[q], st) != hipSuccess) {
         for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
         fail(FFX_ENOMEM, "sequence workspace allocation failed");
       }
     const int batch = L >= 128 ? 64 : 0;
     hipError_t e = launch_sequence(seq_kind(*A), only_sell(E), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
-                                   Wlast, ws[0], ws[1], (uint64_t*)ws[2], (uint64_t*)ws[3], (int64_t*)ws[4], batch, st);
+                                   Wlast, ws[0], ws[1], ws[2], (uint64_t*)ws[3], (uint64_t*)ws[4], (int64_t*)ws[5], batch,
+                                   st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
   });

@@ -43,14 +43,15 @@ inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype d
 hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st);
 
 // The sequence S_i = U^T A^i V, i < L (L >= 1), and A^L V into Wlast when not
-// null. Workspace: w0, w1 (n x s each), p0, p1 ((4 * ntiles + 64) * s * s uint64 each),
-// counter (one int64). Steps are replayed from a hipGraph in batches of
-// `batch` iterations (0: no graph).
+// null. Workspace: w0, w1, u32 (n x s int32 each), p0, p1 ((4 * ntiles + 64) *
+// s * s uint64 each), counter (one int64). Steps are replayed from a hipGraph
+// in batches of `batch` iterations (0: no graph).
 // ak: an integer class (AK_SMALL, AK_BIG, AK_BIG_CH or AK_M31); only_sell: the
 // matrix has SELL tiles only.
 hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
-                           void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st);
+                           void* w1, void* u32, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch,
+                           hipStream_t st);
 
 // Y = alpha*A^T*X + beta*Y by scattering the entries of A (no stored A^T);
 // acc is workspace of ncols * s uint64.

@@ -210,30 +210,32 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
 }
 
 // ------------------------------------------------------------- kernels -----
+// The blocks W_i and U live in workspace as int32 (n x s, ld = s), whatever the
+// caller's element type: residues are below 2^31, and the 32-bit copies halve
+// the bytes every iteration gathers, writes and projects. Only S (and the
+// final W_L) take the caller's type.
+using Tw = int32_t;
+
 struct SeqArgs {
-  const void* U;
-  int64_t ldu;
-  void* W[2];          // W_i lives in W[i & 1] (except W_0 = V)
-  const void* V;
-  int64_t ldv;
+  const Tw* U;         // n x s, ld s
+  Tw* W[2];            // W_i lives in W[i & 1]; n x s, ld s
   uint64_t* part[2];   // [4*ntiles][s*s] partial sums, by parity
   uint64_t* mid[2];    // [NMID][s*s] folded partial sums, by parity
-  void* S;             // L*s*s entries
+  void* S;             // L*s*s entries of the caller's type
   const int64_t* base; // device counter: iteration number of node 0 of this batch
   int64_t L;
   int32_t s;
-  int32_t last_w;      // write W_{i+1} even at i = L-1 (into Wlast)
-  void* Wlast;
+  int32_t last_w;      // compute W_L too (at i = L-1)
 };
 
-// Projection of V into the partials of iteration 0.
-template <class AR, typename Tv>
+// Projection of W_0 = V into the partials of iteration 0.
+template <class AR>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_first(DevMat A, SeqArgs q) {
   __shared__ uint64_t red[TILE_THREADS];
   const Tile T = A.tiles[blockIdx.x];
   const int64_t ss = (int64_t)q.s * q.s;
   uint64_t* out = q.part[0] + (int64_t)blockIdx.x * SELL_SLICES * ss;
-  tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, (const Tv*)q.V, q.ldv, q.s, red, out);
+  tile_projection<AR, Tw>(A, T, q.U, q.s, q.W[0], q.s, q.s, red, out);
   for (int64_t k = ss + threadIdx.x; k < SELL_SLICES * ss; k += TILE_THREADS) out[k] = 0;
 }
 
@@ -245,7 +247,7 @@ constexpr uint32_t NMID = 64;
 
 // ONLY_SELL: the matrix has SELL tiles only, and the kernel is built without
 // the STREAM/LONG path, whose registers would otherwise set the occupancy.
-template <class AR, typename Tv, int S, bool ONLY_SELL>
+template <class AR, typename Ts, int S, bool ONLY_SELL>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int64_t i = *q.base + j;
@@ -261,22 +263,21 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
       if (pair < ss) q.mid[i & 1][r * ss + pair] = t;
     } else if (i > 0) {  // stage 2 for iteration i-1
       uint64_t t = fold_partials(A, q.mid[(i - 1) & 1], 0, 1, NMID, s, (uint64_t*)lds, &pair);
-      if (pair < ss) ((Tv*)q.S)[(i - 1) * ss + pair] = (Tv)mod_u64(t, A.m, A.mu);
+      if (pair < ss) ((Ts*)q.S)[(i - 1) * ss + pair] = (Ts)mod_u64(t, A.m, A.mu);
     }
     return;
   }
   const bool last = i + 1 == q.L;
   if (last && !q.last_w) return;
-  const Tv* Win = i == 0 ? (const Tv*)q.V : (const Tv*)q.W[i & 1];
-  const int64_t ldin = i == 0 ? q.ldv : s;
-  Tv* Wout = last ? (Tv*)q.Wlast : (Tv*)q.W[(i + 1) & 1];
+  const Tw* Win = q.W[i & 1];
+  Tw* Wout = q.W[(i + 1) & 1];
+  const int64_t ldin = s;
   const uint32_t t = blockIdx.x / SELL_SLICES, slice = blockIdx.x % SELL_SLICES;
   const Tile T = A.tiles[t];
   uint64_t* out = q.part[(i + 1) & 1] + (int64_t)blockIdx.x * ss;
   if (tile_kind(T.kind) == TK_SELL) {
-    if (last) sell_slice_rc<AR, Tv, S, false>(A, T, slice, Win, ldin, Wout, s, s, nullptr, 0, nullptr, nullptr);
-    else sell_slice_rc<AR, Tv, S, true>(A, T, slice, Win, ldin, Wout, s, s, (const Tv*)q.U, q.ldu, out,
-                                        (uint64_t*)lds);
+    if (last) sell_slice_rc<AR, Tw, S, false>(A, T, slice, Win, ldin, Wout, s, s, nullptr, 0, nullptr, nullptr);
+    else sell_slice_rc<AR, Tw, S, true>(A, T, slice, Win, ldin, Wout, s, s, q.U, s, out, (uint64_t*)lds);
     return;
   }
   if constexpr (!ONLY_SELL) {
@@ -284,31 +285,31 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
       if (!last && threadIdx.x < ss) out[threadIdx.x] = 0;
       return;
     }
-    if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tv, Tv, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
-    else stream_tile_s<AR, Tv, Tv, S>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+    if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tw, Tw, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
+    else stream_tile_s<AR, Tw, Tw, S>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
     if (last) return;  // W_L only: no partials needed
     // the projection reads back only rows this workgroup wrote: a workgroup barrier orders them
     __syncthreads();
-    tile_projection<AR, Tv>(A, T, (const Tv*)q.U, q.ldu, Wout, s, s, (uint64_t*)lds, out);
+    tile_projection<AR, Tw>(A, T, q.U, s, Wout, s, s, (uint64_t*)lds, out);
   }
 }
 
 // S_{L-1} from the sums of the last iteration.
-template <typename Tv>
+template <typename Ts>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_finish(DevMat A, SeqArgs q) {
   __shared__ uint64_t red[TILE_THREADS];
   const int64_t i = q.L - 1;
   const int64_t ss = (int64_t)q.s * q.s;
   uint32_t pair;
   uint64_t t = fold_partials(A, q.mid[i & 1], 0, 1, NMID, q.s, red, &pair);
-  if (pair < ss) ((Tv*)q.S)[i * ss + pair] = (Tv)mod_u64(t, A.m, A.mu);
+  if (pair < ss) ((Ts*)q.S)[i * ss + pair] = (Ts)mod_u64(t, A.m, A.mu);
 }
 
 __global__ void k_seq_counter(int64_t* base, int64_t add, int set) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *base = set ? add : *base + add;
 }
 
-template <class AR, typename Tv, bool ONLY_SELL>
+template <class AR, typename Ts, bool ONLY_SELL>
 static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int batch, hipStream_t user) {
   const int s = q.s;
   const int S = s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;  // the step always runs the multi-vector tiles
@@ -318,14 +319,14 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   auto step = [&](hipStream_t st, int32_t j) {
     dim3 g(A.ntiles * SELL_SLICES + NMID + 1), b(TILE_THREADS);
     switch (S) {
-      case 2: hipLaunchKernelGGL((k_seq_step<AR, Tv, 2, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      case 4: hipLaunchKernelGGL((k_seq_step<AR, Tv, 4, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      case 8: hipLaunchKernelGGL((k_seq_step<AR, Tv, 8, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      default: hipLaunchKernelGGL((k_seq_step<AR, Tv, 16, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 2: hipLaunchKernelGGL((k_seq_step<AR, Ts, 2, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 4: hipLaunchKernelGGL((k_seq_step<AR, Ts, 4, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 8: hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      default: hipLaunchKernelGGL((k_seq_step<AR, Ts, 16, ONLY_SELL>), g, b, lds, st, A, q, j); break;
     }
   };
   hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, user, base, (int64_t)0, 1);
-  hipLaunchKernelGGL((k_seq_first<AR, Tv>), dim3(A.ntiles), dim3(TILE_THREADS), 0, user, A, q);
+  hipLaunchKernelGGL((k_seq_first<AR>), dim3(A.ntiles), dim3(TILE_THREADS), 0, user, A, q);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t L = q.L;
@@ -354,24 +355,62 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   }
   // the remaining iterations, launched directly (the counter holds nbatch*batch)
   for (int64_t i = nbatch * batch; i < L; ++i) step(user, (int32_t)(i - nbatch * batch));
-  hipLaunchKernelGGL((k_seq_finish<Tv>), dim3(1), dim3(TILE_THREADS), 0, user, A, q);
+  hipLaunchKernelGGL((k_seq_finish<Ts>), dim3(1), dim3(TILE_THREADS), 0, user, A, q);
   return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert_block(const Ti* __restrict__ in, int64_t ldi, To* __restrict__ out, int64_t ldo, int64_t n,
+                                int s) {
+  int64_t total = n * s;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = t / s;
+    int c = (int)(t - k * s);
+    out[k * ldo + c] = (To)in[k * ldi + c];
+  }
+}
+
+// n x s block copy from element type `ti` (stride ldi) to `to` (stride ldo); values are residues, so
+// narrowing int64 -> int32 keeps them.
+static hipError_t convert_block(ffx_dtype ti, const void* in, int64_t ldi, ffx_dtype to, void* out, int64_t ldo,
+                                int64_t n, int s, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int64_t total = n * s;
+  int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  dim3 g(blocks), b(256);
+  if (ti == FFX_I32 && to == FFX_I32)
+    hipLaunchKernelGGL((k_convert_block<int32_t, int32_t>), g, b, 0, st, (const int32_t*)in, ldi, (int32_t*)out, ldo, n, s);
+  else if (ti == FFX_I32)
+    hipLaunchKernelGGL((k_convert_block<int32_t, int64_t>), g, b, 0, st, (const int32_t*)in, ldi, (int64_t*)out, ldo, n, s);
+  else if (to == FFX_I32)
+    hipLaunchKernelGGL((k_convert_block<int64_t, int32_t>), g, b, 0, st, (const int64_t*)in, ldi, (int32_t*)out, ldo, n, s);
+  else
+    hipLaunchKernelGGL((k_convert_block<int64_t, int64_t>), g, b, 0, st, (const int64_t*)in, ldi, (int64_t*)out, ldo, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,
+                             hipStream_t st) {
+  return convert_block(dt, in, ldi, dt, out, ldo, n, s, st);
 }
 
 hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte, ffx_dtype dt, const void* U,
                            int64_t ldu, const void* V, int64_t ldv, int64_t L, int s, void* S, void* Wlast, void* w0,
-                           void* w1, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch, hipStream_t st) {
+                           void* w1, void* u32, uint64_t* p0, uint64_t* p1, int64_t* counter, int batch,
+                           hipStream_t st) {
+  const int64_t n = A.nrows;
+  // int32 copies of U and W_0 = V in workspace
+  hipError_t e = convert_block(dt, U, ldu, FFX_I32, u32, s, n, s, st);
+  if (e == hipSuccess) e = convert_block(dt, V, ldv, FFX_I32, w0, s, n, s, st);
+  if (e != hipSuccess) return e;
   SeqArgs q;
   // the fold buffers live at the end of the partial buffers
   const int64_t ss = (int64_t)s * s;
   q.mid[0] = p0 + (int64_t)A.ntiles * SELL_SLICES * ss;
   q.mid[1] = p1 + (int64_t)A.ntiles * SELL_SLICES * ss;
-  q.U = U;
-  q.ldu = ldu;
-  q.W[0] = w0;
-  q.W[1] = w1;
-  q.V = V;
-  q.ldv = ldv;
+  q.U = (const Tw*)u32;
+  q.W[0] = (Tw*)w0;
+  q.W[1] = (Tw*)w1;
   q.part[0] = p0;
   q.part[1] = p1;
   q.S = S;
@@ -379,7 +418,6 @@ hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte,
   q.L = L;
   q.s = s;
   q.last_w = Wlast ? 1 : 0;
-  q.Wlast = Wlast;
   auto go = [&](auto ar) -> hipError_t {
     using AR = decltype(ar);
     if (only_sell) {
@@ -390,36 +428,13 @@ hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte,
     return seq_go<AR, int64_t, false>(A, mte, q, batch, st);
   };
   switch (ak) {
-    case AK_SMALL: return go(ArSmall{});
-    case AK_M31: return go(ArM31{});
-    case AK_BIG_CH: return go(ArBig<true>{});
-    default: return go(ArBig<false>{});
+    case AK_SMALL: e = go(ArSmall{}); break;
+    case AK_M31: e = go(ArM31{}); break;
+    case AK_BIG_CH: e = go(ArBig<true>{}); break;
+    default: e = go(ArBig<false>{}); break;
   }
-}
-
-template <typename Tv>
-__global__ void k_copy_block(const Tv* __restrict__ in, int64_t ldi, Tv* __restrict__ out, int64_t ldo, int64_t n,
-                             int s) {
-  int64_t total = n * s;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    int64_t k = t / s;
-    int c = (int)(t - k * s);
-    out[k * ldo + c] = in[k * ldi + c];
-  }
-}
-
-hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,
-                             hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  int64_t total = n * s;
-  int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  if (dt == FFX_I32)
-    hipLaunchKernelGGL(k_copy_block<int32_t>, dim3(blocks), dim3(256), 0, st, (const int32_t*)in, ldi, (int32_t*)out,
-                       ldo, n, s);
-  else
-    hipLaunchKernelGGL(k_copy_block<int64_t>, dim3(blocks), dim3(256), 0, st, (const int64_t*)in, ldi, (int64_t*)out,
-                       ldo, n, s);
-  return hipGetLastError();
+  if (e != hipSuccess || !Wlast) return e;
+  return convert_block(FFX_I32, q.W[L & 1], s, dt, Wlast, s, n, s, st);  // W_L, in the caller's type
 }
 
 }  // namespace ffx
