@@ -97,6 +97,25 @@ def copy_calibration(mib):
     del src, dst
 
 
+def copy_bandwidth(mib=512, reps=5):
+    """GB/s of a plain elementwise device copy (mib MiB read + mib MiB written): the achievable
+    counterpart of the 8 TB/s peak."""
+    import torch
+    src = torch.ones(mib * 2**18, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.add(src, 1, out=dst)
+    torch.cuda.synchronize()
+    a, b = event_pairs(1)[0]
+    a.record()
+    for _ in range(reps):
+        torch.add(src, 1, out=dst)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * mib * 2**20 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
 def pmc_summary(fetch_csv, write_csv, mib, out_path, command):
     """HBM bytes per product launch from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB
     per dispatch), each scaled by what the same counter reads for the calibration copy."""
@@ -177,12 +196,14 @@ def bench_spmv(args, big=True):
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
     khash = kernel_hash()
+    copy_gbs = copy_bandwidth() if big else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counters_traffic("spmv_powerlaw_2M_counters.json" if big else "none", khash),
                 "kernel": "k_to_u16 + k_tiles (the product's launches)" if m <= 65536 and A.ncols * 4 > 2**20 else "k_tiles",
                 "kernel_ms": round(kernel_ms, 5),
-                "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows)}
+                "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows),
+                "achievable_copy_GBps": copy_gbs}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -388,16 +409,18 @@ def bench_selector(args):
         block_cost["all_" + name] = round(ST.choice_cost(T[:nval], np.full(nval, f)), 4)
     log("validation blocks, summed time / best: %s" % json.dumps(block_cost))
     # held-out matrices: whole-product time, heuristic vs learned
-    tot_h, tot_l, same, nev = 0.0, 0.0, True, 0
+    tot_h, tot_l, tot_s, tot_b, same, nev = 0.0, 0.0, 0.0, 0.0, True, 0
     for k in range(1800, 1800 + args.eval_mats):
         sp, p = synth.c5_spec(k)
         r1 = min(sp.nrows, args.eval_rows) if args.eval_rows else sp.nrows
         A = synth.rows(sp, 0, r1)
         A.m = synth.M_C5
         x = torch.from_numpy(synth.vector(k, 8, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
-        r = ST.evaluate(A, model, x)
+        r = ST.evaluate(A, model, x, fixed=("STREAM", "BAND_STREAM"))
         tot_h += r["heuristic_us"]
         tot_l += r["learned_us"]
+        tot_s += r["fixed_STREAM_us"]
+        tot_b += r["fixed_BAND_STREAM_us"]
         same = same and r["same_result"]
         nev += 1
         if nev % 10 == 0:
@@ -409,6 +432,7 @@ def bench_selector(args):
               "train_blocks": int(len(X)), "history": hist[-1:]}
     extra = {"validation_block_cost_vs_best": block_cost,
              "heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
+             "all_STREAM_total_us": round(tot_s, 1), "all_BAND_STREAM_total_us": round(tot_b, 1),
              "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4), "results_identical": same}
     args.steps, args.warmup = nev, 0
     line(0.0, tot_l / 1e3, args, "fp32 network / int64 products", config, None, None, extra)

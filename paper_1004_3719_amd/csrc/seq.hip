@@ -109,6 +109,10 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
     prow[q] = (!live || p >= S) ? 0xFFFFFFFFu : (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
     pok[q] = prow[q] < A.nrows;
   }
+  // U of the projection does not depend on the product: its loads go out first
+  uint32_t urow[PPW];
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) urow[q] = (PROJ && pok[q] && cok) ? (uint32_t)U[(int64_t)prow[q] * ldu + comp] : 0u;
   LaneAcc<AR, PPW> acc;
   acc.init(A);
   const uint32_t nd = tile_nd(T.kind), rows_in_tile = tile_rows(T.kind);
@@ -177,7 +181,7 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
     pj.init(A);
 #pragma unroll
     for (int q = 0; q < PPW; ++q) {
-      uint32_t u = (pok[q] && cok) ? (uint32_t)U[(int64_t)prow[q] * ldu + comp] : 0u;
+      uint32_t u = urow[q];
       uint32_t w = (pok[q] && cok) ? r[q] : 0u;
 #pragma unroll
       for (int a = 0; a < S; ++a) {

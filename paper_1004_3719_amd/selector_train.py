@@ -139,8 +139,9 @@ def time_product(M, x, y, reps=10):
     return float(np.median(ts))
 
 
-def evaluate(A, model_path, x, reps=10):
-    """Whole-product time with the heuristic's and the learned formats (and whether the results agree)."""
+def evaluate(A, model_path, x, reps=10, fixed=()):
+    """Whole-product time with the heuristic's and the learned formats (and whether the results agree),
+    and with each format of `fixed` forced on every block (key "fixed_<name>_us")."""
     import torch
     y1 = torch.empty(A.nrows, dtype=x.dtype, device=x.device)
     y2 = torch.empty_like(y1)
@@ -155,4 +156,9 @@ def evaluate(A, model_path, x, reps=10):
            "heuristic_formats": Mh.info()["format_blocks"], "learned_formats": Ml.info()["format_blocks"]}
     Mh.close()
     Ml.close()
+    for f in fixed:
+        Mf = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, fixed_format=f)
+        out["fixed_%s_us" % f] = time_product(Mf, x, y2, reps)
+        out["same_result"] = out["same_result"] and bool(torch.equal(y1, y2))
+        Mf.close()
     return out
