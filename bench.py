@@ -276,9 +276,24 @@ def bench_sequence(args):
                 "algorithmic_bytes": int(b_iter)}
     config = {"workload": "block-Wiedemann sequence U^T A^i V mod 2^31-1: n=200,000, 15 nnz/row, s=8 int64, "
                           "L=%d" % L, "n": A.nrows, "nnz": A.nnz, "s": 8, "L": L}
+    # the same steps launched one per iteration from the host, against the hipGraph replay
+    from paper_1004_3719_amd import set_sequence_graph_batch
+    Lc = min(L, 4096)
+    cmp = {}
+    for gb in (64, 0):
+        set_sequence_graph_batch(gb)
+        M.sequence(Ud, Vd, 4)
+        torch.cuda.synchronize()
+        a, b = event_pairs(1)[0]
+        a.record()
+        M.sequence(Ud, Vd, Lc)
+        b.record()
+        torch.cuda.synchronize()
+        cmp["graph_batch_%d" % gb] = round(a.elapsed_time(b) / Lc, 5)
+    set_sequence_graph_batch(64)
     args.steps, args.warmup = L, 1
     line(work / (ev_ms * 1e-3), per_iter_ms, args, "int64", config, roofline, cpu,
-         {"wall_seconds": round(wall, 3)})
+         {"wall_seconds": round(wall, 3), "ms_per_iteration_%d_iterations" % Lc: cmp})
 
 
 # ---------------------------------------------------------------------- c4

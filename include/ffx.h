@@ -178,6 +178,14 @@ ffx_status ffx_power(ffx_matrix A, int64_t k, int32_t s, const void* V, int64_t 
 ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
                         void* S, void* Wlast, ffx_dtype dtype, void* stream);
 
+/* Iterations per hipGraph replay in ffx_sequence: the steps of `batch`
+ * iterations are captured once and the graph is replayed (Section 2.5: the
+ * iterates stay on the device and the host only launches). Default 64; 0
+ * launches every iteration directly. Process-wide, read at each
+ * ffx_sequence call; a tuning knob only, results never depend on it.
+ * FFX_EINVAL when batch is outside [0, 4096]. */
+ffx_status ffx_set_sequence_graph_batch(int32_t batch);
+
 /* ------------------------------------------------------------------------
  * Batched products: Y_k <- A_k X_k (mod m) for many matrices of uneven size,
  * each with its own number s_k of right-hand sides, in one persistent launch.

@@ -1,5 +1,6 @@
 // The C ABI: argument checks, matrix construction and product dispatch.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,9 @@ static ffx_status guard(F&& f) {
     return FFX_EDEVICE;
   }
 }
+
+// iterations per hipGraph replay of ffx_sequence (0: direct launches)
+static std::atomic<int> g_seq_graph_batch{64};
 
 static int arith_kind(const ffx_matrix_s& M) {
   bool small = M.md.small();
@@ -414,12 +418,20 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
         for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
         fail(FFX_ENOMEM, "sequence workspace allocation failed");
       }
-    const int batch = L >= 128 ? 64 : 0;
+    const int gb = g_seq_graph_batch.load();
+    const int batch = (gb > 0 && L >= 2 * (int64_t)gb) ? gb : 0;
     hipError_t e = launch_sequence(seq_kind(*A), only_sell(E), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
                                    Wlast, ws[0], ws[1], ws[2], (uint64_t*)ws[3], (uint64_t*)ws[4], (int64_t*)ws[5], batch,
                                    st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
+  });
+}
+
+ffx_status ffx_set_sequence_graph_batch(int32_t batch) {
+  return guard([&] {
+    if (batch < 0 || batch > 4096) fail(FFX_EINVAL, "graph batch %d outside [0, 4096]", batch);
+    g_seq_graph_batch.store(batch);
   });
 }
 

@@ -75,6 +75,7 @@ _SIGS = {
                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
     "ffx_power": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    "ffx_set_sequence_graph_batch": (ctypes.c_int, [ctypes.c_int32]),
     "ffx_sequence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_void_p]),
@@ -326,6 +327,11 @@ class Matrix:
                                   ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(W.data_ptr() if W is not None else 0),
                                   _dt(U), _stream(stream)))
         return (S, W) if want_last else S
+
+
+def set_sequence_graph_batch(batch):
+    """Iterations per hipGraph replay in Matrix.sequence (0: one direct launch per iteration)."""
+    _check(lib().ffx_set_sequence_graph_batch(int(batch)))
 
 
 def version():

@@ -84,3 +84,12 @@ def test_null_out_pointer():
     rp, c, v = _csr()
     st = L.ffx_matrix_create_csr(2, 2, rp.ctypes.data, c.ctypes.data, v.ctypes.data, 1, 7, None, None, None)
     assert st == ffx.FFX_EINVAL
+
+
+def test_sequence_graph_batch_range():
+    with pytest.raises(P.FfxError):
+        P.set_sequence_graph_batch(-1)
+    with pytest.raises(P.FfxError):
+        P.set_sequence_graph_batch(4097)
+    P.set_sequence_graph_batch(0)
+    P.set_sequence_graph_batch(64)

@@ -209,6 +209,27 @@ def test_sequence_full_length(dev, orc, ffx, m, s, dt):
     assert np.array_equal(W.cpu().numpy(), Wo)
 
 
+@pytest.mark.parametrize("graph_batch", [0, 8])
+def test_sequence_graph_batch(dev, orc, ffx, graph_batch):
+    """Direct launches per iteration and short graph replays (with a direct-launch remainder) give the
+    same sequence."""
+    from paper_1004_3719_amd import set_sequence_graph_batch
+    n, s, m = 1500, 4, 2**31 - 1
+    A = synth.c3(n=n, ndead=5, m=m)
+    U, V = synth.c3_blocks(n=n, s=s, m=m)
+    L = 37
+    note("sequence graph batch", graph_batch)
+    M = ffx.from_synth(A)
+    set_sequence_graph_batch(graph_batch)
+    try:
+        S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), L, want_last=True)
+    finally:
+        set_sequence_graph_batch(64)
+    So, Wo = orc.sequence(A, U, V, L, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
+
+
 def test_sequence_prefix_full_size(dev, orc, ffx):
     """The block-Wiedemann operand at full size (n = 200,000, s = 8, m = 2^31-1): the first 6
     sequence terms and a 4-term segment restarted from the GPU's own A^6 V."""
