@@ -394,7 +394,7 @@ def bench_selector(args):
             nb = max(1, sp.nrows // BR)
             b0 = int(rng.integers(0, max(1, nb - args.train_blocks + 1)))
             r0, r1 = b0 * BR, min(sp.nrows, (b0 + args.train_blocks) * BR)
-            A = synth.rows(sp, r0, r1)
+            A = ST.shift_columns(synth.rows(sp, r0, r1), r0)
             A.m = synth.M_C5
             x = torch.from_numpy(synth.vector(k, 7, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
             y = torch.empty(A.nrows, dtype=torch.int32, device=dev)

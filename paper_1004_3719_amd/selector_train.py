@@ -68,6 +68,14 @@ def choice_cost(T, choice):
     return float(t[np.arange(len(t)), choice].sum() / t.min(axis=1).sum())
 
 
+def shift_columns(A, r0):
+    """Rows r0.. of a matrix taken as a matrix of their own keep their diagonals only if the columns
+    move with the rows: column c becomes (c - r0) mod ncols, a cyclic permutation of the columns that
+    keeps every diagonal, band and block structure relative to the new row numbers."""
+    A.col = ((A.col.astype(np.int64) - r0) % A.ncols).astype(np.int32)
+    return A
+
+
 def standardisation(X):
     mean = X.mean(axis=0).astype(np.float32)
     sd = X.std(axis=0)
