@@ -317,16 +317,25 @@ __device__ inline void sell_tile(const DevMat& A, const Tile& T, const Tx* __res
   const bool valid = row < A.nrows;
   const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
   const uint32_t* choff = A.choff + T.c0 + off;
-  LaneAcc<AR, S> acc;
-  acc.init(A);
-  if (valid) band_terms<AR, Tx, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
-  for (uint32_t g0 = 0; g0 < groups; g0 += U) {
-    Chunk4<AR, Tx, S, U> b;
+  auto words = [&](Chunk4<AR, Tx, S, U>& b, uint32_t g0) {
     b.load_words(
         [&](int u) -> const u32x4* {
           return g0 + u < groups ? (const u32x4*)(ent + (size_t)(g0 + u) * SELL_GROUP) : nullptr;
         },
         [&](int u) -> uint32_t { return g0 + u < groups ? choff[g0 + u] : 0u; });
+  };
+  // the first batch of entry words is requested before the band part, whose
+  // loads then overlap its latency
+  Chunk4<AR, Tx, S, U> first;
+  words(first, 0);
+  LaneAcc<AR, S> acc;
+  acc.init(A);
+  if (valid) band_terms<AR, Tx, S>(A, T, acc, row, slot, tile_rows(T.kind), 0, 1, X, ldx, s);
+  first.load_gathers(A, X, ldx, s);  // groups past the last hold padding words and add nothing
+  first.accumulate(A, acc, s);
+  for (uint32_t g0 = U; g0 < groups; g0 += U) {
+    Chunk4<AR, Tx, S, U> b;
+    words(b, g0);
     b.load_gathers(A, X, ldx, s);
     b.accumulate(A, acc, s);
   }
@@ -494,15 +503,6 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
   const uint32_t ne = T.ne;
   const uint32_t nchunks = (ne + WCHUNK - 1) / WCHUNK;
   const uint32_t nr = tile_rows(T.kind);
-  if (tid < nr) rps[tid] = A.rowp[T.aux + tid] - T.e0;
-  if (tid == 0) rps[nr] = ne;  // nr may be 256: the sentinel needs its own writer
-  if (tid < nr) {
-    LaneAcc<AR, 1> band;
-    band.init(A);
-    band_terms<AR, Tx, 1>(A, T, band, T.row0 + tid, tid, nr, 0, 1, X, ldx, 1);
-    band.to_residues(A);
-    rowsum[tid] = band.a[0];
-  }
   auto words = [&](Chunk4<AR, Tx, 1, U>& b, uint32_t ch0) {
     b.load_words(
         [&](int u) -> const u32x4* {
@@ -514,9 +514,7 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
           return ch < nchunks ? A.choff[T.c0 + ch] : 0u;
         });
   };
-  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
-    Chunk4<AR, Tx, 1, U> b;
-    words(b, ch0);
+  auto terms = [&](Chunk4<AR, Tx, 1, U>& b, uint32_t ch0) {
     b.load_gathers(A, X, ldx, 1);
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -525,6 +523,25 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
         uint32_t e = (ch0 + u * NW) * WCHUNK + lane * WIDE + k;
         if (e < ne) prod[e] = term<AR>(b.w[u][k] >> TAG_SHIFT, b.v[u][k], b.xv[u][k][0], A.m);
       }
+  };
+  // the first batch of entry words is requested before the row pointers and
+  // the band part, whose loads then overlap its latency
+  Chunk4<AR, Tx, 1, U> first;
+  words(first, wave);
+  if (tid < nr) rps[tid] = A.rowp[T.aux + tid] - T.e0;
+  if (tid == 0) rps[nr] = ne;  // nr may be 256: the sentinel needs its own writer
+  if (tid < nr) {
+    LaneAcc<AR, 1> band;
+    band.init(A);
+    band_terms<AR, Tx, 1>(A, T, band, T.row0 + tid, tid, nr, 0, 1, X, ldx, 1);
+    band.to_residues(A);
+    rowsum[tid] = band.a[0];
+  }
+  terms(first, wave);  // chunks past the end hold padding words and store nothing
+  for (uint32_t ch0 = wave + NW * U; ch0 < nchunks; ch0 += NW * U) {
+    Chunk4<AR, Tx, 1, U> b;
+    words(b, ch0);
+    terms(b, ch0);
   }
   __syncthreads();
   // entry-balanced segmented sum
