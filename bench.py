@@ -4,7 +4,8 @@
 
 Default (c2): a step is one product y = A x mod 32749 over the 2,000,000-row
 power-law matrix (truncated Zipf(1.8) rows, a 5-diagonal band, 60% of entries
-+-1), with A, x and y resident in HBM. Prints one JSON line with the roofline
++-1), with A, x and y resident in HBM; block formats are chosen by the trained
+selector shipped in the package (--selector heuristic for the plain rules). Prints one JSON line with the roofline
 of the product kernel (algorithmic bytes over its HIP-event time against the
 8 TB/s HBM peak) and a CPU baseline: the plain C oracle, one thread, on the
 host, on repeated full products (checking the GPU result bit for bit).
@@ -413,6 +414,8 @@ def bench_selector(args):
     nval = max(1, len(X) // 10)
     S, hist = ST.fit(X[nval:], T[nval:], epochs=args.epochs, lr=args.lr, seed=args.seed, val=(X[:nval], T[:nval]),
                      log=lambda r: log(json.dumps(r)))
+    mu, mu_costs = ST.pick_margin(S, X[:nval], T[:nval])
+    log("decision margin %.2f (validation block cost by margin: %s)" % (mu, json.dumps(mu_costs)))
     model = args.model_out
     os.makedirs(os.path.dirname(model), exist_ok=True)
     S.save(model)
@@ -445,7 +448,7 @@ def bench_selector(args):
                           "matrices (first %s rows), 32->64->64->6 FP32" % (args.train_mats, args.train_blocks, nev,
                                                                            args.eval_rows or "all"),
               "train_blocks": int(len(X)), "history": hist[-1:]}
-    extra = {"validation_block_cost_vs_best": block_cost,
+    extra = {"validation_block_cost_vs_best": block_cost, "decision_margin_log2": mu,
              "heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
              "all_STREAM_total_us": round(tot_s, 1), "all_BAND_STREAM_total_us": round(tot_b, 1),
              "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4), "results_identical": same}
@@ -460,7 +463,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
-    ap.add_argument("--selector", default="heuristic", choices=["heuristic", "learned"])
+    ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
+                    help="block format chooser: the trained network shipped in the package (falls back to the "
+                         "heuristic if the model is missing) or the plain heuristic")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
     ap.add_argument("--tile-entries", type=int, default=0)
     ap.add_argument("--fixed-format", default=None)

@@ -669,7 +669,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
   const Tile T = A.tiles[blockIdx.x % A.ntiles];
   switch (tile_kind(T.kind)) {
     case TK_SELL:
-      if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 2>(A, T, X, ldx, Y, ldy, s, alpha, beta);
+      if constexpr (S == 1) sell_tile<AR, Tx, Tv, 1, 4>(A, T, X, ldx, Y, ldy, s, alpha, beta);
       else sell_tile_rc<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta);
       break;
     case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 1)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;

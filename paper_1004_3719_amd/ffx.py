@@ -168,6 +168,9 @@ def _block(t, rows, name):
     return t.data_ptr(), t.shape[1], max(t.stride(0), t.shape[1])
 
 
+PACKAGED_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "selector.bin")
+
+
 def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=True, block_rows=4096,
                build_transpose=False, tile_entries=0, compact_x=-1, model_path=None):
     o = BuildOpts()
@@ -182,6 +185,8 @@ def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=Tr
     o.build_transpose = int(bool(build_transpose))
     o.tile_entries = int(tile_entries)
     o.compact_x = int(compact_x)
+    if selector == "learned" and not model_path:
+        model_path = PACKAGED_MODEL  # the network trained for this GPU, shipped with the package
     o.model_path = model_path.encode() if model_path else None
     return o
 

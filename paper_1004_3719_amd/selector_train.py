@@ -83,11 +83,21 @@ def standardisation(X):
     return mean, scale
 
 
+def relative(T):
+    """log2 times relative to the STREAM format of the same block: the choice only depends on the
+    differences between formats, which are small beside the spread of block times, so the network
+    learns them directly."""
+    return T - T[:, :1]
+
+
 def fit(X, T, M=None, epochs=60, batch=512, lr=2e-3, seed=0, device="cuda:0", val=None, log=None):
-    """Train a Selector on features X and log-time targets T (numpy); M masks missing labels.
-    Returns (selector, history)."""
+    """Train a Selector on features X and log-time targets T (numpy, trained relative to STREAM);
+    M masks missing labels. Returns (selector, history)."""
     import torch
     dev = torch.device(device)
+    T = relative(T)
+    if val is not None:
+        val = (val[0], relative(val[1]))
     if M is None:
         M = np.ones_like(T)
     mean, scale = standardisation(X)
@@ -120,6 +130,30 @@ def fit(X, T, M=None, epochs=60, batch=512, lr=2e-3, seed=0, device="cuda:0", va
             if log:
                 log(rec)
     return S, hist
+
+
+def apply_margin(S, mu):
+    """Fold a decision margin into the output biases: every format other than STREAM (output 0) is
+    predicted mu (log2 units) slower, so a block leaves STREAM only when the network predicts a gain
+    larger than mu. Predicted differences smaller than the network's error then cost nothing."""
+    th, mean, scale = S.get_params()
+    th = th.copy()
+    th[-5:] += np.float32(mu)  # b3[1..5]
+    S.set_params(theta=th, mean=mean, scale=scale)
+
+
+def pick_margin(S, X, T, margins=(0.0, 0.05, 0.1, 0.2, 0.3, 0.5)):
+    """The margin with the lowest summed block time on (X, T), applied to S; returns (mu, costs)."""
+    base, mean, scale = S.get_params()
+    costs = {}
+    for mu in margins:
+        S.set_params(theta=base, mean=mean, scale=scale)
+        apply_margin(S, mu)
+        costs[mu] = choice_cost(T, choose(S, X)[0])
+    best = min(margins, key=lambda m: (round(costs[m], 4), m))
+    S.set_params(theta=base, mean=mean, scale=scale)
+    apply_margin(S, best)
+    return best, costs
 
 
 def choose(S, X, device="cuda:0"):
