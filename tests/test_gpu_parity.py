@@ -267,6 +267,25 @@ def test_sequence_projection_bound(dev, orc, ffx, m, s):
         assert np.array_equal(S, orc.sequence(A, U, V, 5)), fmt
 
 
+def test_sequence_full_size_checkpoints(dev, orc, ffx):
+    """The block-Wiedemann operand at full size over a long run: the first 48 terms against the oracle,
+    then 16-term oracle segments restarted from the GPU's own iterates W_c at c = 4,096 and 12,288
+    (graph replays of 64 steps, their counter and the parity of every buffer all cycle many times
+    before a checkpoint)."""
+    A = synth.c3()
+    U, V = synth.c3_blocks()
+    note("sequence full-size checkpoints")
+    M = ffx.from_synth(A)
+    Ud, Vd = tdev(U, dev, torch.int64), tdev(V, dev, torch.int64)
+    S = M.sequence(Ud, Vd, 48).cpu().numpy()
+    assert np.array_equal(S, orc.sequence(A, U, V, 48))
+    for c in (4096, 12288):
+        Sc = M.sequence(Ud, Vd, c + 16)
+        _, Wc = M.sequence(Ud, Vd, c, want_last=True)
+        seg = orc.sequence(A, U, Wc.cpu().numpy(), 16)
+        assert np.array_equal(Sc.cpu().numpy()[c:c + 16], seg), c
+
+
 # ---------------------------------------------------------- edge cases -----
 def test_degenerate_shapes(dev, orc, ffx):
     note("degenerate shapes")
