@@ -158,7 +158,7 @@ def bench_spmv(args, big=True):
     log("generated n=%d nnz=%d in %.1fs" % (A.nrows, A.nnz, time.time() - t0))
     t0 = time.time()
     opts = dict(acc=args.acc, selector=args.selector, tile_entries=args.tile_entries, fixed_format=args.fixed_format,
-                build_transpose=not big)
+                build_transpose=not big, compact_x=args.compact_x)
     if args.selector == "learned":
         opts["model_path"] = args.model
     M = Matrix.from_synth(A, **opts)
@@ -201,7 +201,9 @@ def bench_spmv(args, big=True):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counters_traffic("spmv_powerlaw_2M_counters.json" if big else "none", khash),
-                "kernel": "k_to_u16 + k_tiles (the product's launches)" if m <= 65536 and A.ncols * 4 > 2**20 else "k_tiles",
+                "kernel": ("k_to_u16 + k_tiles (the product's launches)"
+                           if m <= 65536 and (args.compact_x == 1 or (args.compact_x == -1 and A.ncols * 4 > 2**20))
+                           else "k_tiles"),
                 "kernel_ms": round(kernel_ms, 5),
                 "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows),
                 "achievable_copy_GBps": copy_gbs}
@@ -468,6 +470,8 @@ def main():
                          "heuristic if the model is missing) or the plain heuristic")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
     ap.add_argument("--tile-entries", type=int, default=0)
+    ap.add_argument("--compact-x", type=int, default=-1, choices=[-1, 0, 1],
+                    help="16-bit copy of x for m <= 65536: -1 auto (x above 1 MiB), 0 never, 1 always")
     ap.add_argument("--fixed-format", default=None)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
