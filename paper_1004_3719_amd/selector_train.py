@@ -27,23 +27,6 @@ from .ffx import FORMATS, Matrix, Selector, block_features
 NF = len(FORMATS)
 
 
-def block_labels(A, x_dev, reps=4, opts=None):
-    """(features (nb x 32), log2 microseconds (nb x 6), the heuristic's formats (nb)) of the row blocks of
-    A, a Csr-like object with nrows, ncols, rowptr, col, val, m."""
-    opts = dict(opts or {})
-    F = block_features(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
-    T = np.zeros((F.shape[0], NF), np.float32)
-    for f in range(NF):
-        M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, fixed_format=f, **opts)
-        t = M.block_times(x_dev, reps=reps)
-        M.close()
-        T[:, f] = np.log2(np.maximum(t, 1e-3))
-    M = Matrix.from_csr(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, **opts)
-    H = M.block_formats()
-    M.close()
-    return F, T, H
-
-
 def window_labels(A, x_dev, y_dev, reps=6, opts=None):
     """(features (nb x 32), log2 microseconds per block (nb x 6), the heuristic's formats (nb)) of a
     window A whose blocks share one generator: each format's label is the in-place product time of the

@@ -138,6 +138,23 @@ def test_block_times(dev):
     assert np.array_equal(y.cpu().numpy(), oracle.get().spmv(A, x.cpu().numpy()))
 
 
+def test_decision_margin_shifts_non_default_outputs(dev):
+    """The margin is folded into the output biases of the five non-STREAM formats: their predictions
+    move by exactly mu, STREAM's does not, and a block leaves STREAM only for a larger predicted gain."""
+    from paper_1004_3719_amd import Selector, selector_train as ST
+    X, _, _ = data(64, 7)
+    S = Selector(seed=5)
+    Xd = torch.from_numpy(X).to(dev)
+    before = S.predict(Xd).cpu().numpy()
+    ST.apply_margin(S, 0.25)
+    after = S.predict(Xd).cpu().numpy()
+    assert np.array_equal(after[:, 0], before[:, 0])
+    assert np.allclose(after[:, 1:] - before[:, 1:], 0.25, atol=1e-5)
+    ch, _ = ST.choose(S, X)
+    rel = before[:, 1:].min(axis=1) - before[:, 0]
+    assert np.array_equal(ch == 0, rel >= -0.25 + 1e-5) or np.all((ch == 0) == (rel > -0.25))
+
+
 MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1004_3719_amd", "models",
                      "selector.bin")
 
