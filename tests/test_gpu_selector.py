@@ -152,7 +152,8 @@ def test_decision_margin_shifts_non_default_outputs(dev):
     assert np.allclose(after[:, 1:] - before[:, 1:], 0.25, atol=1e-5)
     ch, _ = ST.choose(S, X)
     rel = before[:, 1:].min(axis=1) - before[:, 0]
-    assert np.array_equal(ch == 0, rel >= -0.25 + 1e-5) or np.all((ch == 0) == (rel > -0.25))
+    far = np.abs(rel + 0.25) > 1e-3  # away from the tie at exactly mu
+    assert np.array_equal((ch == 0)[far], (rel > -0.25)[far])
 
 
 MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1004_3719_amd", "models",
