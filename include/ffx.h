@@ -144,6 +144,16 @@ ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* ou
 
 ffx_status ffx_matrix_destroy(ffx_matrix A);
 
+/* Checked mode. Products take vector entries that are already residues in
+ * [0, m-1] (Section 2.2) and do not look at them; this call checks an n x s
+ * block X (device memory, element type dtype, leading dimension ldx >= s)
+ * before use. FFX_OK when every entry is in [0, m-1]; FFX_EINVAL when one is
+ * not, with *first_bad (when not NULL) the smallest flat index k*ldx + c of
+ * such an entry, and -1 on FFX_OK. FFX_EINVAL also for a bad modulus, dtype or
+ * shape. Runs on `stream` and waits for it. */
+ffx_status ffx_check_block(uint32_t m, const void* X, int64_t n, int32_t s, int64_t ldx, ffx_dtype dtype,
+                           void* stream, int64_t* first_bad);
+
 /* y <- alpha*A*x + beta*y (mod m). x: ncols entries, y: nrows entries, both
  * of element type dtype. */
 ffx_status ffx_spmv(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,

@@ -4,8 +4,8 @@ The compute path is libffx.so (hand-written HIP kernels behind the C ABI of
 include/ffx.h); `ffx` is its ctypes binding. Importing this package does not
 load the library; the first call does, and raises if it was not built.
 """
-from .ffx import (FORMATS, Batch, FfxError, Matrix, Selector, block_features, build_opts, lib,  # noqa: F401
-                  set_sequence_graph_batch, version)
+from .ffx import (FORMATS, Batch, FfxError, Matrix, Selector, block_features, build_opts, check_block,  # noqa: F401
+                  lib, set_sequence_graph_batch, version)
 
 __all__ = ["Matrix", "Batch", "Selector", "FfxError", "FORMATS", "block_features", "build_opts", "lib",
-           "set_sequence_graph_batch", "version"]
+           "set_sequence_graph_batch", "check_block", "version"]

@@ -428,6 +428,32 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
   });
 }
 
+ffx_status ffx_check_block(uint32_t m, const void* X, int64_t n, int32_t s, int64_t ldx, ffx_dtype dtype,
+                           void* stream, int64_t* first_bad) {
+  return guard([&] {
+    if (first_bad) *first_bad = -1;
+    if (m < 2 || m > 2147483647u) fail(FFX_EINVAL, "modulus %u outside [2, 2^31-1]", m);
+    if (n < 0 || s < 1 || s > MAX_S) fail(FFX_EINVAL, "shape %lld x %d", (long long)n, s);
+    check_dtype(dtype);
+    check_block("X", X, n, s, ldx);
+    if (n == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long* d = nullptr;
+    if (hipMallocAsync((void**)&d, sizeof(unsigned long long), st) != hipSuccess)
+      fail(FFX_ENOMEM, "hipMallocAsync of 8 bytes failed");
+    unsigned long long h = ~0ull;
+    hipError_t e = launch_check_block(dtype, X, n, s, ldx, m, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    (void)hipFreeAsync(d, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    FFX_HIP(e);
+    if (h != ~0ull) {
+      if (first_bad) *first_bad = (int64_t)h;
+      fail(FFX_EINVAL, "entry %llu of the block is not a residue in [0, %u]", h, m - 1);
+    }
+  });
+}
+
 ffx_status ffx_set_sequence_graph_batch(int32_t batch) {
   return guard([&] {
     if (batch < 0 || batch > 4096) fail(FFX_EINVAL, "graph batch %d outside [0, 4096]", batch);

@@ -1,6 +1,8 @@
 // Arithmetic-class dispatch of the tile kernels.
 #pragma once
 
+#include <algorithm>
+
 #include "ffx_impl.h"
 
 namespace ffx {
@@ -58,6 +60,11 @@ hipError_t launch_sequence(int ak, bool only_sell, const DevMat& A, int64_t mte,
 hipError_t launch_transpose_scatter(bool small, const DevMat& A, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
                                     int64_t ldy, int s, uint32_t alpha, uint32_t beta, unsigned long long* acc,
                                     hipStream_t st);
+
+// *first = the smallest flat index k*ldx + c of an entry of the n x s block X
+// outside [0, m-1], or ~0 when there is none (device memory, set by the launch).
+hipError_t launch_check_block(ffx_dtype dt, const void* X, int64_t n, int s, int64_t ldx, uint32_t m,
+                              unsigned long long* first, hipStream_t st);
 
 // Strided copy of an n x s block (ld_in -> ld_out) of dtype elements.
 hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,

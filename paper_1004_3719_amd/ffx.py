@@ -76,6 +76,8 @@ _SIGS = {
     "ffx_power": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
     "ffx_set_sequence_graph_batch": (ctypes.c_int, [ctypes.c_int32]),
+    "ffx_check_block": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "ffx_sequence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_void_p]),
@@ -332,6 +334,19 @@ class Matrix:
                                   ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(W.data_ptr() if W is not None else 0),
                                   _dt(U), _stream(stream)))
         return (S, W) if want_last else S
+
+
+def check_block(X, m, stream=None):
+    """Checked mode: -1 when every entry of the device tensor X (n or n x s, int32/int64) is a residue
+    in [0, m-1], else the smallest flat index k*ld + c of an entry outside it. Bad arguments raise."""
+    n = X.shape[0]
+    p, s, ld = _block(X, n, "X")
+    bad = ctypes.c_int64(-1)
+    st = lib().ffx_check_block(int(m), ctypes.c_void_p(p), n, s, ld, _dt(X), _stream(stream), ctypes.byref(bad))
+    if st == 1 and bad.value >= 0:  # FFX_EINVAL naming an entry: the block is not canonical
+        return bad.value
+    _check(st)
+    return -1
 
 
 def set_sequence_graph_batch(batch):

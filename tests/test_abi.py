@@ -93,3 +93,14 @@ def test_sequence_graph_batch_range():
         P.set_sequence_graph_batch(4097)
     P.set_sequence_graph_batch(0)
     P.set_sequence_graph_batch(64)
+
+
+def test_check_block_argument_errors():
+    L = P.lib()
+    bad = ctypes.c_int64(7)
+    assert L.ffx_check_block(1, None, 0, 1, 1, 0, None, ctypes.byref(bad)) == 1  # modulus
+    assert L.ffx_check_block(65521, None, 10, 1, 1, 0, None, ctypes.byref(bad)) == 1  # NULL block
+    assert L.ffx_check_block(65521, ctypes.c_void_p(16), 10, 4, 2, 0, None, ctypes.byref(bad)) == 1  # ld < s
+    assert L.ffx_check_block(65521, ctypes.c_void_p(16), 10, 1, 1, 7, None, ctypes.byref(bad)) == 1  # dtype
+    assert bad.value == -1
+    assert L.ffx_check_block(65521, None, 0, 1, 1, 0, None, ctypes.byref(bad)) == 0  # empty block

@@ -428,3 +428,22 @@ def test_transpose_without_stored_transpose(dev, orc, ffx, m, fmt, s):
         Yd2 = tdev(Y0, dev, torch.int64)
         M.spmm_t(tdev(X, dev, torch.int64), alpha=5 % m, beta=7 % m, Y=Yd2)
         assert torch.equal(Yd, Yd2)
+
+
+@pytest.mark.parametrize("dt", [torch.int32, torch.int64])
+def test_check_block(dev, dt):
+    """Checked mode finds the first entry outside [0, m-1], through a leading dimension."""
+    from paper_1004_3719_amd import check_block
+    m, n, s, ld = 65521, 5000, 3, 5
+    X = torch.from_numpy(vec(3, 1, n * ld, m).reshape(n, ld)).to(dt).to(dev)
+    note("check block", dt)
+    assert check_block(X[:, :s], m) == -1
+    assert check_block(X[:, 0].contiguous(), m) == -1
+    X[n - 1, ld - 1] = -1  # outside the checked columns: ignored
+    assert check_block(X[:, :s], m) == -1
+    planted = []
+    bad = [(4999, 2, m), (1234, 1, -5), (17, 0, m + 1)] + ([(7, 2, 2**40)] if dt == torch.int64 else [])
+    for (k, c, v) in bad:
+        X[k, c] = v
+        planted.append(k * ld + c)
+        assert check_block(X[:, :s], m) == min(planted), (k, c)
