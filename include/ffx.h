@@ -144,6 +144,15 @@ ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* ou
 
 ffx_status ffx_matrix_destroy(ffx_matrix A);
 
+/* Y <- A X over GF(2) with bit-packed blocks (Section 4 points to compressing
+ * GF(2) vectors into machine words). A must have been built with m = 2, so
+ * every stored entry is 1. X (ncols x w) and Y (nrows x w) are 32-bit words in
+ * device memory with leading dimensions ldx, ldy >= w: bit b of word c of row
+ * j is entry j of vector 32c + b, so one call multiplies A by 32w vectors.
+ * Sums are exclusive ors; Y is overwritten. w in [1, 16]. FFX_EINVAL for
+ * m != 2, a bad w or shape, NULL or overlapping blocks. */
+ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
+
 /* Checked mode. Products take vector entries that are already residues in
  * [0, m-1] (Section 2.2) and do not look at them; this call checks an n x s
  * block X (device memory, element type dtype, leading dimension ldx >= s)

@@ -428,6 +428,21 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
   });
 }
 
+ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream) {
+  return guard([&] {
+    if (!A) fail(FFX_EINVAL, "matrix handle is NULL");
+    if (A->md.m != 2) fail(FFX_EINVAL, "GF(2) product needs a matrix built with m = 2 (m = %u)", A->md.m);
+    if (w < 1 || w > MAX_S) fail(FFX_EINVAL, "w = %d outside [1, %d]", w, MAX_S);
+    const int64_t nin = A->info.ncols, nout = A->info.nrows;
+    check_block("X", X, nin, w, ldx);
+    check_block("Y", Y, nout, w, ldy);
+    check_disjoint("X", X, nin, ldx, "Y", Y, nout, ldy, w, FFX_I32);
+    if (nout == 0) return;
+    const Encoded& E = A->A;
+    FFX_HIP(launch_tiles_gf2(E.dm, E.max_tile_entries, X, ldx, Y, ldy, w, (hipStream_t)stream));
+  });
+}
+
 ffx_status ffx_check_block(uint32_t m, const void* X, int64_t n, int32_t s, int64_t ldx, ffx_dtype dtype,
                            void* stream, int64_t* first_bad) {
   return guard([&] {

@@ -41,6 +41,10 @@ inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype d
   }
 }
 
+// Y = A X over GF(2), X and Y bit-packed blocks of w 32-bit words per row (A built with m = 2).
+hipError_t launch_tiles_gf2(const DevMat& A, int64_t mte, const void* X, int64_t ldx, void* Y, int64_t ldy, int w,
+                            hipStream_t st);
+
 // 16-bit copy of one vector of n residues (stride ldx) for the compact-x path.
 hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st);
 

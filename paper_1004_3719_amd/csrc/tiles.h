@@ -79,6 +79,31 @@ struct ArM31 {
   }
   __device__ static inline Acc from_residue(uint32_t r) { return r; }
 };
+// GF(2) with bit-packed blocks: every 32-bit word of X holds bit j of 32
+// vectors, an entry of A is 1 (m = 2 keeps only residue 1), and a sum over GF(2)
+// is an exclusive or, so one word operation adds 32 products. The accumulator
+// type makes + an exclusive or, so the tile code runs unchanged.
+struct Gf2 {
+  uint32_t v;
+  Gf2() = default;
+  __host__ __device__ Gf2(uint32_t x) : v(x) {}
+  __device__ Gf2& operator+=(Gf2 o) {
+    v ^= o.v;
+    return *this;
+  }
+  __device__ Gf2 operator+(Gf2 o) const { return Gf2(v ^ o.v); }
+};
+using ::atomicAdd;  // the overload below must not hide the runtime's
+__device__ inline void atomicAdd(Gf2* p, Gf2 x) { atomicXor(&p->v, x.v); }
+struct ArGF2 {
+  using ValT = uint16_t;
+  using Acc = Gf2;
+  using Prod = Gf2;
+  static constexpr bool CHUNK = false;
+  __device__ static inline Prod mul(uint32_t v, uint32_t x) { return Gf2((v & 1u) ? x : 0u); }
+  __device__ static inline uint32_t reduce(Acc a, const DevMat&) { return a.v; }
+  __device__ static inline Acc from_residue(uint32_t r) { return Gf2(r); }
+};
 // exact doubles: integers up to 2^53 add exactly.
 template <typename V, bool CH>
 struct ArF64 {
@@ -139,6 +164,7 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask, int width) {
 }
 __device__ inline double shfl_xor_acc(double v, int mask, int width) { return __shfl_xor(v, mask, width); }
 __device__ inline uint64_t shfl_xor_acc(uint64_t v, int mask, int width) { return shfl_xor_u64(v, mask, width); }
+__device__ inline Gf2 shfl_xor_acc(Gf2 v, int mask, int width) { return Gf2((uint32_t)__shfl_xor((int)v.v, mask, width)); }
 
 // stored values are streamed once: non-temporal loads keep them out of the way of x in L2
 template <typename V>

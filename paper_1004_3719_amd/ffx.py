@@ -76,6 +76,8 @@ _SIGS = {
     "ffx_power": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
     "ffx_set_sequence_graph_batch": (ctypes.c_int, [ctypes.c_int32]),
+    "ffx_spmm_gf2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p]),
     "ffx_check_block": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "ffx_sequence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -309,6 +311,22 @@ class Matrix:
 
     def spmm_t(self, X, alpha=1, beta=0, Y=None, stream=None):
         return self._prod("ffx_spmm_t", True, X, alpha, beta, Y, stream)
+
+    def spmm_gf2(self, X, Y=None, stream=None):
+        """Y = A X over GF(2) for a matrix built with m = 2; X is an int32 tensor of ncols x w packed words
+        (bit b of word c of row j = entry j of vector 32c + b)."""
+        import torch
+        inf = self.info()
+        if X.dtype != torch.int32:
+            raise TypeError("GF(2) blocks are int32 tensors of packed words")
+        px, w, ldx = _block(X, inf["ncols"], "X")
+        if Y is None:
+            Y = torch.empty((inf["nrows"], w) if X.dim() == 2 else (inf["nrows"],), dtype=torch.int32, device=X.device)
+        py, wy, ldy = _block(Y, inf["nrows"], "Y")
+        if wy != w:
+            raise ValueError("X and Y have different word counts")
+        _check(lib().ffx_spmm_gf2(self._h, w, ctypes.c_void_p(px), ldx, ctypes.c_void_p(py), ldy, _stream(stream)))
+        return Y
 
     def power(self, k, V, W=None, stream=None):
         import torch

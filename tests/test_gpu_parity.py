@@ -447,3 +447,39 @@ def test_check_block(dev, dt):
         X[k, c] = v
         planted.append(k * ld + c)
         assert check_block(X[:, :s], m) == min(planted), (k, c)
+
+
+def unpack_bits(W):
+    """n x w packed words -> n x 32w bits (vector 32c + b = bit b of word c)."""
+    W = np.ascontiguousarray(W).view(np.uint32)
+    return ((W[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(W.shape[0], -1).astype(np.int64)
+
+
+def pack_bits(B):
+    n = B.shape[0]
+    B = B.reshape(n, -1, 32).astype(np.uint64)
+    return (B << np.arange(32, dtype=np.uint64)).sum(axis=2).astype(np.uint32).view(np.int32)
+
+
+@pytest.mark.parametrize("fmt", [None] + FORMATS)
+@pytest.mark.parametrize("w", [1, 3, 16])
+def test_gf2_packed(dev, orc, ffx, fmt, w):
+    """Y = A X over GF(2) on bit-packed blocks against the oracle applied to the 32w unpacked vectors."""
+    s = synth.spec(6000, 5000, 91 + w, len_kind=synth.LEN_ZIPF, len_a=1, len_b=900, len_alpha=1.6,
+                   col_kind=synth.COL_UNIFORM, band_lo=-2, band_hi=2, p_pm1=0.5, val_lo=-(2**31), val_hi=2**31 - 1)
+    A = synth.rows(s)
+    A.m = 2
+    rng = np.random.default_rng(w)
+    X = rng.integers(-(2**31), 2**31, size=(A.ncols, w), dtype=np.int64).astype(np.int32)
+    note("gf2", fmt, w)
+    M = ffx.from_synth(A, fixed_format=fmt)
+    Y = M.spmm_gf2(torch.from_numpy(X).to(dev)).cpu().numpy()
+    want = pack_bits(orc.spmm(A, unpack_bits(X)))
+    assert np.array_equal(Y, want)
+
+
+def test_gf2_rejects_other_moduli(dev, ffx):
+    A = synth.c1(n=1000)
+    M = ffx.from_synth(A)
+    with pytest.raises(Exception):
+        M.spmm_gf2(torch.zeros((A.ncols, 1), dtype=torch.int32, device=dev))
