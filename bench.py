@@ -231,6 +231,69 @@ def bench_spmv(args, big=True):
     line(A.nnz / (ms * 1e-3), ms, args, args.acc, config, roofline, cpu, extra)
 
 
+# --------------------------------------------------------------------- gf2
+def bench_gf2(args):
+    """The power-law matrix taken mod 2 (odd values become 1, even values vanish), times a block of
+    32*w vectors over GF(2) packed in w 32-bit words per row."""
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix
+
+    dev = torch.device("cuda:0")
+    w = args.gf2_words
+    A = synth.c2()
+    A.m = 2
+    M = Matrix.from_synth(A, selector=args.selector)
+    info = M.info()
+    nnz = info["nnz"]  # entries left after reduction mod 2
+    rng = np.random.default_rng(11)
+    X_np = rng.integers(-(2**31), 2**31, size=(A.ncols, w), dtype=np.int64).astype(np.int32)
+    X = torch.from_numpy(X_np).to(dev)
+    Y = torch.empty((A.nrows, w), dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        M.spmm_gf2(X, Y)
+    torch.cuda.synchronize()
+    ev = event_pairs(args.steps)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        M.spmm_gf2(X, Y)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    vecs = 32 * w
+    b_alg = 4 * nnz + 4 * (A.nrows + 1) + 4 * w * (A.ncols + A.nrows)  # no values over GF(2)
+    achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_tiles (GF(2) packed)",
+                "kernel_ms": round(kernel_ms, 5), "algorithmic_bytes": int(b_alg)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        # a bounded sample: the oracle on the first rows and the 32 vectors of the first word, unpacked
+        rows = 262144
+        sub = synth.rows(synth.c2_spec(), 0, rows)
+        sub.m = 2
+        Xb = ((X_np[:, 0].view(np.uint32)[:, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(np.int64)
+        t1 = time.perf_counter()
+        Yb = orc.spmm(sub, Xb)
+        t_cpu = time.perf_counter() - t1
+        packed = (Yb.astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(axis=1).astype(np.uint32)
+        exact = bool(np.array_equal(packed.view(np.int32), Y[:rows, 0].cpu().numpy()))
+        sub_nnz = int(np.count_nonzero(np.mod(sub.val, 2)))
+        cpu = {"value": round(sub_nnz * 32 / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": "the first %d rows times the 32 vectors of the first word, unpacked (single thread)" % rows,
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+    config = {"workload": "power-law SpMM over GF(2): the 2,000,000-row power-law matrix mod 2 (%d entries) "
+                          "times %d bit-packed vectors (%d words per row)" % (nnz, vecs, w),
+              "n": A.nrows, "nnz": nnz, "vectors": vecs, "formats": info["format_blocks"]}
+    line(nnz * vecs / (ms * 1e-3), ms, args, "u32 (xor)", config, roofline, cpu)
+
+
 # ---------------------------------------------------------------------- c3
 def bench_sequence(args):
     import torch
@@ -463,7 +526,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2"])
+    ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
     ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
                     help="block format chooser: the trained network shipped in the package (falls back to the "
@@ -506,6 +570,8 @@ def main():
         bench_spmv(args, big=False)
     elif args.config == "c3":
         bench_sequence(args)
+    elif args.config == "gf2":
+        bench_gf2(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)
