@@ -34,6 +34,11 @@ enum TileKind : uint32_t {
   TK_SELL = 2,    // up to 4 slices of 64 rows in padded 4-column groups
 };
 constexpr uint32_t TF_SORTED = 1u << 4;  // SELL slots map to rows through perm[]
+// A STREAM tile with a row of more than STREAM_LONG_ROW entries is flagged
+// TF_LONGROWS: with s > 1 vectors a kernel of its own sums its long rows with
+// the whole workgroup instead of one lane.
+constexpr uint32_t TF_LONGROWS = 1u << 5;
+constexpr uint32_t STREAM_LONG_ROW = 64;
 
 constexpr int TILE_THREADS = 256;
 constexpr int WAVE = 64;
@@ -68,12 +73,14 @@ struct DevMat {
   const Tile* tiles;
   const uint32_t* ent;
   const void* val;       // uint16_t or uint32_t, by the modulus
-  const uint32_t* choff; // value offset of each 64-entry chunk
+  const uint32_t* choff; // value offset of each 256-entry chunk
   const uint32_t* rowp;  // STREAM tiles: rows+1 absolute entry offsets per tile
   const uint32_t* perm;  // sorted SELL: slot -> row (0xFFFFFFFF for padding slots)
   const uint32_t* swidth;// SELL: 4-column groups of each slice
   const void* bval;      // band values, diagonal-major inside each tile
   const int32_t* boffs;  // band diagonal offsets (column - row)
+  const uint32_t* ltiles;// STREAM tiles flagged TF_LONGROWS
+  uint32_t nltiles;
   uint32_t ntiles;
   uint32_t nrows, ncols;
   uint32_t m;

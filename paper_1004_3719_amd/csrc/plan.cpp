@@ -262,6 +262,9 @@ void encode_stream(const BlockRows& R, int64_t r0, int64_t nr, uint32_t boff, in
     Tile T{};
     int64_t rows = t - t0;
     T.kind = TK_STREAM | ((uint32_t)R.nd << 8) | ((uint32_t)rows << 16);
+    int64_t longest = 0;
+    for (int64_t q = t0; q < t; ++q) longest = std::max<int64_t>(longest, rlen(q));
+    if (longest > (int64_t)STREAM_LONG_ROW) T.kind |= TF_LONGROWS;
     T.row0 = (uint32_t)(r0 + t0);
     H.align_ent();
     T.e0 = (uint32_t)H.ent.size();
@@ -459,6 +462,10 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   add_part<uint32_t>(offs, total, H.swidth.size());
   size_t o_bval = total; offs.push_back(o_bval); total += (H.bval.size() * vb + 255) / 256 * 256;
   add_part<int32_t>(offs, total, H.boffs.size());
+  std::vector<uint32_t> ltiles;  // STREAM tiles with long rows, for the s > 1 long-row kernel
+  for (size_t t = 0; t < H.tiles.size(); ++t)
+    if (tile_kind(H.tiles[t].kind) == TK_STREAM && (H.tiles[t].kind & TF_LONGROWS)) ltiles.push_back((uint32_t)t);
+  add_part<uint32_t>(offs, total, ltiles.size());
   if (total == 0) total = 256;
   std::vector<unsigned char> host(total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(host.data() + off, src, bytes); };
@@ -477,6 +484,7 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   put(offs[4], H.rowp.data(), H.rowp.size() * 4);
   put(offs[5], H.perm.data(), H.perm.size() * 4);
   put(offs[6], H.swidth.data(), H.swidth.size() * 4);
+  put(offs[9], ltiles.data(), ltiles.size() * 4);
   put(offs[8], H.boffs.data(), H.boffs.size() * 4);
 
   void* dev = nullptr;
@@ -495,6 +503,8 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   dm.swidth = (const uint32_t*)(d + offs[6]);
   dm.bval = (const void*)(d + offs[7]);
   dm.boffs = (const int32_t*)(d + offs[8]);
+  dm.ltiles = (const uint32_t*)(d + offs[9]);
+  dm.nltiles = (uint32_t)ltiles.size();
   dm.ntiles = (uint32_t)H.tiles.size();
   dm.nrows = (uint32_t)A.nrows;
   dm.ncols = (uint32_t)A.ncols;

@@ -603,7 +603,159 @@ __device__ inline void stream_tile_1(const DevMat& A, const Tile& T, const Tx* _
   }
 }
 
-// s > 1 vectors: stage words and values in LDS, one lane per row
+// s > 1 vectors on a tile whose rows are skewed (TF_LONGROWS): a row of up to
+// STREAM_LONG_ROW entries is summed by its own lane, a longer one by the whole
+// workgroup, lane = (slot, component), so a power-law row inside a tile does
+// not serialize on one lane. The workgroup's partial sums of a long row meet
+// through shuffles and LDS atomics.
+
+// LDS of stream_tile_s for a tile of ne entries (see the layout there).
+template <class AR, int S>
+__host__ __device__ inline size_t stream_s_lds_bytes(int64_t ne) {
+  const size_t maxl = (size_t)ne / (STREAM_LONG_ROW + 1) + 1;
+  return (size_t)ne * 8 + 16 + 4 + maxl * 4 + 16 + maxl * S * sizeof(typename AR::Acc);  // with alignment slack
+}
+
+template <class AR, typename Tx, typename Tv, int S>
+__device__ inline void stream_tile_s_long(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
+                                     Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta,
+                                     unsigned char* lds) {
+  using Acc = typename AR::Acc;
+  constexpr uint32_t NW = TILE_THREADS / WAVE;
+  constexpr int U = 2;
+  // LDS: words [ne], values [ne], long-row count, long rows [maxl], their sums [maxl][S]
+  uint32_t* sw = (uint32_t*)lds;
+  uint32_t* sv = sw + T.ne;
+  const uint32_t maxl = T.ne / (STREAM_LONG_ROW + 1) + 1;
+  uint32_t* lcount = (uint32_t*)(((uintptr_t)(sv + T.ne) + 15) & ~(uintptr_t)15);
+  uint32_t* lrows = lcount + 1;
+  Acc* lacc = (Acc*)(((uintptr_t)(lrows + maxl) + 15) & ~(uintptr_t)15);
+  const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const uint32_t nchunks = (T.ne + WCHUNK - 1) / WCHUNK;
+  const uint32_t nr = tile_rows(T.kind);
+  if (tid == 0) *lcount = 0;
+  uint32_t kb = 0, ke = 0;
+  if (tid < nr) {
+    kb = A.rowp[T.aux + tid] - T.e0;
+    ke = A.rowp[T.aux + tid + 1] - T.e0;
+  }
+  for (uint32_t ch0 = wave; ch0 < nchunks; ch0 += NW * U) {
+    uint32_t w[U][WIDE], vo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t ch = ch0 + u * NW, k = ch * WCHUNK + lane * WIDE;
+      u32x4 q = (ch < nchunks && k < T.ne) ? __builtin_nontemporal_load((const u32x4*)(A.ent + T.e0 + k))
+                                           : (u32x4)(PAD_WORD);
+      w[u][0] = q.x;
+      w[u][1] = q.y;
+      w[u][2] = q.z;
+      w[u][3] = q.w;
+      vo[u] = ch < nchunks ? A.choff[T.c0 + ch] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t v[WIDE];
+      load_values4<AR>(A, w[u], vo[u], v);
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        uint32_t e = (ch0 + u * NW) * WCHUNK + lane * WIDE + k;
+        if (e < T.ne) {
+          sw[e] = w[u][k];
+          sv[e] = v[k];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const bool mine = tid < nr;
+  const bool islong = mine && ke - kb > STREAM_LONG_ROW;
+  uint32_t lidx = 0;
+  if (islong) {
+    lidx = atomicAdd(lcount, 1u);
+    lrows[lidx] = tid;
+  }
+  const uint32_t row = T.row0 + tid;
+  if (mine) {
+    LaneAcc<AR, S> acc;
+    acc.init(A);
+    band_terms<AR, Tx, S>(A, T, acc, row, tid, nr, 0, 1, X, ldx, s);
+    if (islong) {  // a long row's sums start from its band part, as residues; the workgroup adds the rest
+      acc.to_residues(A);
+#pragma unroll
+      for (int c = 0; c < S; ++c) lacc[lidx * S + c] = acc.a[c];
+    } else {
+      // EU entries of the row at a time: their gathers are all issued before the
+      // first term is added (16 in flight per lane)
+      constexpr int EU = S >= 16 ? 1 : 16 / S;
+      for (uint32_t k0 = kb; k0 < ke; k0 += EU) {
+        uint32_t w[EU], xv[EU][S];
+#pragma unroll
+        for (int e = 0; e < EU; ++e) {
+          w[e] = k0 + e < ke ? sw[k0 + e] : PAD_WORD;
+          const Tx* xr = X + (int64_t)(w[e] & COL_MASK) * ldx;
+          const bool live = (w[e] >> TAG_SHIFT) != TAG_PAD;
+#pragma unroll
+          for (int c = 0; c < S; ++c) xv[e][c] = (live && c < s) ? (uint32_t)xr[c] : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < EU; ++e) {
+          const uint32_t tag = w[e] >> TAG_SHIFT, v = k0 + e < ke ? sv[k0 + e] : 0u;
+#pragma unroll
+          for (int c = 0; c < S; ++c)
+            if (c < s) acc.a[c] += term<AR>(tag, v, xv[e][c], A.m);
+          acc.tick(A);
+        }
+      }
+      uint32_t r[S];
+#pragma unroll
+      for (int c = 0; c < S; ++c) r[c] = AR::reduce(acc.a[c], A);
+      write_row<Tv, S>(A, Y, ldy, row, r, s, alpha, beta);
+    }
+  }
+  __syncthreads();  // the long-row list and the band sums of long rows are complete
+  const uint32_t nl = *lcount;
+  if (nl) {
+    constexpr uint32_t SLOTS = TILE_THREADS / S;
+    constexpr int EU2 = 4;
+    const uint32_t comp = tid % S, slot = tid / S;
+    const bool cok = (int)comp < s;
+    for (uint32_t q = 0; q < nl; ++q) {
+      const uint32_t r = lrows[q];
+      const uint32_t b = A.rowp[T.aux + r] - T.e0, e = A.rowp[T.aux + r + 1] - T.e0;
+      LaneAcc<AR, 1> pa;
+      pa.init(A);
+      for (uint32_t k0 = b + slot; k0 < e; k0 += SLOTS * EU2) {
+        uint32_t w[EU2], xv[EU2];
+#pragma unroll
+        for (int u = 0; u < EU2; ++u) {
+          const uint32_t k = k0 + u * SLOTS;
+          w[u] = k < e ? sw[k] : PAD_WORD;
+          xv[u] = ((w[u] >> TAG_SHIFT) != TAG_PAD && cok) ? (uint32_t)X[(int64_t)(w[u] & COL_MASK) * ldx + comp] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < EU2; ++u) {
+          const uint32_t k = k0 + u * SLOTS;
+          pa.a[0] += term<AR>(w[u] >> TAG_SHIFT, k < e ? sv[k] : 0u, xv[u], A.m);
+          pa.tick(A);
+        }
+      }
+      pa.to_residues(A);
+      Acc t = pa.a[0];
+      for (int o = S; o < WAVE; o <<= 1) t += shfl_xor_acc(t, o, WAVE);  // the wave's slots of one component
+      if (lane < (uint32_t)S && cok) atomicAdd(&lacc[q * S + comp], t);
+    }
+    __syncthreads();
+    if (islong) {
+      uint32_t r[S];
+#pragma unroll
+      for (int c = 0; c < S; ++c) r[c] = AR::reduce(lacc[lidx * S + c], A);
+      write_row<Tv, S>(A, Y, ldy, row, r, s, alpha, beta);
+    }
+  }
+}
+
+// s > 1 vectors: stage words and values in LDS, one lane per row (correct
+// for every tile; tiles flagged TF_LONGROWS are faster with stream_tile_s_long)
 template <class AR, typename Tx, typename Tv, int S>
 __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* __restrict__ X, int64_t ldx,
                                      Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta,
@@ -701,8 +853,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tiles(DevMat A, const Tx* __re
     case TK_LONG: long_tile<AR, Tx, Tv, S, (S == 1 ? U : 1)>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds); break;
     default:
       if constexpr (S == 1) stream_tile_1<AR, Tx, Tv, U>(A, T, X, ldx, Y, ldy, alpha, beta, lds);
-      else stream_tile_s<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
+      else if (!(T.kind & TF_LONGROWS)) stream_tile_s<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
+      // (flagged tiles, s > 1: k_tiles_long)
   }
+}
+
+// The STREAM tiles flagged TF_LONGROWS, for s > 1 (one workgroup each).
+template <class AR, typename Tx, typename Tv, int S>
+__global__ __launch_bounds__(TILE_THREADS) void k_tiles_long(DevMat A, const Tx* __restrict__ X, int64_t ldx,
+                                                             Tv* __restrict__ Y, int64_t ldy, int s, uint32_t alpha,
+                                                             uint32_t beta) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const Tile T = A.tiles[A.ltiles[blockIdx.x]];
+  stream_tile_s_long<AR, Tx, Tv, S>(A, T, X, ldx, Y, ldy, s, alpha, beta, lds);
 }
 
 template <typename Tv>
@@ -747,7 +910,10 @@ template <class AR>
 inline size_t tiles_lds_bytes(int64_t max_tile_entries, int S) {
   size_t stream = S == 1 ? TILE_THREADS * sizeof(typename AR::Acc) + (TILE_THREADS + 4) * 4 +
                                (size_t)max_tile_entries * sizeof(typename AR::Prod)
-                         : (size_t)max_tile_entries * 8;
+                  : S == 2  ? stream_s_lds_bytes<AR, 2>(max_tile_entries)
+                  : S == 4  ? stream_s_lds_bytes<AR, 4>(max_tile_entries)
+                  : S == 8  ? stream_s_lds_bytes<AR, 8>(max_tile_entries)
+                            : stream_s_lds_bytes<AR, 16>(max_tile_entries);
   size_t red = (size_t)(TILE_THREADS / WAVE) * S * sizeof(typename AR::Acc);
   size_t b = stream > red ? stream : red;
   return b < 16 ? 16 : b;
@@ -795,6 +961,15 @@ hipError_t launch_tiles_t(const DevMat& A, int64_t max_tile_entries, const void*
     case 4: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 4, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
     case 8: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 8, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
     default: hipLaunchKernelGGL((k_tiles<AR, Tv, Tv, 16, 4>), grid, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+  }
+  if (A.nltiles && !nblocks) {  // the flagged tiles the launch above left out
+    dim3 lg(A.nltiles);
+    switch (S) {
+      case 2: hipLaunchKernelGGL((k_tiles_long<AR, Tv, Tv, 2>), lg, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+      case 4: hipLaunchKernelGGL((k_tiles_long<AR, Tv, Tv, 4>), lg, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+      case 8: hipLaunchKernelGGL((k_tiles_long<AR, Tv, Tv, 8>), lg, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+      default: hipLaunchKernelGGL((k_tiles_long<AR, Tv, Tv, 16>), lg, block, lds, st, A, x, ldx, y, ldy, s, alpha, beta); break;
+    }
   }
   return hipGetLastError();
 }
