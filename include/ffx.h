@@ -153,6 +153,18 @@ ffx_status ffx_matrix_destroy(ffx_matrix A);
  * m != 2, a bad w or shape, NULL or overlapping blocks. */
 ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
 
+/* The block-Wiedemann sequence over GF(2) with packed blocks (Section 3,
+ * step 1, with the GF(2) compression of Section 4): S_i = U^T A^i V for
+ * i = 0 .. L-1 and 32w vectors. A: built with m = 2, square. U, V: n x w
+ * words (device, leading dimensions >= w), bit b of word c of row j being
+ * entry j of vector 32c + b. S: L * 32w * w words (device); row a of S_i is
+ * S[(i*32w + a)*w .. +w), bit b of its word c being the parity of the rows
+ * where vector a of U and vector 32c + b of A^i V are both 1. Wlast (n x w,
+ * leading dimension w, or NULL) receives A^L V. w in [1, 16]. Errors as for
+ * ffx_sequence. */
+ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
+                            void* S, void* Wlast, void* stream);
+
 /* Checked mode. Products take vector entries that are already residues in
  * [0, m-1] (Section 2.2) and do not look at them; this call checks an n x s
  * block X (device memory, element type dtype, leading dimension ldx >= s)

@@ -443,6 +443,58 @@ ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, voi
   });
 }
 
+ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu, const void* V, int64_t ldv, int64_t L,
+                            void* S, void* Wlast, void* stream) {
+  return guard([&] {
+    if (!A) fail(FFX_EINVAL, "matrix handle is NULL");
+    if (A->md.m != 2) fail(FFX_EINVAL, "GF(2) sequence needs a matrix built with m = 2 (m = %u)", A->md.m);
+    if (A->info.nrows != A->info.ncols) fail(FFX_EINVAL, "sequence needs a square matrix");
+    if (w < 1 || w > MAX_S) fail(FFX_EINVAL, "w = %d outside [1, %d]", w, MAX_S);
+    if (L < 0) fail(FFX_EINVAL, "L = %lld < 0", (long long)L);
+    const int64_t n = A->info.nrows;
+    const int npairs = 32 * w * w;
+    check_block("U", U, n, w, ldu);
+    check_block("V", V, n, w, ldv);
+    if (L > 0 && !S) fail(FFX_EINVAL, "S is NULL");
+    if (Wlast) {
+      check_disjoint("V", V, n, ldv, "Wlast", Wlast, n, w, w, FFX_I32);
+      check_disjoint("U", U, n, ldu, "Wlast", Wlast, n, w, w, FFX_I32);
+      if (L > 0) check_disjoint("S", S, L * 32 * w, w, "Wlast", Wlast, n, w, w, FFX_I32);
+    }
+    if (L > 0) {
+      check_disjoint("U", U, n, ldu, "S", S, L * 32 * w, w, w, FFX_I32);
+      check_disjoint("V", V, n, ldv, "S", S, L * 32 * w, w, w, FFX_I32);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {  // empty sums
+      if (L > 0) FFX_HIP(hipMemsetAsync(S, 0, (size_t)L * npairs * 4, st));
+      return;
+    }
+    if (L == 0) {
+      if (Wlast) FFX_HIP(launch_copy_block(FFX_I32, V, ldv, Wlast, w, n, w, st));
+      return;
+    }
+    warm_pool(st);
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, std::max(64, 65536 / npairs)));
+    size_t wbytes = (size_t)n * w * 4;
+    void* ws[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[4] = {wbytes, wbytes, wbytes, (size_t)G * npairs * 4};
+    for (int q = 0; q < 4; ++q)
+      if (hipMallocAsync(&ws[q], sizes[q], st) != hipSuccess) {
+        for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
+        fail(FFX_ENOMEM, "GF(2) sequence workspace allocation failed");
+      }
+    hipError_t e = launch_copy_block(FFX_I32, U, ldu, ws[0], w, n, w, st);
+    if (e == hipSuccess) e = launch_copy_block(FFX_I32, V, ldv, ws[1], w, n, w, st);
+    const Encoded& E = A->A;
+    if (e == hipSuccess)
+      e = launch_sequence_gf2(E.dm, E.max_tile_entries, w, (const uint32_t*)ws[0], (const uint32_t*)ws[1], L,
+                              (uint32_t*)S, (uint32_t*)ws[2], (uint32_t*)ws[3], G, (uint32_t*)Wlast, st);
+    for (void* p : ws) (void)hipFreeAsync(p, st);
+    FFX_HIP(e);
+  });
+}
+
 ffx_status ffx_check_block(uint32_t m, const void* X, int64_t n, int32_t s, int64_t ldx, ffx_dtype dtype,
                            void* stream, int64_t* first_bad) {
   return guard([&] {

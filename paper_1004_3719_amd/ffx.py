@@ -76,6 +76,9 @@ _SIGS = {
     "ffx_power": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
     "ffx_set_sequence_graph_batch": (ctypes.c_int, [ctypes.c_int32]),
+    "ffx_sequence_gf2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     "ffx_spmm_gf2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_void_p]),
     "ffx_check_block": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
@@ -327,6 +330,25 @@ class Matrix:
             raise ValueError("X and Y have different word counts")
         _check(lib().ffx_spmm_gf2(self._h, w, ctypes.c_void_p(px), ldx, ctypes.c_void_p(py), ldy, _stream(stream)))
         return Y
+
+    def sequence_gf2(self, U, V, L, want_last=False, stream=None):
+        """S_i = U^T A^i V over GF(2), i < L, for int32 tensors U, V of n x w packed words; returns S as an
+        L x 32w x w int32 tensor (and A^L V)."""
+        import torch
+        n = self.info()["nrows"]
+        for t in (U, V):
+            if t.dtype != torch.int32:
+                raise TypeError("GF(2) blocks are int32 tensors of packed words")
+        pu, w, ldu = _block(U, n, "U")
+        pv, wv, ldv = _block(V, n, "V")
+        if wv != w:
+            raise ValueError("U and V have different word counts")
+        S = torch.empty((int(L), 32 * w, w), dtype=torch.int32, device=V.device)
+        W = torch.empty((n, w), dtype=torch.int32, device=V.device) if want_last else None
+        _check(lib().ffx_sequence_gf2(self._h, w, ctypes.c_void_p(pu), ldu, ctypes.c_void_p(pv), ldv, int(L),
+                                      ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(W.data_ptr() if W is not None else 0),
+                                      _stream(stream)))
+        return (S, W) if want_last else S
 
     def power(self, k, V, W=None, stream=None):
         import torch

@@ -483,3 +483,28 @@ def test_gf2_rejects_other_moduli(dev, ffx):
     M = ffx.from_synth(A)
     with pytest.raises(Exception):
         M.spmm_gf2(torch.zeros((A.ncols, 1), dtype=torch.int32, device=dev))
+
+
+@pytest.mark.parametrize("w", [1, 2, 3])
+@pytest.mark.parametrize("kind", ["c3", "powerlaw"])
+def test_gf2_sequence(dev, orc, ffx, w, kind):
+    """S_i = U^T A^i V over GF(2) on packed blocks against the oracle on the 32w unpacked vectors, with
+    A^L V."""
+    if kind == "c3":
+        A = synth.c3(n=1500, ndead=10, m=2)
+    else:
+        s = synth.spec(1500, 1500, 17 + w, len_kind=synth.LEN_ZIPF, len_a=1, len_b=700, len_alpha=1.5,
+                       col_kind=synth.COL_UNIFORM, band_lo=-1, band_hi=1, p_pm1=0.5, val_lo=0, val_hi=2**20)
+        A = synth.rows(s)
+        A.m = 2
+    rng = np.random.default_rng(40 + w)
+    U = rng.integers(-(2**31), 2**31, size=(A.nrows, w), dtype=np.int64).astype(np.int32)
+    V = rng.integers(-(2**31), 2**31, size=(A.nrows, w), dtype=np.int64).astype(np.int32)
+    L = 12
+    note("gf2 sequence", kind, w)
+    M = ffx.from_synth(A)
+    S, W = M.sequence_gf2(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), L, want_last=True)
+    So, Wo = orc.sequence(A, unpack_bits(U), unpack_bits(V), L, want_last=True)
+    want = np.stack([pack_bits(So[i]) for i in range(L)])
+    assert np.array_equal(S.cpu().numpy(), want)
+    assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
