@@ -294,6 +294,56 @@ def bench_gf2(args):
     line(nnz * vecs / (ms * 1e-3), ms, args, "u32 (xor)", config, roofline, cpu)
 
 
+def bench_gf2_sequence(args):
+    """The block-Wiedemann sequence over GF(2): the 200,000-row operand of the sequence workload taken
+    mod 2 (every entry 1), 32w packed vectors, L = 2n/(32w) + 3 terms."""
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix
+
+    dev = torch.device("cuda:0")
+    w = args.gf2_words
+    vecs = 32 * w
+    A = synth.c3(m=2)
+    n = A.nrows
+    L = args.seq_length or (2 * n) // vecs + 3
+    M = Matrix.from_synth(A)
+    rng = np.random.default_rng(12)
+    U_np = rng.integers(-(2**31), 2**31, size=(n, w), dtype=np.int64).astype(np.int32)
+    V_np = rng.integers(-(2**31), 2**31, size=(n, w), dtype=np.int64).astype(np.int32)
+    U, V = torch.from_numpy(U_np).to(dev), torch.from_numpy(V_np).to(dev)
+    M.sequence_gf2(U, V, 4)
+    torch.cuda.synchronize()
+    a, b = event_pairs(1)[0]
+    a.record()
+    S = M.sequence_gf2(U, V, L)
+    b.record()
+    torch.cuda.synchronize()
+    ev_ms = a.elapsed_time(b)
+    nnz = M.info()["nnz"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        ub = ((U_np.view(np.uint32)[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(n, -1)
+        vb = ((V_np.view(np.uint32)[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(n, -1)
+        Lc = 4
+        t1 = time.perf_counter()
+        So = orc.sequence(A, ub.astype(np.int64), vb.astype(np.int64), Lc)
+        t_cpu = time.perf_counter() - t1
+        packed = np.stack([(So[i].reshape(vecs, w, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64))
+                           .sum(axis=2).astype(np.uint32).view(np.int32) for i in range(Lc)])
+        exact = bool(np.array_equal(packed, S[:Lc].cpu().numpy()))
+        cpu = {"value": round(nnz * vecs * Lc / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": "sequence prefix i = 0..%d at full size, %d unpacked vectors (single thread)" % (Lc - 1, vecs),
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+    config = {"workload": "block-Wiedemann sequence over GF(2): n=200,000, 15 nnz/row (all 1), %d packed vectors, "
+                          "L=%d" % (vecs, L), "n": n, "nnz": nnz, "vectors": vecs, "L": L}
+    args.steps, args.warmup = L, 1
+    line(nnz * vecs * L / (ev_ms * 1e-3), ev_ms / L, args, "u32 (xor)", config, None, cpu)
+
+
 # ---------------------------------------------------------------------- c3
 def bench_sequence(args):
     import torch
@@ -526,7 +576,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq"])
     ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
     ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
@@ -572,6 +622,8 @@ def main():
         bench_sequence(args)
     elif args.config == "gf2":
         bench_gf2(args)
+    elif args.config == "gf2seq":
+        bench_gf2_sequence(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)

@@ -475,7 +475,7 @@ ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu,
       return;
     }
     warm_pool(st);
-    const int G = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, std::max(64, 65536 / npairs)));
+    const int G = (int)((n + 255) / 256);  // 256 rows per projection workgroup
     size_t wbytes = (size_t)n * w * 4;
     void* ws[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t sizes[4] = {wbytes, wbytes, wbytes, (size_t)G * npairs * 4};

@@ -46,7 +46,8 @@ hipError_t launch_tiles_gf2(const DevMat& A, int64_t mte, const void* X, int64_t
                             hipStream_t st);
 
 // S_i = U^T A^i W0 over GF(2) for i < L (L >= 1), packed blocks of w words per row (ld w); S holds
-// L * 32w * w words. Workspace: w1 (n x w words), part (G * 32w * w words); W0 is overwritten.
+// L * 32w * w words. Workspace: w1 (n x w words), part (G * 32w * w words, G = ceil(n / 256)); W0 is
+// overwritten.
 // Wlast (n x w, or null) receives A^L W0.
 hipError_t launch_sequence_gf2(const DevMat& A, int64_t mte, int w, const uint32_t* U, const uint32_t* W0, int64_t L,
                                uint32_t* S, uint32_t* w1, uint32_t* part, int G, uint32_t* Wlast, hipStream_t st);
