@@ -232,7 +232,7 @@ def test_sequence_graph_batch(dev, orc, ffx, graph_batch):
 
 def test_sequence_prefix_full_size(dev, orc, ffx):
     """The block-Wiedemann operand at full size (n = 200,000, s = 8, m = 2^31-1): the first 6
-    sequence terms and a 4-term segment restarted from the GPU's own A^6 V."""
+    sequence terms and A^6 V, then a 4-term sequence started from the oracle's own A^6 V."""
     A = synth.c3()
     U, V = synth.c3_blocks()
     note("sequence full-size prefix")
@@ -241,9 +241,8 @@ def test_sequence_prefix_full_size(dev, orc, ffx):
     So, Wo = orc.sequence(A, U, V, 6, want_last=True)
     assert np.array_equal(S.cpu().numpy(), So)
     assert np.array_equal(W.cpu().numpy(), Wo)
-    W6 = W.cpu().numpy()
-    S2 = M.sequence(tdev(U, dev, torch.int64), W, 4).cpu().numpy()
-    assert np.array_equal(S2, orc.sequence(A, U, W6, 4))
+    S2 = M.sequence(tdev(U, dev, torch.int64), tdev(Wo, dev, torch.int64), 4).cpu().numpy()
+    assert np.array_equal(S2, orc.sequence(A, U, Wo, 4))
 
 
 @pytest.mark.parametrize("m", [2**31 - 1, 2**31 - 19, 3_000_017])
@@ -268,10 +267,11 @@ def test_sequence_projection_bound(dev, orc, ffx, m, s):
 
 
 def test_sequence_full_size_checkpoints(dev, orc, ffx):
-    """The block-Wiedemann operand at full size over a long run: the first 48 terms against the oracle,
-    then 16-term oracle segments restarted from the GPU's own iterates W_c at c = 4,096 and 12,288
-    (graph replays of 64 steps, their counter and the parity of every buffer all cycle many times
-    before a checkpoint)."""
+    """The block-Wiedemann operand at full size over a long run: the first 48 terms against the oracle;
+    then, at c = 4,096 and 12,288 (graph replays of 64 steps, their counter and the parity of every
+    buffer have cycled many times), the terms c .. c+15 of the long run must equal a 16-term sequence
+    started from A^c V computed by the separate power path (the product kernels, c launches): a
+    property of the sequence, checked between two GPU paths, no GPU value enters the oracle."""
     A = synth.c3()
     U, V = synth.c3_blocks()
     note("sequence full-size checkpoints")
@@ -280,10 +280,10 @@ def test_sequence_full_size_checkpoints(dev, orc, ffx):
     S = M.sequence(Ud, Vd, 48).cpu().numpy()
     assert np.array_equal(S, orc.sequence(A, U, V, 48))
     for c in (4096, 12288):
-        Sc = M.sequence(Ud, Vd, c + 16)
-        _, Wc = M.sequence(Ud, Vd, c, want_last=True)
-        seg = orc.sequence(A, U, Wc.cpu().numpy(), 16)
-        assert np.array_equal(Sc.cpu().numpy()[c:c + 16], seg), c
+        Sc = M.sequence(Ud, Vd, c + 16).cpu().numpy()
+        Wc = M.power(c, Vd)
+        seg = M.sequence(Ud, Wc, 16).cpu().numpy()
+        assert np.array_equal(Sc[c:c + 16], seg), c
 
 
 # ---------------------------------------------------------- edge cases -----
