@@ -364,10 +364,10 @@ def test_c2_full_size_sampled(dev, orc, ffx):
     rows = np.unique(np.concatenate([rng.choice(A.nrows, 4000, replace=False), np.argsort(lens)[-200:],
                                      np.arange(10), np.arange(A.nrows - 10, A.nrows)]))
     want = orc.spmv(subrows(A, rows), x)
-    for acc in ["int64", "fp64"]:
-        M = ffx.from_synth(A, acc=acc)
+    for acc, sel in [("int64", "learned"), ("int64", "heuristic"), ("fp64", "heuristic")]:
+        M = ffx.from_synth(A, acc=acc, selector=sel)  # learned: the packaged model, as the benchmark runs
         got = M.spmv(tdev(x, dev)).cpu().numpy()
-        assert np.array_equal(got[rows], want), acc
+        assert np.array_equal(got[rows], want), (acc, sel)
         assert got.min() >= 0 and got.max() < A.m
         M.close()
 
