@@ -17,7 +17,9 @@ Other configurations print the same kind of line:
   c4  256 uneven matrices with 1..16 right-hand sides, one persistent batched
       launch (tuned) against back-to-back per-matrix launches;
   c5  learned format selection: train on measured block timings, evaluate the
-      whole-product time on held-out matrices against the plain heuristic.
+      whole-product time on held-out matrices against the plain heuristic;
+  acc the accumulators (int64, fp64, fp32, centered fp32 and fp64) on the
+      power-law matrix with m = 4093, times 1, 8 and 16 vectors.
 """
 import argparse
 import hashlib
@@ -229,6 +231,63 @@ def bench_spmv(args, big=True):
     config = {"workload": workload, "n": A.nrows, "nnz": A.nnz, "m": m, "acc": args.acc, "selector": args.selector,
               "formats": info["format_blocks"], "kernel_hash": khash}
     line(A.nnz / (ms * 1e-3), ms, args, args.acc, config, roofline, cpu, extra)
+
+
+# ------------------------------------------------------------ accumulators
+ACC_NAMES = ["int64", "fp64", "fp32", "fp32c", "fp64c"]
+
+
+def bench_accumulators(args):
+    """The float/double trade-off of the delayed reduction: the power-law matrix with m = 4093, where
+    every accumulator applies (fp32 reduces after each term there, centered fp32 after four, the
+    others once per row), times 1, 8 and 16 vectors, per accumulator. The line's value is the
+    one-vector product of --acc."""
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix
+
+    dev = torch.device("cuda:0")
+    m = 4093
+    A = synth.c2(m=m)
+    stream = torch.cuda.current_stream()
+    table, ms_main, khash = {}, None, kernel_hash()
+    for acc in ACC_NAMES:
+        M = Matrix.from_synth(A, acc=acc, selector=args.selector, model_path=args.model)
+        info = M.info()
+        row = {"reduce_every": info["reduce_every"]}
+        for s_ in (1, 8, 16):
+            X = torch.from_numpy(synth.vector(synth.SEED0 + 1, 30 + s_, A.ncols * s_, 0, m - 1)
+                                 .astype(np.int32).reshape(A.ncols, s_)).to(dev)
+            Y = torch.empty((A.nrows, s_), dtype=torch.int32, device=dev)
+            steps = args.steps if s_ == 1 else max(5, args.steps // 8)
+            run = (lambda: M.spmv(X[:, 0], y=Y[:, 0])) if s_ == 1 else (lambda: M.spmm(X, Y=Y))
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize()
+            ev = event_pairs(steps)
+            for i in range(steps):
+                ev[i][0].record(stream)
+                run()
+                ev[i][1].record(stream)
+            torch.cuda.synchronize()
+            k_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+            row["s%d_ms" % s_] = round(k_ms, 5)
+            row["s%d_Gnnz_vec_per_s" % s_] = round(A.nnz * s_ / (k_ms * 1e-3) / 1e9, 1)
+            if s_ == 1 and acc == args.acc:
+                ms_main = k_ms
+        table[acc] = row
+        log("acc %s: %s" % (acc, row))
+        M.close()
+    b_alg = algorithmic_bytes(A, m)
+    achieved = b_alg / (ms_main * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_to_u16 + k_tiles",
+                "kernel_ms": round(ms_main, 5), "algorithmic_bytes": int(b_alg)}
+    config = {"workload": "accumulator trade-off: the 2,000,000-row power-law matrix with m = 4093 (every "
+                          "accumulator applies) times 1, 8 and 16 vectors", "n": A.nrows, "nnz": A.nnz, "m": m,
+              "acc": args.acc, "selector": args.selector, "kernel_hash": khash}
+    line(A.nnz / (ms_main * 1e-3), ms_main, args, args.acc, config, roofline, None, {"accumulators": table})
 
 
 # --------------------------------------------------------------------- gf2
@@ -576,9 +635,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc"])
     ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
-    ap.add_argument("--acc", default="int64", choices=["int64", "fp64"])
+    ap.add_argument("--acc", default="int64", choices=ACC_NAMES)
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
                     help="block format chooser: the trained network shipped in the package (falls back to the "
                          "heuristic if the model is missing) or the plain heuristic")
@@ -624,6 +683,8 @@ def main():
         bench_gf2(args)
     elif args.config == "gf2seq":
         bench_gf2_sequence(args)
+    elif args.config == "acc":
+        bench_accumulators(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)

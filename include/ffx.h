@@ -56,9 +56,23 @@ typedef enum { FFX_I32 = 0, FFX_I64 = 1 } ffx_dtype;
  * a wide type and reduced modulo m only when the next term could exceed what
  * the type holds exactly. INT64: unsigned 64-bit integers, at most
  * 2^63 - 1 before a reduction. FP64: doubles, at most 2^53 - 1 (every
- * integer up to 2^53 is exact); refused with FFX_EBOUND when (m-1)^2 alone
- * does not fit. AUTO: INT64. */
-typedef enum { FFX_ACC_AUTO = 0, FFX_ACC_INT64 = 1, FFX_ACC_FP64 = 2 } ffx_acc;
+ * integer up to 2^53 is exact). FP32: floats, at most 2^24 - 1 (m <= 4096).
+ * The CENTERED variants (Section 2.2, the ring represented on
+ * [-floor((m-1)/2), ceil((m-1)/2)]) use every operand as a residue of
+ * magnitude at most floor(m/2), so a product is about a quarter of (m-1)^2
+ * and sums of both signs stay exact up to 2^53 - 1 (m <= 189,812,531) or
+ * 2^24 - 1 (m <= 8191) in magnitude: about four times as many terms between
+ * reductions. Inputs and results stay canonical residues in [0, m-1] for
+ * every accumulator. A floating accumulator that cannot hold one product
+ * exactly is refused with FFX_EBOUND. AUTO: INT64. */
+typedef enum {
+  FFX_ACC_AUTO = 0,
+  FFX_ACC_INT64 = 1,
+  FFX_ACC_FP64 = 2,
+  FFX_ACC_FP32 = 3,
+  FFX_ACC_FP64_CENTERED = 4,
+  FFX_ACC_FP32_CENTERED = 5
+} ffx_acc;
 
 /* Who chooses each row block's storage format (Section 2.4 "Heuristic format
  * chooser"): the plain heuristic, the learned cost model (falls back to the
@@ -100,7 +114,7 @@ typedef struct ffx_matrix_s* ffx_matrix;
 typedef struct {
   int64_t nrows, ncols;
   uint32_t m;
-  int32_t acc;              /* accumulator actually used (FFX_ACC_INT64 or FFX_ACC_FP64) */
+  int32_t acc;              /* accumulator actually used (ffx_acc, never FFX_ACC_AUTO) */
   int64_t nnz_input;        /* entries given to the create call */
   int64_t nnz;              /* stored nonzero residues after merging duplicates and dropping zeros */
   int64_t n_plus, n_minus;  /* entries stored without a value (residue 1 and m-1) */

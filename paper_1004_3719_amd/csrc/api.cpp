@@ -52,6 +52,12 @@ static int arith_kind(const ffx_matrix_s& M) {
     if (small) return M.chunk ? AK_F64_16_CH : AK_F64_16;
     return M.chunk ? AK_F64_32_CH : AK_F64_32;
   }
+  if (M.acc == FFX_ACC_FP64_CENTERED) {
+    if (small) return M.chunk ? AK_F64C_16_CH : AK_F64C_16;
+    return M.chunk ? AK_F64C_32_CH : AK_F64C_32;
+  }
+  if (M.acc == FFX_ACC_FP32) return M.chunk ? AK_F32_CH : AK_F32;
+  if (M.acc == FFX_ACC_FP32_CENTERED) return M.chunk ? AK_F32C_CH : AK_F32C;
   if (small) return AK_SMALL;
   if (M.md.m == 2147483647u) return AK_M31;
   return M.chunk ? AK_BIG_CH : AK_BIG;
@@ -82,7 +88,7 @@ static PlanOpts plan_opts(const ffx_build_opts* o) {
     d.size = sizeof(ffx_build_opts);
   }
   PlanOpts p;
-  if (d.acc < FFX_ACC_AUTO || d.acc > FFX_ACC_FP64) fail(FFX_EINVAL, "accumulator %d", d.acc);
+  if (d.acc < FFX_ACC_AUTO || d.acc > FFX_ACC_FP32_CENTERED) fail(FFX_EINVAL, "accumulator %d", d.acc);
   p.acc = d.acc == FFX_ACC_AUTO ? FFX_ACC_INT64 : d.acc;
   if (d.selector < FFX_SEL_HEURISTIC || d.selector > FFX_SEL_FIXED) fail(FFX_EINVAL, "selector %d", d.selector);
   p.selector = d.selector;
@@ -117,21 +123,47 @@ static void warm_pool(hipStream_t st) {
   (void)st;
 }
 
+// Delayed-reduction bound (Section 2.2): the number of terms that can be
+// added to a reduced accumulator while every partial sum stays exact.
+// Canonical operands lie in [0, m-1]: a term is at most (m-1)^2 (or m, the
+// term m - 0 of an entry of residue m-1), a reduced accumulator at most m-1,
+// and sums must stay at most 2^63 - 1 (int64) or 2^p - 1 (p = 53 for doubles,
+// 24 for floats: every integer up to 2^p is exact). Centered operands lie in
+// [-h, h], h = floor(m/2): a term is at most h^2 in magnitude and sums of both
+// signs stay exact while their magnitude is at most 2^p - 1. Partial sums of
+// up to 257 reduced lanes also meet before the final reduction; the bound
+// covers them whenever it is at least 1 (257 * rmax <= rmax + tmax for rmax
+// >= 256, and 257 * 255 < 2^24 otherwise).
+static int64_t reduce_bound(int acc, uint32_t m) {
+  const bool centered = acc == FFX_ACC_FP64_CENTERED || acc == FFX_ACC_FP32_CENTERED;
+  const uint64_t rmax = centered ? m >> 1 : (uint64_t)m - 1;
+  const uint64_t tmax = std::max<uint64_t>(rmax * rmax, centered ? rmax : m);
+  uint64_t limit = (uint64_t)INT64_MAX;
+  if (acc == FFX_ACC_FP64 || acc == FFX_ACC_FP64_CENTERED) limit = ((uint64_t)1 << 53) - 1;
+  if (acc == FFX_ACC_FP32 || acc == FFX_ACC_FP32_CENTERED) limit = ((uint64_t)1 << 24) - 1;
+  return terms_before_reduce(limit, rmax, tmax);
+}
+
+static const char* acc_name(int acc) {
+  switch (acc) {
+    case FFX_ACC_INT64: return "INT64";
+    case FFX_ACC_FP64: return "FP64";
+    case FFX_ACC_FP32: return "FP32";
+    case FFX_ACC_FP64_CENTERED: return "centered FP64";
+    default: return "centered FP32";
+  }
+}
+
 static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts, int build_t, hipStream_t st) {
   PlanOpts po = plan_opts(opts);
   ffx_matrix_s* M = new ffx_matrix_s();
   try {
     M->md = make_modulus(m);
     M->acc = po.acc;
-    // delayed-reduction bound (Section 2.2): terms are at most tmax, a reduced
-    // accumulator is at most m-1, and the sum must stay representable
-    const uint64_t mm1 = (uint64_t)m - 1;
-    const uint64_t tmax = std::max<uint64_t>(mm1 * mm1, m);
-    const uint64_t limit = po.acc == FFX_ACC_FP64 ? ((uint64_t)1 << 53) - 1 : (uint64_t)INT64_MAX;
-    int64_t b = terms_before_reduce(limit, m, tmax);
+    const int64_t b = reduce_bound(po.acc, m);
     if (b < 1)
-      fail(FFX_EBOUND, "FP64 accumulator cannot hold (m-1)^2 = %llu exactly (needs < 2^53); use FFX_ACC_INT64",
-           (unsigned long long)(mm1 * mm1));
+      fail(FFX_EBOUND, "the %s accumulator cannot hold one product of residues modulo %u exactly",
+           acc_name(po.acc), m);
     encode(A, M->md, po, st, &M->A);
     int64_t maxterms = M->A.max_row_terms;
     if (build_t) {

@@ -121,7 +121,15 @@ static hipError_t batch_launch_class(int ak, ffx_dtype dt, int cls, const DevMat
     case AK_F64_16: go(ArF64<uint16_t, false>{}); break;
     case AK_F64_16_CH: go(ArF64<uint16_t, true>{}); break;
     case AK_F64_32: go(ArF64<uint32_t, false>{}); break;
-    default: go(ArF64<uint32_t, true>{}); break;
+    case AK_F64_32_CH: go(ArF64<uint32_t, true>{}); break;
+    case AK_F32: go(ArF32<false>{}); break;
+    case AK_F32_CH: go(ArF32<true>{}); break;
+    case AK_F32C: go(ArCentered<float, uint16_t, false>{}); break;
+    case AK_F32C_CH: go(ArCentered<float, uint16_t, true>{}); break;
+    case AK_F64C_16: go(ArCentered<double, uint16_t, false>{}); break;
+    case AK_F64C_16_CH: go(ArCentered<double, uint16_t, true>{}); break;
+    case AK_F64C_32: go(ArCentered<double, uint32_t, false>{}); break;
+    default: go(ArCentered<double, uint32_t, true>{}); break;
   }
   return hipGetLastError();
 }

@@ -86,6 +86,7 @@ struct DevMat {
   uint32_t m;
   uint64_t mu;           // floor((2^64-1)/m), for Barrett reduction
   double inv_m;          // 1/m rounded, for the fp64 path
+  float inv_mf;          // 1/m rounded to float, for the fp32 paths
   int64_t reduce_every;  // terms summed between two reductions
 };
 
@@ -128,6 +129,42 @@ __host__ __device__ inline uint32_t mod_f64(double a, uint32_t m, double inv_m) 
   return (uint32_t)r;
 }
 
+// a mod m for an integer-valued float 0 <= a <= 2^24 (m <= 8191): as in
+// mod_f64, with a quotient estimate within 1 of the floor (a/m * 2^-23 < 1)
+// and one correction each way.
+__host__ __device__ inline uint32_t mod_f32(float a, uint32_t m, float inv_m) {
+  float q = floorf(a * inv_m);
+  float md = (float)m;
+  float r = fmaf(-q, md, a);
+  if (r < 0) r += md;
+  if (r >= md) r -= md;
+  return (uint32_t)r;
+}
+
+// Centered remainder (Section 2.2, the representation on
+// [-floor((m-1)/2), ceil((m-1)/2)]): for an integer-valued a with |a| at most
+// 2^53 (double) or 2^24 (float), returns the r = a (mod m) with
+// -h <= r <= h, h = floor(m/2) = ceil((m-1)/2). The nearest-integer quotient
+// estimate is within 1 of the true nearest quotient, so |a - q*m| <= h + m is
+// an exact integer that one fma computes exactly and one correction each way
+// brings into [-h, h].
+__host__ __device__ inline double crem_f64(double a, uint32_t m, double inv_m) {
+  double md = (double)m, h = (double)(m >> 1);
+  double q = rint(a * inv_m);
+  double r = fma(-q, md, a);
+  if (r > h) r -= md;
+  if (r < -h) r += md;
+  return r;
+}
+__host__ __device__ inline float crem_f32(float a, uint32_t m, float inv_m) {
+  float md = (float)m, h = (float)(m >> 1);
+  float q = rintf(a * inv_m);
+  float r = fmaf(-q, md, a);
+  if (r > h) r -= md;
+  if (r < -h) r += md;
+  return r;
+}
+
 // (alpha*r + beta*y) mod m with every operand in [0, m): both products are
 // below 2^62, so their sum fits 64 bits.
 __host__ __device__ inline uint32_t axpby(uint32_t alpha, uint32_t r, uint32_t beta, uint32_t y, uint32_t m,
@@ -135,11 +172,12 @@ __host__ __device__ inline uint32_t axpby(uint32_t alpha, uint32_t r, uint32_t b
   return mod_u64((uint64_t)alpha * r + (uint64_t)beta * y, m, mu);
 }
 
-// The largest number of terms, each at most tmax, that can be added to a
-// residue (<= m-1) while the sum stays <= limit.
-__host__ __device__ inline int64_t terms_before_reduce(uint64_t limit, uint64_t m, uint64_t tmax) {
-  if (limit < m - 1) return 0;
-  return (int64_t)((limit - (m - 1)) / tmax);
+// The largest number of terms, each at most tmax in magnitude, that can be
+// added to a reduced accumulator (magnitude at most rmax) while the sum stays
+// at most limit in magnitude.
+__host__ __device__ inline int64_t terms_before_reduce(uint64_t limit, uint64_t rmax, uint64_t tmax) {
+  if (limit < rmax) return 0;
+  return (int64_t)((limit - rmax) / tmax);
 }
 
 }  // namespace ffx

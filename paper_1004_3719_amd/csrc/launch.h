@@ -10,8 +10,12 @@ namespace ffx {
 // Accumulator classes (see tiles.h): integer for m <= 65536; 64-bit integer
 // for larger m, with or without reductions inside a row; exact doubles with
 // 16- or 32-bit stored values, with or without reductions inside a row; the
-// folding integer class of m = 2^31 - 1.
-enum ArithKind { AK_SMALL = 0, AK_BIG, AK_BIG_CH, AK_F64_16, AK_F64_16_CH, AK_F64_32, AK_F64_32_CH, AK_M31, AK_COUNT };
+// folding integer class of m = 2^31 - 1; exact floats (m <= 4096); centered
+// floats and doubles.
+enum ArithKind {
+  AK_SMALL = 0, AK_BIG, AK_BIG_CH, AK_F64_16, AK_F64_16_CH, AK_F64_32, AK_F64_32_CH, AK_M31,
+  AK_F32, AK_F32_CH, AK_F32C, AK_F32C_CH, AK_F64C_16, AK_F64C_16_CH, AK_F64C_32, AK_F64C_32_CH, AK_COUNT
+};
 
 hipError_t launch_tiles_small(const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
                               int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
@@ -23,6 +27,18 @@ hipError_t launch_tiles_big(int ak, const DevMat& A, int64_t mte, ffx_dtype dt, 
 hipError_t launch_tiles_f64(bool v16, bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X,
                             int64_t ldx, void* Y, int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st,
                             const uint16_t* x16, uint32_t nblocks);
+hipError_t launch_tiles_f32(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
+                           int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                           uint32_t nblocks);
+hipError_t launch_tiles_f32c(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
+                            int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                            uint32_t nblocks);
+hipError_t launch_tiles_f64c16(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
+                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                              uint32_t nblocks);
+hipError_t launch_tiles_f64c32(bool chunk, const DevMat& A, int64_t mte, ffx_dtype dt, const void* X, int64_t ldx, void* Y,
+                              int64_t ldy, int s, uint32_t alpha, uint32_t beta, hipStream_t st, const uint16_t* x16,
+                              uint32_t nblocks);
 
 // x16: a 16-bit copy of X (only for s = 1 and m <= 65536), or null. nblocks:
 // the grid size (0: one workgroup per tile; larger grids repeat the tiles).
@@ -37,7 +53,16 @@ inline hipError_t launch_tiles(int ak, const DevMat& A, int64_t mte, ffx_dtype d
     case AK_F64_16: return launch_tiles_f64(true, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
     case AK_F64_16_CH: return launch_tiles_f64(true, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
     case AK_F64_32: return launch_tiles_f64(false, false, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
-    default: return launch_tiles_f64(false, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
+    case AK_F64_32_CH: return launch_tiles_f64(false, true, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
+    case AK_F32:
+    case AK_F32_CH: return launch_tiles_f32(ak == AK_F32_CH, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    case AK_F32C:
+    case AK_F32C_CH: return launch_tiles_f32c(ak == AK_F32C_CH, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    case AK_F64C_16:
+    case AK_F64C_16_CH:
+      return launch_tiles_f64c16(ak == AK_F64C_16_CH, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16, nb);
+    default:
+      return launch_tiles_f64c32(ak == AK_F64C_32_CH, A, mte, dt, X, ldx, Y, ldy, s, alpha, beta, st, nullptr, nb);
   }
 }
 

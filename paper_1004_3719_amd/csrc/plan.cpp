@@ -511,6 +511,7 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   dm.m = md.m;
   dm.mu = md.mu;
   dm.inv_m = md.inv_m;
+  dm.inv_mf = 1.0f / (float)md.m;
 
   out->nrows = A.nrows;
   out->ncols = A.ncols;

@@ -44,6 +44,7 @@ struct ArSmall {
   using Acc = uint64_t;
   using Prod = uint32_t;
   static constexpr bool CHUNK = false;
+  static constexpr bool CENTERED = false;
   __device__ static inline Prod mul(uint32_t v, uint32_t x) { return v * x; }
   __device__ static inline uint32_t reduce(Acc a, const DevMat& A) { return mod_u64(a, A.m, A.mu); }
   __device__ static inline Acc from_residue(uint32_t r) { return r; }
@@ -55,6 +56,7 @@ struct ArBig {
   using Acc = uint64_t;
   using Prod = uint64_t;
   static constexpr bool CHUNK = CH;
+  static constexpr bool CENTERED = false;
   __device__ static inline Prod mul(uint32_t v, uint32_t x) { return (uint64_t)v * x; }
   __device__ static inline uint32_t reduce(Acc a, const DevMat& A) { return mod_u64(a, A.m, A.mu); }
   __device__ static inline Acc from_residue(uint32_t r) { return r; }
@@ -67,6 +69,7 @@ struct ArM31 {
   using Acc = uint64_t;
   using Prod = uint64_t;
   static constexpr bool CHUNK = false;
+  static constexpr bool CENTERED = false;
   static constexpr uint64_t M = 0x7FFFFFFFull;
   __device__ static inline Prod mul(uint32_t v, uint32_t x) {
     uint64_t p = (uint64_t)v * x;
@@ -100,6 +103,7 @@ struct ArGF2 {
   using Acc = Gf2;
   using Prod = Gf2;
   static constexpr bool CHUNK = false;
+  static constexpr bool CENTERED = false;
   __device__ static inline Prod mul(uint32_t v, uint32_t x) { return Gf2((v & 1u) ? x : 0u); }
   __device__ static inline uint32_t reduce(Acc a, const DevMat&) { return a.v; }
   __device__ static inline Acc from_residue(uint32_t r) { return Gf2(r); }
@@ -111,16 +115,72 @@ struct ArF64 {
   using Acc = double;
   using Prod = double;
   static constexpr bool CHUNK = CH;
+  static constexpr bool CENTERED = false;
   __device__ static inline Prod mul(uint32_t v, uint32_t x) { return (double)v * (double)x; }
   __device__ static inline uint32_t reduce(Acc a, const DevMat& A) { return mod_f64(a, A.m, A.inv_m); }
   __device__ static inline Acc from_residue(uint32_t r) { return (double)r; }
 };
 
+// exact floats: integers up to 2^24 add exactly (m <= 4096, values in 16 bits).
+template <bool CH>
+struct ArF32 {
+  using ValT = uint16_t;
+  using Acc = float;
+  using Prod = float;
+  static constexpr bool CHUNK = CH;
+  static constexpr bool CENTERED = false;
+  __device__ static inline Prod mul(uint32_t v, uint32_t x) { return (float)v * (float)x; }
+  __device__ static inline uint32_t reduce(Acc a, const DevMat& A) { return mod_f32(a, A.m, A.inv_mf); }
+  __device__ static inline Acc from_residue(uint32_t r) { return (float)r; }
+};
+// Centered residues (Section 2.2): a residue r is used as r - m when r > m/2,
+// so every operand lies in [-h, h], h = floor(m/2), a product is at most h^2
+// (about a quarter of (m-1)^2) in magnitude, and sums of both signs use the
+// whole symmetric range of the floating type: about four times as many
+// terms between reductions, and fp32 holds one product up to m = 8191. The
+// stored entries and x stay canonical; operands are centered as they are
+// used, partial reductions keep accumulators centered, and the final one
+// returns the canonical residue.
+template <typename F, typename V, bool CH>
+struct ArCentered {
+  using ValT = V;
+  using Acc = F;
+  using Prod = F;
+  static constexpr bool CHUNK = CH;
+  static constexpr bool CENTERED = true;
+  __device__ static inline F lift(uint32_t r, uint32_t m) { return (F)(int32_t)(r > (m >> 1) ? r - m : r); }
+  __device__ static inline F crem(F a, const DevMat& A) {
+    if constexpr (sizeof(F) == 4) return crem_f32(a, A.m, A.inv_mf);
+    else return crem_f64(a, A.m, A.inv_m);
+  }
+  __device__ static inline uint32_t reduce(Acc a, const DevMat& A) {
+    F r = crem(a, A);
+    return (uint32_t)(int32_t)(r < 0 ? r + (F)A.m : r);
+  }
+};
+
+// one term v*x (the +-1 entries pass x or m - x), and a partial reduction
+// that keeps an accumulator in the class's representation
+template <class AR>
+__device__ inline typename AR::Prod lift(uint32_t r, uint32_t m) {
+  if constexpr (AR::CENTERED) return AR::lift(r, m);
+  else return (typename AR::Prod)r;
+}
+template <class AR>
+__device__ inline typename AR::Prod mul_term(uint32_t v, uint32_t x, uint32_t m) {
+  if constexpr (AR::CENTERED) return AR::lift(v, m) * AR::lift(x, m);
+  else return AR::mul(v, x);
+}
+template <class AR>
+__device__ inline typename AR::Acc renorm(typename AR::Acc a, const DevMat& A) {
+  if constexpr (AR::CENTERED) return AR::crem(a, A);
+  else return AR::from_residue(AR::reduce(a, A));
+}
 template <class AR>
 __device__ inline typename AR::Prod term(uint32_t tag, uint32_t v, uint32_t x, uint32_t m) {
-  if (tag == TAG_GEN) return AR::mul(v, x);
-  if (tag == TAG_PLUS) return (typename AR::Prod)x;
-  if (tag == TAG_MINUS) return (typename AR::Prod)(m - x);
+  if (tag == TAG_GEN) return mul_term<AR>(v, x, m);
+  if (tag == TAG_PLUS) return lift<AR>(x, m);
+  if (tag == TAG_MINUS) return lift<AR>(m - x, m);
   return (typename AR::Prod)0;
 }
 
@@ -139,7 +199,7 @@ struct LaneAcc {
     if (AR::CHUNK) {
       if (--left == 0) {
 #pragma unroll
-        for (int c = 0; c < S; ++c) a[c] = AR::from_residue(AR::reduce(a[c], A));
+        for (int c = 0; c < S; ++c) a[c] = renorm<AR>(a[c], A);
         left = A.reduce_every;
       }
     }
@@ -148,7 +208,7 @@ struct LaneAcc {
   __device__ inline void to_residues(const DevMat& A) {
     if (AR::CHUNK) {
 #pragma unroll
-      for (int c = 0; c < S; ++c) a[c] = AR::from_residue(AR::reduce(a[c], A));
+      for (int c = 0; c < S; ++c) a[c] = renorm<AR>(a[c], A);
     }
   }
 };
@@ -163,6 +223,7 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask, int width) {
   return ((uint64_t)hi << 32) | lo;
 }
 __device__ inline double shfl_xor_acc(double v, int mask, int width) { return __shfl_xor(v, mask, width); }
+__device__ inline float shfl_xor_acc(float v, int mask, int width) { return __shfl_xor(v, mask, width); }
 __device__ inline uint64_t shfl_xor_acc(uint64_t v, int mask, int width) { return shfl_xor_u64(v, mask, width); }
 __device__ inline Gf2 shfl_xor_acc(Gf2 v, int mask, int width) { return Gf2((uint32_t)__shfl_xor((int)v.v, mask, width)); }
 
@@ -218,7 +279,7 @@ __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>
     for (int q = 0; q < BAND_BATCH; ++q) {
       if (d0 + q * step < nd) {
 #pragma unroll
-        for (int c = 0; c < S; ++c) acc.a[c] += AR::mul(v[q], xv[q][c]);
+        for (int c = 0; c < S; ++c) acc.a[c] += mul_term<AR>(v[q], xv[q][c], A.m);
         acc.tick(A);
       }
     }
@@ -411,7 +472,7 @@ __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __
       bool ok = prow[p] < A.nrows && col >= 0 && col < (int64_t)A.ncols && cok;
       uint32_t v = ok ? ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot) : 0u;
       uint32_t x = ok ? (uint32_t)X[col * ldx + comp] : 0u;
-      acc.a[p] += AR::mul(v, x);
+      acc.a[p] += mul_term<AR>(v, x, A.m);
     }
     acc.tick(A);
   }

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libffx.so")
 
 FFX_OK, FFX_EINVAL, FFX_EBOUND, FFX_ENOMEM, FFX_EDEVICE, FFX_EUNSUPPORTED = range(6)
 FFX_I32, FFX_I64 = 0, 1
-ACC = {"auto": 0, "int64": 1, "fp64": 2}
+ACC = {"auto": 0, "int64": 1, "fp64": 2, "fp32": 3, "fp64c": 4, "fp32c": 5}  # fp64c, fp32c: centered residues
 SEL = {"heuristic": 0, "learned": 1, "fixed": 2}
 FORMATS = ["STREAM", "SELL", "SELL_SORTED", "BAND_STREAM", "BAND_SELL", "BAND_SELL_SORTED"]
 NUM_FORMATS = len(FORMATS)

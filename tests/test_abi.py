@@ -71,6 +71,23 @@ def test_fp64_bound_refused():
     assert e.value.status == ffx.FFX_EBOUND
 
 
+@pytest.mark.parametrize("acc,largest", [("fp64", 94_906_266), ("fp64c", 189_812_531), ("fp32", 4096),
+                                         ("fp32c", 8191)])
+def test_float_bounds(acc, largest):
+    """Each floating accumulator is refused just above the largest modulus whose product of two
+    extreme operands (m-1 canonical, floor(m/2) centered), plus a reduced accumulator, is exact;
+    at that modulus the bound check passes (a later device step may still fail without a GPU)."""
+    rp, c, v = _csr()
+    for m in (largest + 1, largest + 2):
+        with pytest.raises(P.FfxError) as e:
+            P.Matrix.from_csr(2, 2, rp, c, v, m, acc=acc)
+        assert e.value.status == ffx.FFX_EBOUND, m
+    try:
+        P.Matrix.from_csr(2, 2, rp, c, v, largest, acc=acc).close()
+    except P.FfxError as e:
+        assert e.status != ffx.FFX_EBOUND
+
+
 def test_bad_options():
     rp, c, v = _csr()
     for kw in [dict(block_rows=100), dict(block_rows=0), dict(tile_entries=100), dict(fixed_format=9)]:

@@ -56,3 +56,22 @@ def test_batch_tune_and_cache(dev, tmp_path):
     orc = oracle.get()
     for k, A in enumerate(mats):
         assert np.array_equal(Ys[k].cpu().numpy(), orc.spmm(A, synth.c4_rhs(k, A)))
+
+
+@pytest.mark.parametrize("acc,m", [("fp32", 4093), ("fp32c", 8191), ("fp64c", 65521)])
+def test_batch_float_accumulators(dev, acc, m):
+    """A batch built with a floating accumulator (reductions after every term for fp32 at 4093
+    and centered fp32 at 8191) against the oracle."""
+    from paper_1004_3719_amd import Batch, Matrix
+    mats = [synth.c4_matrix(k, nmax=20_000, m=m) for k in range(10)]
+    print("[case] batch acc", acc, m, flush=True)
+    Ms = [Matrix.from_synth(A, acc=acc) for A in mats]
+    B = Batch(Ms, [A.s for A in mats])
+    rhs = [synth.c4_rhs(k, A, m=m) for k, A in enumerate(mats)]
+    Xs = [torch.from_numpy(X.astype(np.int32)).to(dev) for X in rhs]
+    Ys = [torch.full((A.nrows, A.s), -5, dtype=torch.int32, device=dev) for A in mats]
+    B.spmm(Xs, Ys)
+    torch.cuda.synchronize()
+    orc = oracle.get()
+    for k, A in enumerate(mats):
+        assert np.array_equal(Ys[k].cpu().numpy(), orc.spmm(A, rhs[k])), (k, A.params)

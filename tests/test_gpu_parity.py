@@ -90,7 +90,7 @@ def test_c1_spmv_t(dev, orc, ffx, fmt):
 
 
 @pytest.mark.parametrize("fmt", [None] + FORMATS)
-@pytest.mark.parametrize("acc", ["int64", "fp64"])
+@pytest.mark.parametrize("acc", ["int64", "fp64", "fp64c"])
 def test_powerlaw_spmv(dev, orc, ffx, fmt, acc):
     """The power-law + band + 60% +-1 workload at n = 120,000 (30 blocks, rows up to 5,000 terms)."""
     A = synth.c2(n=120_000)
@@ -123,15 +123,23 @@ def test_tile_sizes(dev, orc, ffx, tile_entries):
 
 
 # ------------------------------------------------------- moduli and bounds --
-@pytest.mark.parametrize("m", [2, 3, 27, 65521, 65537, 1_000_003, 94_906_263, 2**31 - 1])
-@pytest.mark.parametrize("acc", ["int64", "fp64"])
+# Largest modulus each floating accumulator takes: one product plus a reduced
+# accumulator must be exact, below 2^53 (doubles) or 2^24 (floats), with
+# canonical operands up to m-1 or centered ones up to floor(m/2) in magnitude.
+LARGEST_M = {"int64": 2**31 - 1, "fp64": 94_906_266, "fp64c": 189_812_531, "fp32": 4096, "fp32c": 8191}
+ACCS = list(LARGEST_M)
+
+
+@pytest.mark.parametrize("m", [2, 3, 27, 251, 4093, 4096, 4097, 8191, 8192, 65521, 65537, 1_000_003, 94_906_263,
+                               189_812_531, 189_812_533, 2**31 - 1])
+@pytest.mark.parametrize("acc", ACCS)
 def test_moduli(dev, orc, ffx, m, acc):
     s = synth.spec(4000, 3000, 77 + m, len_kind=synth.LEN_ZIPF, len_a=1, len_b=1500, len_alpha=1.5,
                    col_kind=synth.COL_UNIFORM, band_lo=-1, band_hi=1, p_pm1=0.4, val_lo=-(2**40), val_hi=2**40)
     A = synth.rows(s)
     A.m = m
     note("modulus", m, acc)
-    if acc == "fp64" and (m - 1) ** 2 >= 2**53:
+    if m > LARGEST_M[acc]:
         with pytest.raises(Exception):
             ffx.from_synth(A, acc=acc)
         return
@@ -142,25 +150,65 @@ def test_moduli(dev, orc, ffx, m, acc):
     assert np.array_equal(M.spmv_t(tdev(xt, dev, torch.int64)).cpu().numpy(), orc.spmv_t(A, xt))
 
 
-@pytest.mark.parametrize("m,acc", [(2**31 - 1, "int64"), (94_906_263, "fp64"), (65521, "fp64"), (3_000_017, "int64")])
+@pytest.mark.parametrize("m,acc", [(2**31 - 1, "int64"), (94_906_263, "fp64"), (65521, "fp64"), (3_000_017, "int64"),
+                                   (4093, "fp32"), (4096, "fp32"), (251, "fp32"), (8191, "fp32c"), (4093, "fp32c"),
+                                   (251, "fp32c"), (189_812_531, "fp64c"), (65521, "fp64c"), (32749, "fp64c")])
 @pytest.mark.parametrize("fmt", ["STREAM", "SELL", "BAND_SELL_SORTED"])
 @pytest.mark.parametrize("split", [False, True])
-def test_bound_edges(dev, orc, ffx, m, acc, fmt, split):
-    """Every value and x entry is m-1 (each term is the largest possible), rows of every length
-    around the reduction bound; the answer is the row length mod m."""
+@pytest.mark.parametrize("extreme", ["m-1", "half", "-half"])
+def test_bound_edges(dev, orc, ffx, m, acc, fmt, split, extreme):
+    """Every value and x entry is the same extreme residue, so every term of a row is the
+    largest possible and of one sign: m-1 (largest canonical term), floor(m/2) or m - floor(m/2)
+    (largest centered terms, +h*h both). Rows of every length around the reduction bound; the
+    answer is (length * v * v) mod m."""
+    v = {"m-1": m - 1, "half": m // 2, "-half": m - m // 2}[extreme]
     lens = np.array(list(range(0, 40)) + [63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 2047, 3000, 5000])
     n = 6000
     rng = np.random.default_rng(9)
     rows = [np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]
     rp = np.zeros(len(lens) + 1, np.int64)
     np.cumsum(lens, out=rp[1:])
-    A = synth.Csr(len(lens), n, rp, np.concatenate(rows).astype(np.int32), np.full(int(lens.sum()), -1, np.int64), m=m)
-    note("bound edge", m, acc, fmt, split)
+    A = synth.Csr(len(lens), n, rp, np.concatenate(rows).astype(np.int32), np.full(int(lens.sum()), v, np.int64), m=m)
+    note("bound edge", m, acc, fmt, split, extreme)
     M = ffx.from_synth(A, acc=acc, fixed_format=fmt, split_pm1=split)
-    x = np.full(n, m - 1, np.int64)
+    x = np.full(n, v, np.int64)
     got = M.spmv(tdev(x, dev, torch.int64)).cpu().numpy()
-    assert np.array_equal(got, lens % m)
+    assert np.array_equal(got, np.array([(int(L) * v * v) % m for L in lens]))
     assert np.array_equal(got, orc.spmv(A, x))
+
+
+def test_reduction_bounds(dev, ffx):
+    """Terms between reductions for accumulators whose bound is small (worked by hand: one
+    product of (m-1)^2 = 16,736,256 or h^2 = 4095^2 fits 2^24 - 1 once with a residue; h = 2046
+    gives (2^24 - 1 - 2046) // 2046^2 = 4)."""
+    rp, c, v = np.array([0, 1], np.int64), np.array([0], np.int32), np.array([5], np.int64)
+    for acc, m, b in [("fp32", 4093, 1), ("fp32", 4096, 1), ("fp32c", 8191, 1), ("fp32c", 4093, 4),
+                      ("fp32", 251, (2**24 - 1 - 250) // 250**2), ("fp32c", 251, (2**24 - 1 - 125) // 125**2)]:
+        M = ffx.from_csr(1, 1, rp, c, v, m, acc=acc)
+        assert M.info()["reduce_every"] == b, (acc, m)
+        M.close()
+
+
+@pytest.mark.parametrize("acc", ["int64", "fp64", "fp32", "fp32c", "fp64c"])
+@pytest.mark.parametrize("fmt", [None] + FORMATS)
+def test_small_modulus_accumulators(dev, orc, ffx, acc, fmt):
+    """The power-law workload with m = 4093 (every accumulator applies; fp32 reduces after each
+    term, centered fp32 after four) at n = 60,000: products with one and several vectors."""
+    A = synth.c2(n=60_000, m=4093)
+    note("small modulus", acc, fmt)
+    M = ffx.from_synth(A, fixed_format=fmt, acc=acc, build_transpose=True)
+    assert M.info()["acc"] == {"int64": 1, "fp64": 2, "fp32": 3, "fp64c": 4, "fp32c": 5}[acc]
+    x = vec(21, 1, A.ncols, A.m)
+    assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+    xt = vec(21, 2, A.nrows, A.m)
+    assert np.array_equal(M.spmv_t(tdev(xt, dev)).cpu().numpy(), orc.spmv_t(A, xt))
+    for s in (2, 5, 16):
+        X = vec(21, 3 + s, A.ncols, A.m, s)
+        Y0 = vec(21, 40 + s, A.nrows, A.m, s)
+        Y = tdev(Y0, dev)
+        M.spmm(tdev(X, dev), alpha=A.m - 2, beta=3, Y=Y)
+        assert np.array_equal(Y.cpu().numpy(), orc.spmm(A, X, A.m - 2, 3, Y0)), s
+    M.close()
 
 
 # ---------------------------------------------------------------- SpMM -----
