@@ -19,7 +19,9 @@ Other configurations print the same kind of line:
   c5  learned format selection: train on measured block timings, evaluate the
       whole-product time on held-out matrices against the plain heuristic;
   acc the accumulators (int64, fp64, fp32, centered fp32 and fp64) on the
-      power-law matrix with m = 4093, times 1, 8 and 16 vectors.
+      power-law matrix with m = 4093, times 1, 8 and 16 vectors;
+  reorder  a randomly numbered 9-point stencil (2M rows), products in the
+      caller's numbering against reverse Cuthill-McKee storage.
 """
 import argparse
 import hashlib
@@ -288,6 +290,83 @@ def bench_accumulators(args):
                           "accumulator applies) times 1, 8 and 16 vectors", "n": A.nrows, "nnz": A.nnz, "m": m,
               "acc": args.acc, "selector": args.selector, "kernel_hash": khash}
     line(A.nnz / (ms_main * 1e-3), ms_main, args, args.acc, config, roofline, None, {"accumulators": table})
+
+
+# ---------------------------------------------------------------- reorder
+def bench_reorder(args):
+    """A 9-point stencil on a 2048 x 1024 grid whose nodes are numbered at random (2,097,152 rows,
+    18.9 M entries, m = 32749): the product in the caller's numbering against the same matrix stored
+    in reverse Cuthill-McKee order (one x gather and one y scatter per call), and ten products chained
+    through ffx_power, where the permutations are paid once."""
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix
+
+    dev = torch.device("cuda:0")
+    A = synth.stencil()
+    m = A.m
+    x_np = synth.vector(synth.SEED0 + 5, 1, A.ncols, 0, m - 1)
+    x = torch.from_numpy(x_np.astype(np.int32)).to(dev)
+    stream = torch.cuda.current_stream()
+    res, y_main = {}, None
+    for reorder in (False, True):
+        t0 = time.time()
+        M = Matrix.from_synth(A, reorder=reorder, selector=args.selector, model_path=args.model)
+        build_s = time.time() - t0
+        info = M.info()
+        y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup):
+            M.spmv(x, y=y)
+        torch.cuda.synchronize()
+        ev = event_pairs(args.steps)
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            M.spmv(x, y=y)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        ev_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+        a_, b_ = event_pairs(1)[0]
+        M.power(10, x)
+        a_.record(stream)
+        M.power(10, x)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        key = "reordered" if reorder else "caller_order"
+        res[key] = {"build_s": round(build_s, 2), "bandwidth": info["bandwidth_stored"], "wall_ms": round(wall_ms, 5),
+                    "event_ms": round(ev_ms, 5), "power10_ms_per_product": round(a_.elapsed_time(b_) / 10, 5),
+                    "formats": info["format_blocks"]}
+        log("%s: %s" % (key, res[key]))
+        if reorder:
+            y_main, ms, kernel_ms = y, wall_ms, ev_ms
+        M.close()
+    b_alg = algorithmic_bytes(A, m)
+    achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_permute_to_u16 (x gathered into the stored order) + k_tiles (y written through the row map)",
+                "kernel_ms": round(kernel_ms, 5), "algorithmic_bytes": int(b_alg)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.get()
+        got = y_main.cpu().numpy()
+        reps, t_cpu, exact = 0, 0.0, True
+        while t_cpu < args.cpu_seconds or reps < 1:
+            t1 = time.perf_counter()
+            want = orc.spmv(A, x_np)
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+            exact = exact and bool(np.array_equal(got, want))
+        cpu = {"value": round(A.nnz * reps / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
+               "sample": "%d full products y = A x in the caller's numbering (single thread)" % reps,
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+    config = {"workload": "shuffled 9-point stencil SpMV mod 32749: 2048 x 1024 grid, 2,097,152 rows, nodes numbered "
+                          "at random, 60% +-1, x int32; stored in reverse Cuthill-McKee order",
+              "n": A.nrows, "nnz": A.nnz, "m": m, "selector": args.selector}
+    line(A.nnz / (ms * 1e-3), ms, args, "int64", config, roofline, cpu, {"orders": res})
 
 
 # --------------------------------------------------------------------- gf2
@@ -635,7 +714,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc", "reorder"])
     ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
     ap.add_argument("--acc", default="int64", choices=ACC_NAMES)
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
@@ -685,6 +764,8 @@ def main():
         bench_gf2_sequence(args)
     elif args.config == "acc":
         bench_accumulators(args)
+    elif args.config == "reorder":
+        bench_reorder(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)

@@ -107,6 +107,13 @@ typedef struct {
   int32_t compact_x;        /* m <= 65536, one vector: gather x from a 16-bit copy made per product
                                (-1 = when x exceeds 1 MiB, 0 = never, 1 = always); never changes a result */
   const char* model_path;   /* learned selector weights; NULL = none */
+  int32_t reorder;          /* square matrices: 1 = store P A P^T under the reverse Cuthill-McKee order
+                               of the pattern of A + A^T (Section 5, reordering A), so the x entries
+                               of a tile come from a narrow window; every entry point then takes and
+                               returns vectors in the caller's order (one gather in, one scatter out
+                               per call, once per call for ffx_power and ffx_sequence); never changes
+                               a result. 0 (default): the caller's order. Batches refuse reordered
+                               matrices. */
 } ffx_build_opts;
 
 typedef struct ffx_matrix_s* ffx_matrix;
@@ -128,6 +135,9 @@ typedef struct {
   int32_t has_transpose;
   int32_t value_bytes;      /* 2 when m <= 65536, else 4 */
   int64_t format_blocks[FFX_NUM_FORMATS]; /* number of blocks in each format */
+  int32_t reordered;        /* 1 when the handle stores P A P^T (ffx_build_opts.reorder) */
+  int64_t bandwidth_input;  /* max |i - j| over the entries of A */
+  int64_t bandwidth_stored; /* the same for the stored operator (P A P^T when reordered) */
 } ffx_matrix_info;
 
 /* Fill *opts with the defaults. */
@@ -320,6 +330,15 @@ ffx_status ffx_selector_destroy(ffx_selector S);
 ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
                               const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts, float* out,
                               int64_t cap, int64_t* nblocks);
+
+/* The reordering used by ffx_build_opts.reorder, on the host alone (no GPU
+ * call): reverse Cuthill-McKee (Cuthill and McKee 1969, reversed as George
+ * 1971) on the pattern of A + A^T of the square n x n pattern (rowptr,
+ * colidx), each connected part started from a pseudo-peripheral node (George
+ * and Liu 1979), neighbours visited by increasing degree, ties by index.
+ * perm (host, n entries) receives perm[new] = old. Section 5 names reordering
+ * A as a way to faster products. */
+ffx_status ffx_reorder_rcm(int64_t n, const int64_t* rowptr, const int32_t* colidx, int32_t* perm);
 
 /* Time of each row block of A in its stored format, in microseconds per
  * product (host array, nblocks floats): the block's tiles are launched

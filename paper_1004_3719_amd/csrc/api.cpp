@@ -105,6 +105,8 @@ static PlanOpts plan_opts(const ffx_build_opts* o) {
   if (d.compact_x < -1 || d.compact_x > 1) fail(FFX_EINVAL, "compact_x %d not in {-1, 0, 1}", d.compact_x);
   p.compact_x = d.compact_x;
   if (d.model_path) p.model_path = d.model_path;
+  if (d.reorder < 0 || d.reorder > 1) fail(FFX_EINVAL, "reorder %d not in {0, 1}", d.reorder);
+  p.reorder = d.reorder != 0;
   return p;
 }
 
@@ -164,17 +166,30 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
     if (b < 1)
       fail(FFX_EBOUND, "the %s accumulator cannot hold one product of residues modulo %u exactly",
            acc_name(po.acc), m);
-    encode(A, M->md, po, st, &M->A);
+    // reordering (Section 5): the handle stores B = P A P^T and keeps perm
+    RCsr B;
+    if (po.reorder) {
+      if (A.nrows != A.ncols)
+        fail(FFX_EINVAL, "reordering needs a square matrix (%lld x %lld)", (long long)A.nrows, (long long)A.ncols);
+      std::vector<uint32_t> perm = rcm_order(A);
+      B = permute_sym(A, perm);
+      if (A.nrows > 0) {
+        FFX_HIP(hipMalloc((void**)&M->perm, perm.size() * sizeof(uint32_t)));
+        FFX_HIP(hipMemcpy(M->perm, perm.data(), perm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+      }
+    }
+    const RCsr& S = po.reorder ? B : A;
+    encode(S, M->md, po, st, &M->A);
     int64_t maxterms = M->A.max_row_terms;
     if (build_t) {
-      RCsr T = transpose(A);
+      RCsr T = transpose(S);
       encode(T, M->md, po, st, &M->AT);
       M->has_t = true;
       maxterms = std::max(maxterms, M->AT.max_row_terms);
     } else {
       // the scatter form of A^T sums one column per output: bound by the longest column
-      std::vector<int64_t> cnt(A.ncols, 0);
-      for (uint32_t c : A.col) cnt[c]++;
+      std::vector<int64_t> cnt(S.ncols, 0);
+      for (uint32_t c : S.col) cnt[c]++;
       for (int64_t v : cnt) maxterms = std::max(maxterms, v);
     }
     M->chunk = maxterms > b;
@@ -199,9 +214,14 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
     I.has_transpose = M->has_t;
     I.value_bytes = M->md.small() ? 2 : 4;
     for (int f = 0; f < FFX_NUM_FORMATS; ++f) I.format_blocks[f] = M->A.format_blocks[f];
+    I.reordered = po.reorder;
+    I.bandwidth_input = bandwidth(A);
+    I.bandwidth_stored = po.reorder ? bandwidth(B) : I.bandwidth_input;
+    I.device_bytes += po.reorder ? A.nrows * (int64_t)sizeof(uint32_t) : 0;
   } catch (...) {
     M->A.release();
     M->AT.release();
+    if (M->perm) (void)hipFree(M->perm);
     delete M;
     throw;
   }
@@ -233,6 +253,38 @@ static void check_disjoint(const char* a, const void* pa, int64_t na, int64_t ld
   if (a0 < b1 && b0 < a1) fail(FFX_EINVAL, "%s and %s overlap", a, b);
 }
 
+static void product_core(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
+                         void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st, int64_t nin, int64_t nout);
+
+// For a reordered handle: gathers the caller's n x s block X (and Y when
+// y_in) into compact copies in the stored order, runs f(xp, yp), which leaves
+// its result in yp, and scatters yp back into Y.
+template <class F>
+static void permuted(const ffx_matrix_s& M, int64_t n, int s, size_t esz, const void* X, int64_t ldx, void* Y,
+                     int64_t ldy, bool y_in, hipStream_t st, F&& f) {
+  warm_pool(st);
+  void* buf[2] = {nullptr, nullptr};
+  const size_t bytes = (size_t)n * s * esz;
+  for (int q = 0; q < 2; ++q)
+    if (hipMallocAsync(&buf[q], bytes, st) != hipSuccess) {
+      for (void* p : buf) if (p) (void)hipFreeAsync(p, st);
+      fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+    }
+  hipError_t e = launch_permute_rows(esz, X, ldx, buf[0], s, M.perm, n, s, false, st);
+  if (e == hipSuccess && y_in) e = launch_permute_rows(esz, Y, ldy, buf[1], s, M.perm, n, s, false, st);
+  if (e == hipSuccess) {
+    try {
+      f(buf[0], buf[1]);
+    } catch (...) {
+      for (void* p : buf) (void)hipFreeAsync(p, st);
+      throw;
+    }
+    e = launch_permute_rows(esz, buf[1], s, Y, ldy, M.perm, n, s, true, st);
+  }
+  for (void* p : buf) (void)hipFreeAsync(p, st);
+  FFX_HIP(e);
+}
+
 static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
                     void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st) {
   if (!M) fail(FFX_EINVAL, "matrix handle is NULL");
@@ -245,6 +297,37 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
   check_block("y", Y, nout, s, ldy);
   check_disjoint("x", X, nin, ldx, "y", Y, nout, ldy, s, dt);
   if (nout == 0) return;
+  if (M->perm && !(trans && !M->has_t)) {
+    // square and stored as P A P^T: gather x into the stored order (into the 16-bit copy when the
+    // product takes one) and let the tiles write each row of y to its caller's row
+    const Encoded& E = trans ? M->AT : M->A;
+    DevMat dm = E.dm;
+    dm.rowmap = M->perm;
+    const bool c16 = s == 1 && M->compact_x;
+    const size_t bytes = c16 ? (size_t)nin * 2 : (size_t)nin * s * esize(dt);
+    warm_pool(st);
+    void* xp = nullptr;
+    if (hipMallocAsync(&xp, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+    hipError_t e = c16 ? launch_permute_to_u16(dt, X, ldx, (uint16_t*)xp, M->perm, nin, st)
+                       : launch_permute_rows(esize(dt), X, ldx, xp, s, M->perm, nin, s, false, st);
+    if (e == hipSuccess)
+      e = launch_tiles(arith_kind(*M), dm, E.max_tile_entries, dt, c16 ? nullptr : xp, s, Y, ldy, s, alpha, beta, st,
+                       c16 ? (const uint16_t*)xp : nullptr);
+    (void)hipFreeAsync(xp, st);
+    FFX_HIP(e);
+    return;
+  }
+  if (M->perm) {  // the scatter form of A^T: gather x (and y when beta != 0), scatter y back
+    permuted(*M, nin, s, esize(dt), X, ldx, Y, ldy, beta != 0, st, [&](void* xp, void* yp) {
+      product_core(M, trans, s, alpha, xp, s, beta, yp, s, dt, st, nin, nout);
+    });
+    return;
+  }
+  product_core(M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, nin, nout);
+}
+
+static void product_core(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
+                         void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st, int64_t nin, int64_t nout) {
   if (trans && !M->has_t) {  // scatter the entries of A with 64-bit integer atomics
     warm_pool(st);
     unsigned long long* acc = nullptr;
@@ -269,6 +352,41 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
     return;
   }
   FFX_HIP(launch_tiles(ak, E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st));
+}
+
+// W = A^k V for k >= 1 on the stored operator; the last product writes its
+// row r to row rowmap[r] of W when rowmap is not null.
+static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, int64_t ldv, void* W, int64_t ldw,
+                       ffx_dtype dtype, hipStream_t st, const uint32_t* rowmap) {
+  {
+    const int64_t n = M.info.nrows;
+    const int ak = arith_kind(M);
+    const Encoded& E = M.A;
+    void* tmp[2] = {nullptr, nullptr};
+    size_t bytes = (size_t)n * s * esize(dtype);
+    if (k >= 2) {
+      for (int q = 0; q < (k >= 3 ? 2 : 1); ++q)
+        if (hipMallocAsync(&tmp[q], bytes, st) != hipSuccess) {
+          for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+          fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+        }
+    }
+    const void* cur = V;
+    int64_t ldc = ldv;
+    hipError_t e = hipSuccess;
+    for (int64_t it = 0; it < k && e == hipSuccess; ++it) {
+      bool last = it == k - 1;
+      void* dst = last ? W : tmp[it & 1];
+      int64_t ldd = last ? ldw : s;
+      DevMat dm = E.dm;
+      if (last) dm.rowmap = rowmap;
+      e = launch_tiles(ak, dm, E.max_tile_entries, dtype, cur, ldc, dst, ldd, s, 1, 0, st);
+      cur = dst;
+      ldc = ldd;
+    }
+    for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+    FFX_HIP(e);
+  }
 }
 
 }  // namespace ffx
@@ -343,6 +461,7 @@ ffx_status ffx_matrix_destroy(ffx_matrix A) {
     if (!A) return;
     A->A.release();
     A->AT.release();
+    if (A->perm) (void)hipFree(A->perm);
     delete A;
   });
 }
@@ -385,30 +504,25 @@ ffx_status ffx_power(ffx_matrix A, int64_t k, int32_t s, const void* V, int64_t 
       FFX_HIP(launch_copy_block(dtype, V, ldv, W, ldw, n, s, st));
       return;
     }
-    const int ak = arith_kind(*A);
-    const Encoded& E = A->A;
-    void* tmp[2] = {nullptr, nullptr};
-    size_t bytes = (size_t)n * s * esize(dtype);
-    if (k >= 2) {
-      for (int q = 0; q < (k >= 3 ? 2 : 1); ++q)
-        if (hipMallocAsync(&tmp[q], bytes, st) != hipSuccess) {
-          for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
-          fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+    if (A->perm) {  // V gathered once into the stored order; the last product writes W in the caller's order
+      warm_pool(st);
+      void* vp = nullptr;
+      const size_t bytes = (size_t)n * s * esize(dtype);
+      if (hipMallocAsync(&vp, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+      hipError_t e = launch_permute_rows(esize(dtype), V, ldv, vp, s, A->perm, n, s, false, st);
+      if (e == hipSuccess) {
+        try {
+          power_iter(*A, k, s, vp, s, W, ldw, dtype, st, A->perm);
+        } catch (...) {
+          (void)hipFreeAsync(vp, st);
+          throw;
         }
+      }
+      (void)hipFreeAsync(vp, st);
+      FFX_HIP(e);
+      return;
     }
-    const void* cur = V;
-    int64_t ldc = ldv;
-    hipError_t e = hipSuccess;
-    for (int64_t it = 0; it < k && e == hipSuccess; ++it) {
-      bool last = it == k - 1;
-      void* dst = last ? W : tmp[it & 1];
-      int64_t ldd = last ? ldw : s;
-      e = launch_tiles(ak, E.dm, E.max_tile_entries, dtype, cur, ldc, dst, ldd, s, 1, 0, st);
-      cur = dst;
-      ldc = ldd;
-    }
-    for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
-    FFX_HIP(e);
+    power_iter(*A, k, s, V, ldv, W, ldw, dtype, st, nullptr);
   });
 }
 
@@ -452,10 +566,29 @@ ffx_status ffx_sequence(ffx_matrix A, int32_t s, const void* U, int64_t ldu, con
       }
     const int gb = g_seq_graph_batch.load();
     const int batch = (gb > 0 && L >= 2 * (int64_t)gb) ? gb : 0;
-    hipError_t e = launch_sequence(seq_kind(*A), only_sell(E), E.dm, E.max_tile_entries, dtype, U, ldu, V, ldv, L, s, S,
-                                   Wlast, ws[0], ws[1], ws[2], (uint64_t*)ws[3], (uint64_t*)ws[4], (int64_t*)ws[5], batch,
-                                   st);
+    // reordered: S_i = (P U)^T B^i (P V) with B = P A P^T, and A^L V = P^T B^L (P V)
+    void* pw[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    if (A->perm) {
+      const size_t pb = (size_t)n * s * esize(dtype);
+      for (int q = 0; q < (Wlast ? 3 : 2); ++q)
+        if (hipMallocAsync(&pw[q], pb, st) != hipSuccess) {
+          for (void* p : ws) (void)hipFreeAsync(p, st);
+          for (void* p : pw) if (p) (void)hipFreeAsync(p, st);
+          fail(FFX_ENOMEM, "sequence workspace allocation failed");
+        }
+      e = launch_permute_rows(esize(dtype), U, ldu, pw[0], s, A->perm, n, s, false, st);
+      if (e == hipSuccess) e = launch_permute_rows(esize(dtype), V, ldv, pw[1], s, A->perm, n, s, false, st);
+    }
+    if (e == hipSuccess)
+      e = launch_sequence(seq_kind(*A), only_sell(E), E.dm, E.max_tile_entries, dtype, A->perm ? pw[0] : U,
+                          A->perm ? s : ldu, A->perm ? pw[1] : V, A->perm ? s : ldv, L, s, S,
+                          A->perm ? pw[2] : Wlast, ws[0], ws[1], ws[2], (uint64_t*)ws[3], (uint64_t*)ws[4],
+                          (int64_t*)ws[5], batch, st);
+    if (e == hipSuccess && A->perm && Wlast)
+      e = launch_permute_rows(esize(dtype), pw[2], s, Wlast, s, A->perm, n, s, true, st);
     for (void* p : ws) (void)hipFreeAsync(p, st);
+    for (void* p : pw) if (p) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
   });
 }
@@ -471,7 +604,14 @@ ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, voi
     check_disjoint("X", X, nin, ldx, "Y", Y, nout, ldy, w, FFX_I32);
     if (nout == 0) return;
     const Encoded& E = A->A;
-    FFX_HIP(launch_tiles_gf2(E.dm, E.max_tile_entries, X, ldx, Y, ldy, w, (hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    if (A->perm) {
+      permuted(*A, nout, w, 4, X, ldx, Y, ldy, false, st, [&](void* xp, void* yp) {
+        FFX_HIP(launch_tiles_gf2(E.dm, E.max_tile_entries, xp, w, yp, w, w, st));
+      });
+      return;
+    }
+    FFX_HIP(launch_tiles_gf2(E.dm, E.max_tile_entries, X, ldx, Y, ldy, w, st));
   });
 }
 
@@ -509,20 +649,29 @@ ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu,
     warm_pool(st);
     const int G = (int)((n + 255) / 256);  // 256 rows per projection workgroup
     size_t wbytes = (size_t)n * w * 4;
-    void* ws[4] = {nullptr, nullptr, nullptr, nullptr};
-    size_t sizes[4] = {wbytes, wbytes, wbytes, (size_t)G * npairs * 4};
-    for (int q = 0; q < 4; ++q)
+    void* ws[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t sizes[5] = {wbytes, wbytes, wbytes, (size_t)G * npairs * 4, wbytes};
+    const int nws = (A->perm && Wlast) ? 5 : 4;  // reordered: A^L V is scattered back from ws[4]
+    for (int q = 0; q < nws; ++q)
       if (hipMallocAsync(&ws[q], sizes[q], st) != hipSuccess) {
         for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
         fail(FFX_ENOMEM, "GF(2) sequence workspace allocation failed");
       }
-    hipError_t e = launch_copy_block(FFX_I32, U, ldu, ws[0], w, n, w, st);
-    if (e == hipSuccess) e = launch_copy_block(FFX_I32, V, ldv, ws[1], w, n, w, st);
+    hipError_t e;
+    if (A->perm) {  // the stored order of a reordered matrix
+      e = launch_permute_rows(4, U, ldu, ws[0], w, A->perm, n, w, false, st);
+      if (e == hipSuccess) e = launch_permute_rows(4, V, ldv, ws[1], w, A->perm, n, w, false, st);
+    } else {
+      e = launch_copy_block(FFX_I32, U, ldu, ws[0], w, n, w, st);
+      if (e == hipSuccess) e = launch_copy_block(FFX_I32, V, ldv, ws[1], w, n, w, st);
+    }
     const Encoded& E = A->A;
     if (e == hipSuccess)
       e = launch_sequence_gf2(E.dm, E.max_tile_entries, w, (const uint32_t*)ws[0], (const uint32_t*)ws[1], L,
-                              (uint32_t*)S, (uint32_t*)ws[2], (uint32_t*)ws[3], G, (uint32_t*)Wlast, st);
-    for (void* p : ws) (void)hipFreeAsync(p, st);
+                              (uint32_t*)S, (uint32_t*)ws[2], (uint32_t*)ws[3], G,
+                              (uint32_t*)(A->perm && Wlast ? ws[4] : Wlast), st);
+    if (e == hipSuccess && A->perm && Wlast) e = launch_permute_rows(4, ws[4], w, Wlast, w, A->perm, n, w, true, st);
+    for (void* p : ws) if (p) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
   });
 }
@@ -573,6 +722,30 @@ ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowpt
       std::memcpy(out + b * NUM_FEATURES, st.feat, sizeof(float) * NUM_FEATURES);
     }
     if (nblocks) *nblocks = nb;
+  });
+}
+
+ffx_status ffx_reorder_rcm(int64_t n, const int64_t* rowptr, const int32_t* colidx, int32_t* perm) {
+  return guard([&] {
+    if (n < 0 || n > MAX_DIM) fail(FFX_EINVAL, "n = %lld outside [0, 2^30]", (long long)n);
+    if (n > 0 && (!rowptr || !perm)) fail(FFX_EINVAL, "NULL argument");
+    RCsr A;
+    A.nrows = A.ncols = n;
+    if (n == 0) return;
+    if (rowptr[0] != 0) fail(FFX_EINVAL, "rowptr[0] = %lld, expected 0", (long long)rowptr[0]);
+    A.rp.assign(rowptr, rowptr + n + 1);
+    for (int64_t i = 0; i < n; ++i)
+      if (rowptr[i + 1] < rowptr[i]) fail(FFX_EINVAL, "rowptr decreases at row %lld", (long long)i);
+    const int64_t nnz = rowptr[n];
+    if (nnz > 0 && !colidx) fail(FFX_EINVAL, "colidx is NULL");
+    A.col.resize(nnz);
+    for (int64_t k = 0; k < nnz; ++k) {
+      if (colidx[k] < 0 || colidx[k] >= n)
+        fail(FFX_EINVAL, "column index %d at entry %lld outside [0, %lld)", colidx[k], (long long)k, (long long)n);
+      A.col[k] = (uint32_t)colidx[k];
+    }
+    std::vector<uint32_t> p = rcm_order(A);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)p[i];
   });
 }
 

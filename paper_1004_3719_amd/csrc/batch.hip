@@ -379,6 +379,8 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
       for (int k = 0; k < count; ++k) {
         if (!mats[k]) fail(FFX_EINVAL, "matrix %d is NULL", k);
         if (s[k] < 1 || s[k] > MAX_S) fail(FFX_EINVAL, "matrix %d: s = %d outside [1, 16]", k, s[k]);
+        if (mats[k]->perm)
+          fail(FFX_EINVAL, "matrix %d is reordered: a batch takes matrices stored in the caller's order", k);
         int ak = matrix_arith_kind(*mats[k]);
         if (k == 0) B->ak = ak;
         else if (ak != B->ak || mats[k]->md.m != mats[0]->md.m)

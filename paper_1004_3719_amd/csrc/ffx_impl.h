@@ -80,6 +80,7 @@ struct DevMat {
   const void* bval;      // band values, diagonal-major inside each tile
   const int32_t* boffs;  // band diagonal offsets (column - row)
   const uint32_t* ltiles;// STREAM tiles flagged TF_LONGROWS
+  const uint32_t* rowmap;// when not null, row r of the product is written to row rowmap[r] of Y
   uint32_t nltiles;
   uint32_t ntiles;
   uint32_t nrows, ncols;

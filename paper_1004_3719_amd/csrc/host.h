@@ -39,6 +39,13 @@ RCsr reduce_coo(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rowidx
                 const void* vals, ffx_dtype vt, uint32_t m);
 RCsr transpose(const RCsr& A);
 
+// Reverse Cuthill-McKee order of a square matrix (pattern of A + A^T):
+// perm[new] = old. permute_sym returns P A P^T, i.e. row i is row perm[i] of A
+// with every column j renumbered to its new index. bandwidth: max |i - j|.
+std::vector<uint32_t> rcm_order(const RCsr& A);
+RCsr permute_sym(const RCsr& A, const std::vector<uint32_t>& perm);
+int64_t bandwidth(const RCsr& A);
+
 // Per-block statistics (also the features of the learned selector).
 constexpr int NUM_FEATURES = 32;
 struct BlockStats {
@@ -63,6 +70,7 @@ struct PlanOpts {
   int tile_entries = 1024;
   int compact_x = -1;
   std::string model_path;
+  bool reorder = false;
 };
 
 BlockStats block_stats(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, const PlanOpts& o);
@@ -112,5 +120,7 @@ struct ffx_matrix_s {
   bool compact_x = false;  // one-vector products gather x from a 16-bit copy
   ffx::Encoded A, AT;
   bool has_t = false;
+  // reordered matrices: A and AT hold P A P^T; perm[new] = old on the device
+  uint32_t* perm = nullptr;
   ffx_matrix_info info{};
 };

@@ -102,6 +102,15 @@ hipError_t launch_transpose_scatter(bool small, const DevMat& A, ffx_dtype dt, c
 hipError_t launch_check_block(ffx_dtype dt, const void* X, int64_t n, int s, int64_t ldx, uint32_t m,
                               unsigned long long* first, hipStream_t st);
 
+// Row permutation of an n x s block of esize-byte elements (4 or 8) by perm
+// (n entries, each < n): gather out[i] = in[perm[i]], or scatter
+// out[perm[i]] = in[i]. in and out must not overlap.
+hipError_t launch_permute_rows(size_t esize, const void* in, int64_t ldi, void* out, int64_t ldo, const uint32_t* perm,
+                               int64_t n, int s, bool scatter, hipStream_t st);
+// out[i] = x[perm[i] * ldx] as 16 bits, i < n (m <= 65536); out 16-byte aligned.
+hipError_t launch_permute_to_u16(ffx_dtype dt, const void* x, int64_t ldx, uint16_t* out, const uint32_t* perm,
+                                 int64_t n, hipStream_t st);
+
 // Strided copy of an n x s block (ld_in -> ld_out) of dtype elements.
 hipError_t launch_copy_block(ffx_dtype dt, const void* in, int64_t ldi, void* out, int64_t ldo, int64_t n, int s,
                              hipStream_t st);

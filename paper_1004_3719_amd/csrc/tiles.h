@@ -237,7 +237,7 @@ __device__ inline uint32_t ldval(const void* p, uint32_t i) {
 template <typename Tv, int S>
 __device__ inline void write_row(const DevMat& A, Tv* Y, int64_t ldy, uint32_t row, const uint32_t* r, int s,
                                  uint32_t alpha, uint32_t beta) {
-  Tv* yr = Y + (int64_t)row * ldy;
+  Tv* yr = Y + (int64_t)(A.rowmap ? A.rowmap[row] : row) * ldy;
 #pragma unroll
   for (int c = 0; c < S; ++c) {
     if (c < s) {
@@ -513,7 +513,7 @@ __device__ inline void sell_tile_rc(const DevMat& A, const Tile& T, const Tx* __
   for (int p = 0; p < S; ++p) {
     if (prow[p] < A.nrows && cok) {
       uint32_t r = AR::reduce(acc.a[p], A);
-      Tv* yr = Y + (int64_t)prow[p] * ldy + comp;
+      Tv* yr = Y + (int64_t)(A.rowmap ? A.rowmap[prow[p]] : prow[p]) * ldy + comp;
       uint32_t yo = beta ? (uint32_t)*yr : 0u;
       *yr = (Tv)((alpha == 1 && beta == 0) ? r : axpby(alpha, r, beta, yo, A.m, A.mu));
     }

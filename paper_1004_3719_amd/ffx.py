@@ -34,7 +34,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("acc", ctypes.c_int32), ("selector", ctypes.c_int32),
                 ("fixed_format", ctypes.c_int32), ("split_pm1", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("build_transpose", ctypes.c_int32), ("tile_entries", ctypes.c_int32),
-                ("compact_x", ctypes.c_int32), ("model_path", ctypes.c_char_p)]
+                ("compact_x", ctypes.c_int32), ("model_path", ctypes.c_char_p), ("reorder", ctypes.c_int32)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -44,7 +44,8 @@ class MatrixInfo(ctypes.Structure):
                 ("ntiles", ctypes.c_int64), ("max_row_terms", ctypes.c_int64), ("reduce_every", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("stream_bytes", ctypes.c_int64),
                 ("has_transpose", ctypes.c_int32), ("value_bytes", ctypes.c_int32),
-                ("format_blocks", ctypes.c_int64 * NUM_FORMATS)]
+                ("format_blocks", ctypes.c_int64 * NUM_FORMATS), ("reordered", ctypes.c_int32),
+                ("bandwidth_input", ctypes.c_int64), ("bandwidth_stored", ctypes.c_int64)]
 
 
 class BatchParams(ctypes.Structure):
@@ -110,6 +111,7 @@ _SIGS = {
     "ffx_selector_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "ffx_selector_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ffx_selector_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ffx_reorder_rcm": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ffx_block_features": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(BuildOpts),
                                           ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -179,7 +181,7 @@ PACKAGED_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "model
 
 
 def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=True, block_rows=4096,
-               build_transpose=False, tile_entries=0, compact_x=-1, model_path=None):
+               build_transpose=False, tile_entries=0, compact_x=-1, model_path=None, reorder=False):
     o = BuildOpts()
     lib().ffx_build_opts_default(ctypes.byref(o))
     o.acc = ACC[acc]
@@ -195,6 +197,7 @@ def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=Tr
     if selector == "learned" and not model_path:
         model_path = PACKAGED_MODEL  # the network trained for this GPU, shipped with the package
     o.model_path = model_path.encode() if model_path else None
+    o.reorder = int(bool(reorder))
     return o
 
 
@@ -480,6 +483,16 @@ def block_features(nrows, ncols, rowptr, col, val, m, **opts):
     _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
                                     int(m), ctypes.byref(o), out.ctypes.data, nb.value, None))
     return out[:nb.value]
+
+
+def reorder_rcm(n, rowptr, col):
+    """The reverse Cuthill-McKee order of a square pattern (ffx_reorder_rcm, host only): perm[new] = old."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    rp = rp - rp[0]
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    perm = np.empty(max(int(n), 1), np.int32)
+    _check(lib().ffx_reorder_rcm(int(n), rp.ctypes.data, c.ctypes.data, perm.ctypes.data))
+    return perm[:int(n)]
 
 
 class Selector:

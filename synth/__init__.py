@@ -272,3 +272,43 @@ def c5_matrix(k, seed=SEED0 + 4, m=M_C5, r0=0, r1=None, **kw):
     A.params = p
     A.row0 = r0
     return A
+
+
+def stencil(seed=SEED0 + 5, width=2048, height=1024, p_pm1=0.6, shuffle=True, m=M_C2):
+    """A 9-point stencil on a width x height grid: node (x, y) is coupled to itself and to its up to 8
+    grid neighbours (so rows hold 4, 6 or 9 entries and the pattern is symmetric). With shuffle, the
+    nodes are numbered by a seeded uniformly random permutation (the order of counter-based random
+    keys), so the grid's locality is present but hidden by the numbering; without, node (x, y) is
+    row y*width + x (a band of half-width width + 1). Each entry is +-1 with probability p_pm1 (fair
+    sign), else a uniform int32."""
+    n = width * height
+    g = np.arange(n, dtype=np.int64)
+    gx, gy = g % width, g // width
+    if shuffle:
+        order = np.argsort(raw(seed, n), kind="stable")  # order[label] = grid node
+        label = np.empty(n, np.int64)
+        label[order] = np.arange(n, dtype=np.int64)
+    else:
+        order, label = g, g
+    nb = np.full((n, 9), -1, np.int64)
+    q = 0
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            x, y = gx + dx, gy + dy
+            ok = (x >= 0) & (x < width) & (y >= 0) & (y < height)
+            nb[ok, q] = label[(y * width + x)[ok]]
+            q += 1
+    nb = nb[order]  # row r is grid node order[r]
+    nb[nb < 0] = n  # absent neighbours sort last
+    nb.sort(axis=1)
+    lens = (nb < n).sum(axis=1)
+    rowptr = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    col = nb[nb < n].astype(np.int32)
+    nnz = len(col)
+    u = unit(seed, 1, nnz)
+    sign = vector(seed, 2, nnz, 0, 1)
+    val = np.where(u < p_pm1, 2 * sign - 1, vector(seed, 3, nnz, -(2**31), 2**31 - 1))
+    A = Csr(n, n, rowptr, col, val, m=m, name="stencil%dx%d%s" % (width, height, "-shuffled" if shuffle else ""))
+    A.grid = (width, height)
+    return A

@@ -121,3 +121,94 @@ def test_check_block_argument_errors():
     assert L.ffx_check_block(65521, ctypes.c_void_p(16), 10, 1, 1, 7, None, ctypes.byref(bad)) == 1  # dtype
     assert bad.value == -1
     assert L.ffx_check_block(65521, None, 0, 1, 1, 0, None, ctypes.byref(bad)) == 0  # empty block
+
+
+# ---------------------------------------------------------------- reordering --
+def _bandwidth(rowptr, col, perm):
+    n = len(perm)
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    return int(np.abs(inv[rows] - inv[col]).max()) if len(col) else 0
+
+
+def _shuffled(rowptr, col, seed):
+    """The same pattern with its nodes renumbered by a seeded permutation."""
+    import synth
+    n = len(rowptr) - 1
+    lab = np.empty(n, np.int64)
+    lab[np.argsort(synth.raw(seed, n), kind="stable")] = np.arange(n)
+    rows = lab[np.repeat(np.arange(n), np.diff(rowptr))]
+    cols = lab[col]
+    o = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return rp, cols[o].astype(np.int32)
+
+
+def _path(n, parts=1):
+    """parts disjoint paths of n nodes each (tridiagonal blocks)."""
+    rows, cols = [], []
+    for b in range(parts):
+        for i in range(n):
+            for j in (i - 1, i, i + 1):
+                if 0 <= j < n:
+                    rows.append(b * n + i)
+                    cols.append(b * n + j)
+    N = n * parts
+    rp = np.zeros(N + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=N), out=rp[1:])
+    return rp, np.array(cols, np.int32)
+
+
+@pytest.mark.parametrize("parts", [1, 3])
+def test_rcm_recovers_a_shuffled_path(parts):
+    """A path graph renumbered at random has bandwidth ~n; reverse Cuthill-McKee from a
+    pseudo-peripheral node (an end of the path) puts it back in path order: bandwidth exactly 1."""
+    rp, col = _shuffled(*_path(500, parts), seed=3)
+    assert _bandwidth(rp, col, np.arange(500 * parts)) > 100
+    perm = P.reorder_rcm(500 * parts, rp, col)
+    assert np.array_equal(np.sort(perm), np.arange(500 * parts))
+    assert _bandwidth(rp, col, perm) == 1
+
+
+def test_rcm_stencil_against_scipy():
+    """On a shuffled 9-point stencil and on a random sparse pattern, the bandwidth after the
+    ordering is within 25% of scipy's reverse Cuthill-McKee."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+
+    import synth
+    A = synth.stencil(width=60, height=45, shuffle=True)
+    R = synth.rows(synth.spec(3000, 3000, 5, len_kind=synth.LEN_UNIFORM, len_a=0, len_b=3,
+                              col_kind=synth.COL_BANDED, band_lo=-40, band_hi=40))
+    for rp, col, n in [(A.rowptr, A.col, A.nrows), (*_shuffled(R.rowptr, R.col, 9), R.nrows)]:
+        perm = P.reorder_rcm(n, rp, col)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        M = sp.csr_matrix((np.ones(len(col)), col, rp), shape=(n, n))
+        ref = reverse_cuthill_mckee((M + M.T).tocsr(), symmetric_mode=True)
+        assert _bandwidth(rp, col, perm) <= 1.25 * _bandwidth(rp, col, ref) + 2
+        assert _bandwidth(rp, col, perm) < _bandwidth(rp, col, np.arange(n)) / 10
+
+
+def test_rcm_edge_cases():
+    assert len(P.reorder_rcm(0, np.zeros(1, np.int64), np.zeros(0, np.int32))) == 0
+    assert list(P.reorder_rcm(1, np.array([0, 0], np.int64), np.zeros(0, np.int32))) == [0]
+    # isolated nodes, self loops and a one-way entry: still a permutation
+    rp = np.array([0, 1, 1, 2, 3], np.int64)
+    col = np.array([0, 3, 3], np.int32)
+    perm = P.reorder_rcm(4, rp, col)
+    assert sorted(perm) == [0, 1, 2, 3]
+    with pytest.raises(P.FfxError) as e:
+        P.reorder_rcm(2, np.array([0, 1, 2], np.int64), np.array([0, 2], np.int32))
+    assert e.value.status == ffx.FFX_EINVAL
+    with pytest.raises(P.FfxError) as e:
+        P.reorder_rcm(2, np.array([0, 2, 1], np.int64), np.array([0, 1], np.int32))
+    assert e.value.status == ffx.FFX_EINVAL
+
+
+def test_reorder_needs_square():
+    rp, c, v = np.array([0, 1, 2], np.int64), np.array([0, 2], np.int32), np.array([5, 6], np.int64)
+    with pytest.raises(P.FfxError) as e:
+        P.Matrix.from_csr(2, 3, rp, c, v, 7, reorder=True)
+    assert e.value.status == ffx.FFX_EINVAL

@@ -556,3 +556,114 @@ def test_gf2_sequence(dev, orc, ffx, w, kind):
     want = np.stack([pack_bits(So[i]) for i in range(L)])
     assert np.array_equal(S.cpu().numpy(), want)
     assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
+
+
+# ------------------------------------------------------------- reordering --
+def reorder_cases():
+    st = synth.stencil(width=96, height=70, shuffle=True)
+    c2 = synth.c2(n=40_000)
+    c1 = synth.c1(n=5000)
+    return {"stencil": st, "powerlaw": c2, "plain": c1}
+
+
+@pytest.mark.parametrize("case", ["stencil", "powerlaw", "plain"])
+@pytest.mark.parametrize("stored_t", [False, True])
+@pytest.mark.parametrize("compact", [0, 1])
+def test_reordered_products(dev, orc, ffx, case, stored_t, compact):
+    """A matrix stored as P A P^T (reverse Cuthill-McKee order) gives the caller's A x, A^T x and
+    A X with alpha/beta, bit for bit, for one and several vectors and both dtypes (x gathered into
+    the stored order, with or without the 16-bit copy; y written through the row map, or scattered
+    back on the A^T path without a stored transpose)."""
+    A = reorder_cases()[case]
+    note("reordered", case, stored_t, compact)
+    M = ffx.from_synth(A, reorder=True, build_transpose=stored_t, compact_x=compact)
+    inf = M.info()
+    assert inf["reordered"] == 1
+    if case == "stencil":
+        assert inf["bandwidth_stored"] < inf["bandwidth_input"] / 10
+    x = vec(31, 1, A.ncols, A.m)
+    y0 = vec(31, 2, A.nrows, A.m)
+    for dt in (torch.int32, torch.int64):
+        assert np.array_equal(M.spmv(tdev(x, dev, dt)).cpu().numpy(), orc.spmv(A, x))
+        assert np.array_equal(M.spmv_t(tdev(x, dev, dt)).cpu().numpy(), orc.spmv_t(A, x))
+    y = tdev(y0, dev)
+    M.spmv(tdev(x, dev), alpha=7, beta=A.m - 3, y=y)
+    assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, 7, A.m - 3, y0))
+    y = tdev(y0, dev)
+    M.spmv_t(tdev(x, dev), alpha=5, beta=2, y=y)
+    assert np.array_equal(y.cpu().numpy(), orc.spmv_t(A, x, 5, 2, y0))
+    for s in (3, 16):
+        X = vec(31, 10 + s, A.ncols, A.m, s)
+        Y0 = vec(31, 30 + s, A.nrows, A.m, s)
+        Y = tdev(Y0, dev)
+        M.spmm(tdev(X, dev), alpha=3, beta=4, Y=Y)
+        assert np.array_equal(Y.cpu().numpy(), orc.spmm(A, X, 3, 4, Y0)), s
+        # a strided view: the caller's leading dimension is kept on the way back
+        big = torch.zeros((A.nrows, s + 5), dtype=torch.int32, device=dev)
+        M.spmm(tdev(X, dev), Y=big[:, 2:2 + s])
+        assert np.array_equal(big[:, 2:2 + s].cpu().numpy(), orc.spmm(A, X))
+        assert not big[:, :2].any() and not big[:, 2 + s:].any()
+    M.close()
+
+
+@pytest.mark.parametrize("acc", ["int64", "fp64"])
+def test_reordered_power_and_sequence(dev, orc, ffx, acc):
+    """A^k V and S_i = U^T A^i V with A^L V through a reordered handle: one permutation at each end."""
+    A = synth.stencil(width=80, height=50, shuffle=True, m=65521)
+    note("reordered power/sequence", acc)
+    M = ffx.from_synth(A, reorder=True, acc=acc)
+    V = vec(32, 1, A.nrows, A.m, 4)
+    U = vec(32, 2, A.nrows, A.m, 4)
+    for k in (0, 1, 2, 5):
+        got = M.power(k, tdev(V, dev, torch.int64)).cpu().numpy()
+        assert np.array_equal(got, orc.power(A, k, V)), k
+    L = 20
+    S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), L, want_last=True)
+    So, Wo = orc.sequence(A, U, V, L, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
+    M.close()
+
+
+def test_reordered_gf2(dev, orc, ffx):
+    """Packed GF(2) products and the GF(2) sequence through a reordered handle."""
+    A = synth.stencil(width=64, height=40, shuffle=True, m=2)
+    M = ffx.from_synth(A, reorder=True)
+    note("reordered gf2")
+    rng = np.random.default_rng(77)
+    for w in (1, 3):
+        X = rng.integers(-(2**31), 2**31, size=(A.ncols, w), dtype=np.int64).astype(np.int32)
+        Y = M.spmm_gf2(torch.from_numpy(X).to(dev)).cpu().numpy()
+        assert np.array_equal(Y, pack_bits(orc.spmm(A, unpack_bits(X)))), w
+    U = rng.integers(-(2**31), 2**31, size=(A.nrows, 2), dtype=np.int64).astype(np.int32)
+    V = rng.integers(-(2**31), 2**31, size=(A.nrows, 2), dtype=np.int64).astype(np.int32)
+    S, W = M.sequence_gf2(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), 10, want_last=True)
+    So, Wo = orc.sequence(A, unpack_bits(U), unpack_bits(V), 10, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), np.stack([pack_bits(So[i]) for i in range(10)]))
+    assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
+    M.close()
+
+
+def test_reordered_batch_refused(dev, ffx):
+    from paper_1004_3719_amd import Batch
+    A = synth.stencil(width=20, height=10, shuffle=True)
+    M = ffx.from_synth(A, reorder=True)
+    with pytest.raises(Exception):
+        Batch([M], [1])
+    M.close()
+
+
+def test_stencil_full_size_sampled(dev, orc, ffx):
+    """The 2,097,152-row shuffled stencil in the benchmark's configuration (reordered, packaged
+    selector): sampled rows against the oracle."""
+    A = synth.stencil()
+    note("stencil full size", A.nnz)
+    x = vec(33, 1, A.ncols, A.m)
+    rows = np.unique(np.concatenate([synth.vector(33, 2, 3000, 0, A.nrows - 1), [0, A.nrows - 1]]))
+    want = orc.spmv(subrows(A, rows), x)
+    for reorder in (True, False):
+        M = ffx.from_synth(A, reorder=reorder, selector="learned")
+        got = M.spmv(tdev(x, dev)).cpu().numpy()
+        assert np.array_equal(got[rows], want), reorder
+        assert got.min() >= 0 and got.max() < A.m
+        M.close()

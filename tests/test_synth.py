@@ -57,3 +57,32 @@ def test_c3_dead_columns():
 def test_vectors_in_range():
     v = synth.vector(1, 2, 100_000, 0, 65520)
     assert v.min() == 0 and v.max() == 65520
+
+
+def test_stencil_shape():
+    """The 9-point stencil: rows of 4 (corners), 6 (edges) or 9 entries, a symmetric pattern with the
+    diagonal, a band of half-width width + 1 in grid order, and the same pattern up to a relabelling
+    when shuffled."""
+    W, H = 37, 23
+    for shuffle in (False, True):
+        A = synth.stencil(width=W, height=H, shuffle=shuffle)
+        n = W * H
+        lens = np.diff(A.rowptr)
+        assert sorted(np.unique(lens)) == [4, 6, 9]
+        assert (lens == 4).sum() == 4 and (lens == 6).sum() == 2 * (W - 2) + 2 * (H - 2)
+        rows = np.repeat(np.arange(n), lens)
+        pairs = set(zip(rows.tolist(), A.col.tolist()))
+        assert all((j, i) in pairs for i, j in pairs)
+        assert all((i, i) in pairs for i in range(n))
+        bw = int(np.abs(A.col - rows).max())
+        if shuffle:
+            assert bw > 10 * (W + 1)
+        else:
+            assert bw == W + 1
+        assert np.all(np.diff(A.col)[np.diff(rows) == 0] > 0)  # sorted, distinct columns per row
+    u = synth.stencil(width=W, height=H, shuffle=False)
+    s = synth.stencil(width=W, height=H, shuffle=True)
+    assert u.nnz == s.nnz
+    assert np.array_equal(np.sort(np.diff(u.rowptr)), np.sort(np.diff(s.rowptr)))
+    frac = np.mean(np.isin(s.val, [1, -1]))
+    assert 0.5 < frac < 0.7
