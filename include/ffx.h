@@ -331,6 +331,39 @@ ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowpt
                               const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts, float* out,
                               int64_t cap, int64_t* nblocks);
 
+/* Order basis (sigma-basis) of an m x n power series over the prime field
+ * F_p, p < 2^31 (block Wiedemann step 2, Section 3.2; PM-Basis of Giorgi,
+ * Jeannerod and Villard 2003 with one-order-at-a-time M-Basis below 32 orders):
+ * M (m x m polynomial matrix, degree <= sigma) with M G = 0 mod x^sigma that
+ * is reduced with respect to the shifted degrees. At each order the rows are
+ * taken by increasing shifted degree (ties by index) and put in echelon form
+ * of the residual coefficient; rows that keep a nonzero residual (pivot column:
+ * their first nonzero entry) are multiplied by x. The result is exactly that
+ * of this process run one order at a time.
+ * G (device): entry (r, c) holds sigma coefficients at G + (r*n + c)*ldg,
+ * residues in [0, p-1]; ldg >= sigma. shift (host, m): the initial shifted
+ * degrees, in [0, 2^28]. M (device): entry (r, c) at M + (r*m + c)*ldm,
+ * ldm >= sigma + 1, coefficients beyond the degree zeroed. d_out (host, m):
+ * the final shifted degrees. Needs 1 <= n <= m <= 16, n <= 8, p prime
+ * (FFX_EINVAL otherwise). Waits for the stream. */
+ffx_status ffx_sigma_basis(uint32_t p, int32_t m, int32_t n, int64_t sigma, const uint32_t* G, int64_t ldg,
+                           const int32_t* shift, uint32_t* M, int64_t ldm, int32_t* d_out, void* stream);
+
+/* Block Wiedemann steps 2 and 3 (Section 3) on a sequence S_i = U^T A^i V,
+ * i < L (as ffx_sequence writes it: device, L x s x s, residues mod the prime
+ * p, dtype int32 or int64): the minimal left matrix generator F of the
+ * sequence from the order basis of [S(x); -I] with shifts 0 on its first s
+ * rows and 1 on the last s (the s rows of smallest shifted degree), and
+ *   *rank = deg det F - codeg det F,
+ * with deg det F = the sum of F's row degrees (deg_out, host, s entries) and
+ * codeg det F its x-adic valuation. With L = 2n/s + O(1) terms, random U and V
+ * and A meeting the preconditions of Kaltofen (1991), this is the rank of A.
+ * FFX_EUNSUPPORTED when the generator is not row reduced or det F vanishes
+ * (sequence too short or degenerate projections). s <= 8. Waits for the
+ * stream. */
+ffx_status ffx_sequence_rank(uint32_t p, int32_t s, int64_t L, const void* S, ffx_dtype dtype, int32_t* deg_out,
+                             int64_t* rank, int64_t* deg_det, int64_t* codeg_det, void* stream);
+
 /* The reordering used by ffx_build_opts.reorder, on the host alone (no GPU
  * call): reverse Cuthill-McKee (Cuthill and McKee 1969, reversed as George
  * 1971) on the pattern of A + A^T of the square n x n pattern (rowptr,

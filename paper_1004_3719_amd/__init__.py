@@ -5,7 +5,7 @@ include/ffx.h); `ffx` is its ctypes binding. Importing this package does not
 load the library; the first call does, and raises if it was not built.
 """
 from .ffx import (FORMATS, Batch, FfxError, Matrix, Selector, block_features, build_opts, check_block,  # noqa: F401
-                  lib, reorder_rcm, set_sequence_graph_batch, version)
+                  lib, reorder_rcm, sequence_rank, set_sequence_graph_batch, sigma_basis, version)
 
 __all__ = ["Matrix", "Batch", "Selector", "FfxError", "FORMATS", "block_features", "build_opts", "lib",
-           "set_sequence_graph_batch", "check_block", "reorder_rcm", "version"]
+           "set_sequence_graph_batch", "check_block", "reorder_rcm", "sigma_basis", "sequence_rank", "version"]

@@ -725,6 +725,20 @@ ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowpt
   });
 }
 
+ffx_status ffx_sigma_basis(uint32_t p, int32_t m, int32_t n, int64_t sigma, const uint32_t* G, int64_t ldg,
+                           const int32_t* shift, uint32_t* M, int64_t ldm, int32_t* d_out, void* stream) {
+  return guard([&] { sigma_basis(p, m, n, sigma, G, ldg, shift, M, ldm, d_out, (hipStream_t)stream); });
+}
+
+ffx_status ffx_sequence_rank(uint32_t p, int32_t s, int64_t L, const void* S, ffx_dtype dtype, int32_t* deg_out,
+                             int64_t* rank, int64_t* deg_det, int64_t* codeg_det, void* stream) {
+  return guard([&] {
+    check_dtype(dtype);
+    if (!deg_out || !rank || !deg_det || !codeg_det) fail(FFX_EINVAL, "NULL argument");
+    sequence_rank(p, s, L, S, dtype, deg_out, rank, deg_det, codeg_det, (hipStream_t)stream);
+  });
+}
+
 ffx_status ffx_reorder_rcm(int64_t n, const int64_t* rowptr, const int32_t* colidx, int32_t* perm) {
   return guard([&] {
     if (n < 0 || n > MAX_DIM) fail(FFX_EINVAL, "n = %lld outside [0, 2^30]", (long long)n);

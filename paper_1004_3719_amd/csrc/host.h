@@ -111,6 +111,13 @@ bool learned_formats(const std::string& model_path, const std::vector<BlockStats
                      hipStream_t stream);
 int matrix_arith_kind(const ffx_matrix_s& M);
 
+// Order basis and block-Wiedemann rank (sigma.hip); arguments as ffx_sigma_basis and
+// ffx_sequence_rank.
+void sigma_basis(uint32_t p, int m, int n, int64_t sigma, const uint32_t* G, int64_t ldg, const int32_t* shift,
+                 uint32_t* M, int64_t ldm, int32_t* d_out, hipStream_t st);
+void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, int32_t* deg_out, int64_t* rank,
+                   int64_t* deg_det, int64_t* codeg_det, hipStream_t st);
+
 }  // namespace ffx
 
 struct ffx_matrix_s {

@@ -1,0 +1,509 @@
+// Block Wiedemann steps 2 and 3 (Section 3) over a prime field F_p, p < 2^31:
+// the order basis (sigma-basis) of a power series by PM-Basis (Giorgi,
+// Jeannerod and Villard, ISSAC 2003; Section 3.2 "Parallelization of the
+// sigma-basis computation"), the minimal matrix generator of the sequence, and
+// rank = deg det F - codeg det F.
+//
+// PM-Basis splits the order in two halves: the basis M1 of the first half, the
+// middle product R = [x^s1 .. x^(s-1)] (M1 G), the basis M2 of R with M1's
+// degrees, and M = M2 M1. Orders up to LEAF are done by the one-order-at-a-time
+// M-Basis in a single workgroup whose basis lives in LDS. Because M-Basis only
+// looks at the residual coefficient [x^k](M G) and the degrees, the
+// divide-and-conquer result is the same basis, step for step, as M-Basis run
+// over the whole order.
+//
+// The polynomial matrix products are schoolbook convolutions on the vector
+// ALU (the paper multiplies through a DFT; p = 2^31 - 1 has no large
+// power-of-two roots of unity, so an NTT would need several primes and a CRT).
+// A workgroup computes 256 consecutive coefficients of one entry; for each
+// inner index q and each 256-coefficient chunk of A it stages the chunk of A and
+// the 511 coefficients of B that the tile needs in LDS, and every lane adds
+// 256 products into a 96-bit accumulator (64-bit sum plus a carry count), so a
+// coefficient is reduced once.
+#include <algorithm>
+#include <vector>
+
+#include "host.h"
+#include "launch.h"
+
+namespace ffx {
+
+constexpr int SB_LEAF = 32;    // orders done by the in-LDS M-Basis
+constexpr int SB_MAXM = 16;    // rows of the basis
+constexpr int SB_MAXN = 8;     // columns of the series
+constexpr int PM_TILE = 256;   // coefficients per workgroup in the products
+
+struct Field {
+  uint32_t p;
+  uint64_t mu;    // floor((2^64-1)/p)
+  uint32_t r64;   // 2^64 mod p
+  int mersenne;   // p = 2^31 - 1: products fold with shifts
+};
+
+__device__ inline uint32_t fmul(uint32_t a, uint32_t b, const Field& F) {
+  uint64_t x = (uint64_t)a * b;
+  if (F.mersenne) {  // x < 2^62: two folds bring it to at most p + 1
+    x = (x & 0x7FFFFFFFull) + (x >> 31);
+    x = (x & 0x7FFFFFFFull) + (x >> 31);
+    return (uint32_t)(x >= 0x7FFFFFFFull ? x - 0x7FFFFFFFull : x);
+  }
+  return mod_u64(x, F.p, F.mu);
+}
+
+// (hi * 2^64 + lo) mod p, hi < 2^32
+__device__ inline uint32_t fold96(uint64_t lo, uint32_t hi, const Field& F) {
+  uint64_t h = (uint64_t)(hi % F.p) * F.r64;
+  return mod_u64(h + mod_u64(lo, F.p, F.mu), F.p, F.mu);
+}
+
+__device__ inline uint32_t finv(uint32_t a, const Field& F) {  // a^(p-2), a != 0
+  uint32_t r = 1, b = a, e = F.p - 2;
+  while (e) {
+    if (e & 1) r = fmul(r, b, F);
+    b = fmul(b, b, F);
+    e >>= 1;
+  }
+  return r;
+}
+
+// C[r][c][t] = sum_q sum_j A[r][q][j] B[q][c][k0 + t - j] for t < len.
+// A: R x Q entries of la coefficients (entry (r,q) at A + (r*Q+q)*sa); B: Q x NC
+// entries of lb coefficients (stride sb); C: R x NC entries (stride sc).
+__global__ void __launch_bounds__(PM_TILE) k_polymul(const uint32_t* __restrict__ A, int64_t sa, int64_t la,
+                                                     const uint32_t* __restrict__ B, int64_t sb, int64_t lb,
+                                                     uint32_t* __restrict__ C, int64_t sc, int64_t k0, int64_t len,
+                                                     int Q, int NC, Field F) {
+  __shared__ uint32_t As[PM_TILE];
+  __shared__ uint32_t Bs[2 * PM_TILE];
+  const int tid = threadIdx.x;
+  const int r = blockIdx.y / NC, c = blockIdx.y % NC;
+  const int64_t kbase = k0 + (int64_t)blockIdx.x * PM_TILE;
+  uint64_t lo = 0;
+  uint32_t hi = 0;
+  const int64_t jlo = std::max<int64_t>(0, kbase - (lb - 1));
+  const int64_t jhi = std::min<int64_t>(la - 1, kbase + PM_TILE - 1);
+  for (int q = 0; q < Q; ++q) {
+    const uint32_t* a = A + (int64_t)(r * Q + q) * sa;
+    const uint32_t* b = B + (int64_t)(q * NC + c) * sb;
+    for (int64_t j0 = jlo; j0 <= jhi; j0 += PM_TILE) {
+      __syncthreads();
+      As[tid] = (j0 + tid <= jhi) ? a[j0 + tid] : 0u;
+      // Bs[u] = B[kbase - j0 - (PM_TILE-1) + u], u < 2*PM_TILE - 1
+      const int64_t base = kbase - j0 - (PM_TILE - 1);
+      for (int u = tid; u < 2 * PM_TILE - 1; u += PM_TILE) {
+        const int64_t idx = base + u;
+        Bs[u] = (idx >= 0 && idx < lb) ? b[idx] : 0u;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int jj = 0; jj < PM_TILE; ++jj) {
+        const uint64_t prod = (uint64_t)As[jj] * Bs[tid - jj + PM_TILE - 1];
+        lo += prod;
+        hi += lo < prod;
+      }
+    }
+  }
+  const int64_t t = (int64_t)blockIdx.x * PM_TILE + tid;
+  if (t < len) C[(int64_t)blockIdx.y * sc + t] = fold96(lo, hi, F);
+}
+
+// One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
+// with shifted degrees d (in/out, device). M: m x m entries of sm >= sg + 1 coefficients.
+__global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldg, int m, int n,
+                                                     int sg, int32_t* __restrict__ d, uint32_t* __restrict__ M,
+                                                     int64_t sm, Field F) {
+  constexpr int LC = SB_LEAF + 1;
+  __shared__ uint32_t Ms[2][SB_MAXM][SB_MAXM][LC];
+  __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF];
+  __shared__ uint32_t Dl[SB_MAXM][SB_MAXN];      // residual coefficient, reduced in place
+  __shared__ uint32_t T[SB_MAXM][SB_MAXM];       // this order's row transformation
+  __shared__ int piv[SB_MAXM];
+  __shared__ int dl[SB_MAXM];
+  __shared__ uint32_t fr[SB_MAXM];              // elimination factors by position in the row order
+  const int tid = threadIdx.x;
+  for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += 256) {
+    int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
+    Gs[r][c][k] = (r < m && c < n && k < sg) ? G[(int64_t)(r * n + c) * ldg + k] : 0u;
+  }
+  for (int i = tid; i < SB_MAXM * SB_MAXM * LC; i += 256) {
+    int r = i / (SB_MAXM * LC), c = (i / LC) % SB_MAXM, k = i % LC;
+    Ms[0][r][c][k] = (r == c && k == 0) ? 1u : 0u;
+  }
+  if (tid < m) dl[tid] = d[tid];
+  __syncthreads();
+  int cur = 0;
+  for (int k = 0; k < sg; ++k) {
+    // residual [x^k](M G): two lanes per entry, each over half of the inner index
+    {
+      const int o = tid >> 1, half = tid & 1;
+      uint64_t lo = 0;
+      uint32_t hi = 0;
+      const int r = o / SB_MAXN, c = o % SB_MAXN;
+      if (r < m && c < n) {
+        for (int q = half; q < m; q += 2)
+          for (int j = 0; j <= k; ++j) {
+            const uint64_t prod = (uint64_t)Ms[cur][r][q][j] * Gs[q][c][k - j];
+            lo += prod;
+            hi += lo < prod;
+          }
+      }
+      uint32_t part = (r < m && c < n) ? fold96(lo, hi, F) : 0u;
+      uint32_t other = __shfl_xor(part, 1);
+      if (half == 0 && r < m && c < n) {
+        uint32_t v = part + other;
+        Dl[r][c] = v >= F.p ? v - F.p : v;
+      }
+    }
+    __syncthreads();
+    // Echelon form of the residual, rows by increasing shifted degree (ties by
+    // index), right-looking: when a row keeps a nonzero residual it becomes a
+    // pivot (column: its first nonzero entry) and every later row is reduced by
+    // it at once, so each row meets the pivots before it in the order they were
+    // found, as in the one-row-at-a-time elimination. T accumulates the row
+    // combinations; pivot rows are multiplied by x below.
+    int order[SB_MAXM];
+    for (int i = 0; i < m; ++i) order[i] = i;
+    for (int i = 1; i < m; ++i)
+      for (int j = i; j > 0 && (dl[order[j]] < dl[order[j - 1]]); --j) {
+        const int t = order[j];
+        order[j] = order[j - 1];
+        order[j - 1] = t;
+      }
+    for (int idx = tid; idx < m * m; idx += 256) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
+    if (tid < m) piv[tid] = 0;
+    __syncthreads();
+    for (int oi = 0; oi < m; ++oi) {
+      const int i = order[oi];
+      int first = -1;
+      for (int c = 0; c < n && first < 0; ++c)
+        if (Dl[i][c]) first = c;
+      if (first < 0) continue;  // the same answer in every lane
+      const uint32_t inv = finv(Dl[i][first], F);
+      if (tid > oi && tid < m) {
+        const uint32_t x = Dl[order[tid]][first];
+        fr[tid] = x ? F.p - fmul(x, inv, F) : 0u;  // minus the factor of the row at position tid
+      }
+      __syncthreads();
+      const int w = n + m, later = m - oi - 1;
+      for (int task = tid; task < later * w; task += 256) {
+        const int pos = oi + 1 + task / w, col = task % w;
+        const uint32_t f = fr[pos];
+        if (!f) continue;
+        const int j = order[pos];
+        if (col < n) {
+          const uint32_t v = Dl[j][col] + fmul(f, Dl[i][col], F);
+          Dl[j][col] = v >= F.p ? v - F.p : v;
+        } else {
+          const uint32_t v = T[j][col - n] + fmul(f, T[i][col - n], F);
+          T[j][col - n] = v >= F.p ? v - F.p : v;
+        }
+      }
+      if (tid == 0) {
+        piv[i] = 1;
+        dl[i] += 1;
+      }
+      __syncthreads();
+    }
+    // M <- diag(x^piv) T M
+    const int nxt = cur ^ 1;
+    for (int idx = tid; idx < m * m * LC; idx += 256) {
+      const int i = idx / (m * LC), c = (idx / LC) % m, j = idx % LC;
+      const int js = piv[i] ? j - 1 : j;
+      uint32_t out = 0;
+      if (js >= 0 && js <= k) {  // M has degree <= k before order k
+        uint64_t lo = 0;
+        uint32_t hi = 0;
+        for (int q = 0; q < m; ++q) {
+          const uint64_t prod = (uint64_t)T[i][q] * Ms[cur][q][c][js];
+          lo += prod;
+          hi += lo < prod;
+        }
+        out = fold96(lo, hi, F);
+      }
+      Ms[nxt][i][c][j] = out;
+    }
+    cur = nxt;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * m * (sg + 1); idx += 256) {
+    const int i = idx / (m * (sg + 1)), c = (idx / (sg + 1)) % m, j = idx % (sg + 1);
+    M[(int64_t)(i * m + c) * sm + j] = Ms[cur][i][c][j];
+  }
+  if (tid < m) d[tid] = dl[tid];
+}
+
+// G = [S(x); -I] as 2s x s entries of L coefficients from S (L x s x s, dtype residues mod p).
+template <typename T>
+__global__ void k_sequence_series(const T* __restrict__ S, int64_t L, int s, uint32_t p, uint32_t* __restrict__ G) {
+  const int64_t total = (int64_t)2 * s * s * L;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / L, k = t % L;
+    const int r = (int)(e / s), c = (int)(e % s);
+    uint32_t v;
+    if (r < s) {
+      const int64_t x = (int64_t)S[(k * s + r) * s + c] % (int64_t)p;
+      v = (uint32_t)(x < 0 ? x + p : x);
+    } else {
+      v = (k == 0 && r - s == c) ? p - 1 : 0u;
+    }
+    G[t] = v;
+  }
+}
+
+// ------------------------------------------------------------------ host ----
+static Field make_field(uint32_t p) {
+  Field F;
+  F.p = p;
+  F.mu = UINT64_MAX / p;
+  F.r64 = (uint32_t)((((unsigned __int128)1) << 64) % p);
+  F.mersenne = p == 0x7FFFFFFFu;
+  return F;
+}
+
+static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B, int64_t sb, int64_t lb, uint32_t* C,
+                    int64_t sc, int64_t k0, int64_t len, int R, int Q, int NC, const Field& F, hipStream_t st) {
+  if (len <= 0) return;
+  dim3 grid((unsigned)((len + PM_TILE - 1) / PM_TILE), (unsigned)(R * NC));
+  hipLaunchKernelGGL(k_polymul, grid, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb, C, sc, k0, len,
+                     Q, NC, F);
+  FFX_HIP(hipGetLastError());
+}
+
+struct SbCtx {
+  Field F;
+  int m, n;
+  hipStream_t st;
+  int32_t* d_dev;  // m shifted degrees on the device
+};
+
+// Basis of G (m x n entries, stride sg, order sigma) into M (m x m entries, stride sm >= sigma + 1,
+// zero beyond the returned length); d: shifted degrees in and out. Returns the number of
+// coefficients of M that can be nonzero.
+static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, std::vector<int32_t>& d, uint32_t* M,
+                       int64_t sm) {
+  const int m = X.m, n = X.n;
+  const int32_t dmin = *std::min_element(d.begin(), d.end());
+  if (sigma <= SB_LEAF) {
+    FFX_HIP(hipMemcpyAsync(X.d_dev, d.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, X.st));
+    hipLaunchKernelGGL(k_mbasis_leaf, dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm, X.F);
+    FFX_HIP(hipGetLastError());
+    FFX_HIP(hipMemcpyAsync(d.data(), X.d_dev, m * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
+    FFX_HIP(hipStreamSynchronize(X.st));
+    const int32_t dmax = *std::max_element(d.begin(), d.end());
+    return std::min<int64_t>(sigma + 1, (int64_t)dmax - dmin + 1);
+  }
+  const int64_t s1 = sigma / 2, s2 = sigma - s1;
+  uint32_t *M1 = nullptr, *R = nullptr, *M2 = nullptr;
+  const size_t b1 = (size_t)m * m * (s1 + 1) * 4, bR = (size_t)m * n * s2 * 4, b2 = (size_t)m * m * (s2 + 1) * 4;
+  FFX_HIP(hipMallocAsync((void**)&M1, b1, X.st));
+  FFX_HIP(hipMallocAsync((void**)&R, bR, X.st));
+  FFX_HIP(hipMallocAsync((void**)&M2, b2, X.st));
+  try {
+    const int64_t l1 = pmbasis(X, G, sg, s1, d, M1, s1 + 1);
+    // R = [x^s1 .. x^(sigma-1)] (M1 G)
+    polymul(M1, s1 + 1, l1, G, sg, sigma, R, s2, s1, s2, m, m, n, X.F, X.st);
+    const int64_t l2 = pmbasis(X, R, s2, s2, d, M2, s2 + 1);
+    const int32_t dmax = *std::max_element(d.begin(), d.end());
+    const int64_t len = std::min<int64_t>(std::min<int64_t>(sigma + 1, l1 + l2 - 1), (int64_t)dmax - dmin + 1);
+    polymul(M2, s2 + 1, l2, M1, s1 + 1, l1, M, sm, 0, len, m, m, m, X.F, X.st);
+    if (len < sm) FFX_HIP(hipMemset2DAsync(M + len, sm * 4, 0, (sm - len) * 4, (size_t)m * m, X.st));
+    (void)hipFreeAsync(M1, X.st);
+    (void)hipFreeAsync(R, X.st);
+    (void)hipFreeAsync(M2, X.st);
+    return len;
+  } catch (...) {
+    (void)hipFreeAsync(M1, X.st);
+    (void)hipFreeAsync(R, X.st);
+    (void)hipFreeAsync(M2, X.st);
+    throw;
+  }
+}
+
+static bool is_prime(uint32_t p) {
+  if (p < 2) return false;
+  for (uint32_t q : {2u, 3u, 5u, 7u}) {
+    if (p % q == 0) return p == q;
+  }
+  uint32_t dd = p - 1;
+  int r = 0;
+  while (!(dd & 1)) {
+    dd >>= 1;
+    ++r;
+  }
+  auto mulm = [&](uint64_t a, uint64_t b) { return a * b % p; };
+  for (uint64_t a : {2ull, 3ull, 5ull, 7ull}) {  // deterministic below 3,215,031,751
+    uint64_t x = 1, b = a, e = dd;
+    while (e) {
+      if (e & 1) x = mulm(x, b);
+      b = mulm(b, b);
+      e >>= 1;
+    }
+    if (x == 1 || x == p - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r && comp; ++i) {
+      x = mulm(x, x);
+      if (x == p - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+void sigma_basis(uint32_t p, int m, int n, int64_t sigma, const uint32_t* G, int64_t ldg, const int32_t* shift,
+                 uint32_t* M, int64_t ldm, int32_t* d_out, hipStream_t st) {
+  if (!is_prime(p)) fail(FFX_EINVAL, "the order basis needs a prime modulus (%u is not prime)", p);
+  if (m < 1 || m > SB_MAXM || n < 1 || n > SB_MAXN || n > m)
+    fail(FFX_EINVAL, "m = %d, n = %d: need 1 <= n <= m <= %d and n <= %d", m, n, SB_MAXM, SB_MAXN);
+  if (sigma < 1) fail(FFX_EINVAL, "sigma = %lld < 1", (long long)sigma);
+  if (ldg < sigma || ldm < sigma + 1) fail(FFX_EINVAL, "ldg < sigma or ldm < sigma + 1");
+  if (!G || !M || !shift || !d_out) fail(FFX_EINVAL, "NULL argument");
+  std::vector<int32_t> d(shift, shift + m);
+  for (int32_t v : d)
+    if (v < 0 || v > (1 << 28)) fail(FFX_EINVAL, "shift %d outside [0, 2^28]", v);
+  SbCtx X{make_field(p), m, n, st, nullptr};
+  FFX_HIP(hipMallocAsync((void**)&X.d_dev, SB_MAXM * sizeof(int32_t), st));
+  try {
+    const int64_t len = pmbasis(X, G, ldg, sigma, d, M, ldm);
+    if (len < ldm) FFX_HIP(hipMemset2DAsync(M + len, ldm * 4, 0, (ldm - len) * 4, (size_t)m * m, st));
+  } catch (...) {
+    (void)hipFreeAsync(X.d_dev, st);
+    throw;
+  }
+  (void)hipFreeAsync(X.d_dev, st);
+  FFX_HIP(hipStreamSynchronize(st));
+  std::copy(d.begin(), d.end(), d_out);
+}
+
+// x-adic valuation of det F (s x s entries of K coefficients, row-major [r][c][k]) over F_p by
+// elimination over F_p[[x]]/x^K; -1 when det F = 0 mod x^K.
+static int64_t det_valuation(std::vector<uint64_t> A, int s, int64_t K, uint32_t p) {
+  auto at = [&](int r, int c) { return &A[((size_t)r * s + c) * K]; };
+  auto pw = [&](uint64_t a, uint64_t e) {
+    uint64_t r = 1;
+    a %= p;
+    while (e) {
+      if (e & 1) r = r * a % p;
+      a = a * a % p;
+      e >>= 1;
+    }
+    return r;
+  };
+  int64_t val = 0;
+  std::vector<uint64_t> u(K), ui(K), f(K);
+  for (int c = 0; c < s; ++c) {
+    int best = -1;
+    int64_t bv = K;
+    for (int r = c; r < s; ++r) {
+      const uint64_t* x = at(r, c);
+      for (int64_t k = 0; k < bv; ++k)
+        if (x[k]) {
+          best = r;
+          bv = k;
+          break;
+        }
+    }
+    if (best < 0) return -1;
+    if (best != c)
+      for (int cc = 0; cc < s; ++cc) std::swap_ranges(at(c, cc), at(c, cc) + K, at(best, cc));
+    val += bv;
+    if (val >= K) return -1;
+    // u = A[c][c] / x^bv, ui = 1/u
+    std::fill(u.begin(), u.end(), 0);
+    for (int64_t k = bv; k < K; ++k) u[k - bv] = at(c, c)[k];
+    const uint64_t i0 = pw(u[0], p - 2);
+    for (int64_t k = 0; k < K; ++k) {
+      uint64_t acc = 0;
+      for (int64_t j = 1; j <= k; ++j) acc = (acc + u[j] * ui[k - j]) % p;
+      ui[k] = k == 0 ? i0 : (p - acc) % p * i0 % p;
+    }
+    for (int r = c + 1; r < s; ++r) {
+      // f = (A[r][c] / x^bv) * ui; row r -= f * row c
+      std::fill(f.begin(), f.end(), 0);
+      for (int64_t k = 0; k + bv < K; ++k) {
+        const uint64_t q = at(r, c)[k + bv];
+        if (!q) continue;
+        for (int64_t j = 0; k + j < K; ++j) f[k + j] = (f[k + j] + q * ui[j]) % p;
+      }
+      for (int cc = c; cc < s; ++cc) {
+        uint64_t* y = at(r, cc);
+        const uint64_t* x = at(c, cc);
+        for (int64_t k = 0; k < K; ++k) {
+          if (!f[k]) continue;
+          for (int64_t j = 0; k + j < K; ++j) y[k + j] = (y[k + j] + (p - f[k]) * x[j]) % p;
+        }
+      }
+    }
+  }
+  return val;
+}
+
+void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, int32_t* deg_out, int64_t* rank,
+                   int64_t* deg_det, int64_t* codeg_det, hipStream_t st) {
+  if (s < 1 || s > SB_MAXN) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, SB_MAXN);
+  if (L < 1) fail(FFX_EINVAL, "L = %lld < 1", (long long)L);
+  if (!S) fail(FFX_EINVAL, "S is NULL");
+  if (!is_prime(p)) fail(FFX_EINVAL, "the rank needs a prime modulus (%u is not prime)", p);
+  const int m = 2 * s;
+  uint32_t *G = nullptr, *M = nullptr;
+  FFX_HIP(hipMallocAsync((void**)&G, (size_t)m * s * L * 4, st));
+  FFX_HIP(hipMallocAsync((void**)&M, (size_t)m * m * (L + 1) * 4, st));
+  std::vector<int32_t> d(m);
+  std::vector<uint32_t> Mh;
+  try {
+    const int64_t total = (int64_t)m * s * L;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+    if (dt == FFX_I32)
+      hipLaunchKernelGGL((k_sequence_series<int32_t>), dim3(blocks), dim3(256), 0, st, (const int32_t*)S, L, s, p, G);
+    else
+      hipLaunchKernelGGL((k_sequence_series<int64_t>), dim3(blocks), dim3(256), 0, st, (const int64_t*)S, L, s, p, G);
+    FFX_HIP(hipGetLastError());
+    std::vector<int32_t> shift(m, 0);
+    for (int i = s; i < m; ++i) shift[i] = 1;
+    sigma_basis(p, m, s, L, G, L, shift.data(), M, L + 1, d.data(), st);
+    Mh.resize((size_t)m * m * (L + 1));
+    FFX_HIP(hipMemcpyAsync(Mh.data(), M, Mh.size() * 4, hipMemcpyDeviceToHost, st));
+    FFX_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipFreeAsync(G, st);
+    (void)hipFreeAsync(M, st);
+    throw;
+  }
+  (void)hipFreeAsync(G, st);
+  (void)hipFreeAsync(M, st);
+  // the generator: the s rows of smallest shifted degree (ties by index), left s x s part
+  std::vector<int> rows(m);
+  for (int i = 0; i < m; ++i) rows[i] = i;
+  std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return d[a] < d[b]; });
+  rows.resize(s);
+  int64_t D = 0;
+  for (int i = 0; i < s; ++i) {
+    deg_out[i] = d[rows[i]];
+    D += d[rows[i]];
+    if (d[rows[i]] > L) fail(FFX_EUNSUPPORTED, "generator degree %d exceeds the sequence length", d[rows[i]]);
+  }
+  auto coef = [&](int r, int c, int64_t k) { return Mh[((size_t)rows[r] * m + c) * (L + 1) + k]; };
+  // row reduced: the reversed form's constant coefficients must be nonsingular, else deg det F is
+  // not the sum of the row degrees
+  {
+    std::vector<uint64_t> A0((size_t)s * s);
+    for (int r = 0; r < s; ++r)
+      for (int c = 0; c < s; ++c) A0[(size_t)r * s + c] = coef(r, c, 0);
+    if (det_valuation(A0, s, 1, p) != 0)
+      fail(FFX_EUNSUPPORTED, "the generator is not row reduced (sequence too short or degenerate projections)");
+  }
+  // codeg det F: F row i = lambda^deg_i Frev_i(1/lambda), so [lambda^k] F_i = [x^(deg_i - k)] Frev_i
+  int64_t e = -1;
+  for (int64_t K = 16; e < 0 && K <= (int64_t)4 * (D + 1); K *= 2) {
+    std::vector<uint64_t> A((size_t)s * s * K, 0);
+    for (int r = 0; r < s; ++r)
+      for (int c = 0; c < s; ++c)
+        for (int64_t k = 0; k < K && k <= deg_out[r]; ++k) A[((size_t)r * s + c) * K + k] = coef(r, c, deg_out[r] - k);
+    e = det_valuation(A, s, K, p);
+  }
+  if (e < 0) fail(FFX_EUNSUPPORTED, "det F vanishes: no rank from this sequence");
+  *deg_det = D;
+  *codeg_det = e;
+  *rank = D - e;
+}
+
+}  // namespace ffx

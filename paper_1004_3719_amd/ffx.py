@@ -111,6 +111,12 @@ _SIGS = {
     "ffx_selector_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "ffx_selector_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ffx_selector_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ffx_sigma_basis": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "ffx_sequence_rank": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "ffx_reorder_rcm": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ffx_block_features": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(BuildOpts),
@@ -483,6 +489,33 @@ def block_features(nrows, ncols, rowptr, col, val, m, **opts):
     _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
                                     int(m), ctypes.byref(o), out.ctypes.data, nb.value, None))
     return out[:nb.value]
+
+
+def sigma_basis(G, p, shift, stream=None):
+    """Order basis of the power series G (device int32 tensor m x n x sigma, residues mod the prime
+    p) to order sigma with the given shifted degrees (ffx_sigma_basis): (M, d) with M a device int32
+    tensor m x m x (sigma + 1) and d the final shifted degrees."""
+    import torch
+    m, n, sigma = (int(v) for v in G.shape)
+    G = G.contiguous()
+    M = torch.empty((m, m, sigma + 1), dtype=torch.int32, device=G.device)
+    sh = np.ascontiguousarray(shift, dtype=np.int32)
+    d = np.zeros(m, np.int32)
+    _check(lib().ffx_sigma_basis(int(p), m, n, sigma, ctypes.c_void_p(G.data_ptr()), sigma, sh.ctypes.data,
+                                 ctypes.c_void_p(M.data_ptr()), sigma + 1, d.ctypes.data, _stream(stream)))
+    return M, [int(v) for v in d]
+
+
+def sequence_rank(S, p, stream=None):
+    """Block Wiedemann steps 2-3 on a sequence S (device tensor L x s x s, int32 or int64, as
+    Matrix.sequence returns it; ffx_sequence_rank): (rank, deg det F, codeg det F, row degrees of F)."""
+    L, s = int(S.shape[0]), int(S.shape[1])
+    S = S.contiguous()
+    deg = np.zeros(s, np.int32)
+    r, D, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ffx_sequence_rank(int(p), s, L, ctypes.c_void_p(S.data_ptr()), _dt(S), deg.ctypes.data,
+                                   ctypes.byref(r), ctypes.byref(D), ctypes.byref(e), _stream(stream)))
+    return r.value, D.value, e.value, [int(v) for v in deg]
 
 
 def reorder_rcm(n, rowptr, col):

@@ -1,0 +1,88 @@
+"""GPU parity of block Wiedemann steps 2-3: the order basis (PM-Basis with M-Basis leaves) against
+the oracle's one-order-at-a-time M-Basis bit for bit, and the rank from the generator against the
+oracle's and the planted rank."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import sigma as osig
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+M31 = 2**31 - 1
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("m,n,sig,shift_kind,p", [
+    (2, 1, 1, "zero", 65521), (2, 1, 40, "zero", M31), (4, 2, 33, "gen", 65521), (16, 8, 31, "gen", M31),
+    (16, 8, 32, "gen", M31), (16, 8, 33, "gen", 65521), (16, 8, 64, "zero", M31), (16, 8, 100, "gen", M31),
+    (6, 3, 257, "rand", 65521), (16, 8, 300, "gen", M31), (5, 5, 70, "rand", 3), (16, 1, 90, "rand", 65521)])
+def test_sigma_basis_matches_oracle(dev, m, n, sig, shift_kind, p):
+    """Random series of every shape the entry point takes, orders around the leaf size (32) and
+    across several levels of the recursion, zero / generator / random shifts, small and large p."""
+    from paper_1004_3719_amd import sigma_basis
+    G = synth.vector(m * 1000 + n * 10 + sig, 7, m * n * sig, 0, p - 1).reshape(m, n, sig)
+    shift = {"zero": [0] * m, "gen": [0] * (m // 2) + [1] * (m - m // 2),
+             "rand": list(synth.vector(sig, 8, m, 0, 5))}[shift_kind]
+    print("[case] sigma basis", m, n, sig, shift_kind, p, flush=True)
+    M, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    Mo, do = osig.mbasis(G, sig, shift, p)
+    assert d == do
+    assert np.array_equal(M.cpu().numpy().astype(np.int64), Mo)
+
+
+def test_sigma_basis_rejects(dev):
+    from paper_1004_3719_amd import sigma_basis
+    G = torch.zeros((4, 2, 8), dtype=torch.int32, device=dev)
+    for p in (65520, 1):  # not prime
+        with pytest.raises(Exception):
+            sigma_basis(G, p, [0] * 4)
+    with pytest.raises(Exception):
+        sigma_basis(torch.zeros((18, 9, 8), dtype=torch.int32, device=dev), 65521, [0] * 18)
+
+
+@pytest.mark.parametrize("n,s,ndead,seed,p", [(40, 1, 3, 1, 65521), (60, 2, 5, 2, M31), (200, 4, 7, 3, M31),
+                                              (300, 8, 12, 4, M31), (257, 3, 0, 5, 65521), (500, 8, 20, 6, 65521)])
+def test_sequence_rank_small(dev, n, s, ndead, seed, p):
+    """Rank from the oracle's sequence through the GPU steps 2-3 equals the oracle's rank (itself
+    pinned to Gaussian elimination), with the same generator degrees; the GPU sequence of the same
+    operands gives the same answer."""
+    from paper_1004_3719_amd import Matrix, sequence_rank
+    A = synth.c3(seed=seed, n=n, k=4, ndead=ndead, m=p)
+    U = synth.vector(seed, 1, n * s, 0, p - 1).reshape(n, s)
+    V = synth.vector(seed, 2, n * s, 0, p - 1).reshape(n, s)
+    L = 2 * n // s + 3
+    print("[case] rank", n, s, ndead, p, flush=True)
+    So = oracle.get().sequence(A, U, V, L)
+    want = osig.rank(So, p)
+    _, dego = osig.generator(So, p)
+    r, D, e, deg = sequence_rank(torch.from_numpy(So).to(dev), p)
+    assert (r, D, e) == want and deg == dego
+    M = Matrix.from_synth(A)
+    Sg = M.sequence(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), L)
+    assert sequence_rank(Sg, p)[:3] == want
+
+
+def test_c3_rank_full_size(dev):
+    """The block-Wiedemann operand at full size (n = 200,000, 15 entries per row drawn from
+    n - 1,000 live columns, m = 2^31 - 1, s = 8, L = 50,003): the GPU sequence and steps 2-3 give
+    the planted rank n - 1,000, with one factor x per row of the generator (the 1,000 empty columns
+    make 0 an eigenvalue of geometric multiplicity 1,000 >= s)."""
+    from paper_1004_3719_amd import Matrix, sequence_rank
+    A = synth.c3()
+    U, V = synth.c3_blocks()
+    L = synth.c3_length(A.nrows, 8)
+    M = Matrix.from_synth(A)
+    print("[case] c3 full rank", flush=True)
+    S = M.sequence(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), L)
+    r, D, e, deg = sequence_rank(S, A.m)
+    assert r == A.nrows - 1000
+    assert e == 8 and D == sum(deg)
