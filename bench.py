@@ -21,7 +21,9 @@ Other configurations print the same kind of line:
   acc the accumulators (int64, fp64, fp32, centered fp32 and fp64) on the
       power-law matrix with m = 4093, times 1, 8 and 16 vectors;
   reorder  a randomly numbered 9-point stencil (2M rows), products in the
-      caller's numbering against reverse Cuthill-McKee storage.
+      caller's numbering against reverse Cuthill-McKee storage;
+  rank the whole block Wiedemann rank of the c3 operand: sequence, order
+      basis (PM-Basis), minimal generator, deg det - codeg det.
 """
 import argparse
 import hashlib
@@ -290,6 +292,58 @@ def bench_accumulators(args):
                           "accumulator applies) times 1, 8 and 16 vectors", "n": A.nrows, "nnz": A.nnz, "m": m,
               "acc": args.acc, "selector": args.selector, "kernel_hash": khash}
     line(A.nnz / (ms_main * 1e-3), ms_main, args, args.acc, config, roofline, None, {"accumulators": table})
+
+
+# ------------------------------------------------------------- block Wiedemann rank
+def bench_rank(args):
+    """Block Wiedemann rank of the sequence workload's operand (n = 200,000, 15 entries per row from
+    n - 1,000 live columns, m = 2^31 - 1, s = 8): step 1, the sequence S_i = U^T A^i V for i < L =
+    50,003 (hipGraph-replayed fused steps); steps 2-3, the order basis of [S(x); -I] (PM-Basis),
+    the minimal generator F and rank = deg det F - codeg det F, against the planted rank n - 1,000."""
+    import torch
+
+    import synth
+    from paper_1004_3719_amd import Matrix, sequence_rank
+
+    dev = torch.device("cuda:0")
+    A = synth.c3()
+    U_np, V_np = synth.c3_blocks()
+    s_ = U_np.shape[1]
+    L = synth.c3_length(A.nrows, s_)
+    M = Matrix.from_synth(A)
+    U, V = torch.from_numpy(U_np).to(dev), torch.from_numpy(V_np).to(dev)
+    # warm-up: a short sequence and a small basis
+    sequence_rank(M.sequence(U, V, 64), A.m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = M.sequence(U, V, L)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r, D, e, deg = sequence_rank(S, A.m)
+    t2 = time.perf_counter()
+    planted = A.nrows - 1000
+    log("sequence %.3f s, sigma basis + rank %.3f s: rank %d (planted %d), deg det %d, codeg %d"
+        % (t1 - t0, t2 - t1, r, planted, D, e))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's order basis, one order at a time, on a bounded prefix of the same sequence
+        from oracle import sigma as osig
+        Sh = S.cpu().numpy()
+        sig = 96
+        t3 = time.perf_counter()
+        osig.mbasis(osig.sequence_series(Sh[:sig], A.m), sig, [0] * s_ + [1] * s_, A.m)
+        t_cpu = time.perf_counter() - t3
+        cpu = {"value": round(sig / t_cpu, 1), "unit": "orders/s", "cores": 1, "kind": "oracle",
+               "sample": "order basis of the first %d terms (one order at a time, numpy, single thread)" % sig,
+               "seconds": round(t_cpu, 2)}
+    total = t2 - t0
+    config = {"workload": "block Wiedemann rank: n=200,000, 15 nnz/row from n-1,000 live columns, m=2^31-1, s=8, "
+                          "L=%d; sequence + order basis + generator + rank" % L, "n": A.nrows, "nnz": A.nnz, "L": L,
+              "s": s_}
+    extra = {"rank": r, "planted_rank": planted, "rank_correct": r == planted, "deg_det": D, "codeg_det": e,
+             "generator_degrees": deg, "sequence_s": round(t1 - t0, 3), "sigma_basis_and_rank_s": round(t2 - t1, 3)}
+    args.steps, args.warmup = 1, 1
+    line(A.nnz * s_ * L / total, total * 1e3, args, "u32 (mod 2^31-1)", config, None, cpu, extra)
 
 
 # ---------------------------------------------------------------- reorder
@@ -714,7 +768,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc", "reorder"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc", "reorder", "rank"])
     ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
     ap.add_argument("--acc", default="int64", choices=ACC_NAMES)
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
@@ -766,6 +820,8 @@ def main():
         bench_accumulators(args)
     elif args.config == "reorder":
         bench_reorder(args)
+    elif args.config == "rank":
+        bench_rank(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)

@@ -66,6 +66,31 @@ __device__ inline uint32_t finv(uint32_t a, const Field& F) {  // a^(p-2), a != 
   return r;
 }
 
+// Sums of products of two residues: for p = 2^31 - 1 each product is folded
+// below 2^32 and added to 64 bits (no reduction for 2^31 terms); otherwise the
+// products are added to a 96-bit sum.
+template <bool MERS>
+struct Acc96 {
+  uint64_t lo = 0;
+  uint32_t hi = 0;
+  __device__ inline void add(uint64_t prod) {
+    if (MERS) {
+      lo += (prod & 0x7FFFFFFFull) + (prod >> 31);
+    } else {
+      lo += prod;
+      hi += lo < prod;
+    }
+  }
+  __device__ inline uint32_t reduce(const Field& F) const {
+    if (MERS) {
+      uint64_t x = (lo & 0x7FFFFFFFull) + (lo >> 31);  // below 2^33
+      x = (x & 0x7FFFFFFFull) + (x >> 31);             // at most p + 3
+      return (uint32_t)(x >= 0x7FFFFFFFull ? x - 0x7FFFFFFFull : x);
+    }
+    return fold96(lo, hi, F);
+  }
+};
+
 // C[r][c][t] = sum_q sum_j A[r][q][j] B[q][c][k0 + t - j] for t < len.
 // A: R x Q entries of la coefficients (entry (r,q) at A + (r*Q+q)*sa); B: Q x NC
 // entries of lb coefficients (stride sb); C: R x NC entries (stride sc).
@@ -109,25 +134,28 @@ __global__ void __launch_bounds__(PM_TILE) k_polymul(const uint32_t* __restrict_
 
 // One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
 // with shifted degrees d (in/out, device). M: m x m entries of sm >= sg + 1 coefficients.
+template <bool MERS>
 __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldg, int m, int n,
                                                      int sg, int32_t* __restrict__ d, uint32_t* __restrict__ M,
                                                      int64_t sm, Field F) {
   constexpr int LC = SB_LEAF + 1;
   __shared__ uint32_t Ms[2][SB_MAXM][SB_MAXM][LC];
-  __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF];
+  __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF + 1];  // padded: the 8 columns fall in different banks
   __shared__ uint32_t Dl[SB_MAXM][SB_MAXN];      // residual coefficient, reduced in place
   __shared__ uint32_t T[SB_MAXM][SB_MAXM];       // this order's row transformation
   __shared__ int piv[SB_MAXM];
   __shared__ int dl[SB_MAXM];
-  __shared__ uint32_t fr[SB_MAXM];              // elimination factors by position in the row order
+  __shared__ uint32_t fr[SB_MAXM];              // entries of the later rows in the pivot column, by position
+  __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   const int tid = threadIdx.x;
   for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += 256) {
     int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
     Gs[r][c][k] = (r < m && c < n && k < sg) ? G[(int64_t)(r * n + c) * ldg + k] : 0u;
   }
-  for (int i = tid; i < SB_MAXM * SB_MAXM * LC; i += 256) {
+  for (int i = tid; i < SB_MAXM * SB_MAXM * LC; i += 256) {  // both buffers: coefficients above the degree stay 0
     int r = i / (SB_MAXM * LC), c = (i / LC) % SB_MAXM, k = i % LC;
     Ms[0][r][c][k] = (r == c && k == 0) ? 1u : 0u;
+    Ms[1][r][c][k] = 0u;
   }
   if (tid < m) dl[tid] = d[tid];
   __syncthreads();
@@ -136,18 +164,13 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
     // residual [x^k](M G): two lanes per entry, each over half of the inner index
     {
       const int o = tid >> 1, half = tid & 1;
-      uint64_t lo = 0;
-      uint32_t hi = 0;
+      Acc96<MERS> acc;
       const int r = o / SB_MAXN, c = o % SB_MAXN;
       if (r < m && c < n) {
         for (int q = half; q < m; q += 2)
-          for (int j = 0; j <= k; ++j) {
-            const uint64_t prod = (uint64_t)Ms[cur][r][q][j] * Gs[q][c][k - j];
-            lo += prod;
-            hi += lo < prod;
-          }
+          for (int j = 0; j <= k; ++j) acc.add((uint64_t)Ms[cur][r][q][j] * Gs[q][c][k - j]);
       }
-      uint32_t part = (r < m && c < n) ? fold96(lo, hi, F) : 0u;
+      uint32_t part = (r < m && c < n) ? acc.reduce(F) : 0u;
       uint32_t other = __shfl_xor(part, 1);
       if (half == 0 && r < m && c < n) {
         uint32_t v = part + other;
@@ -170,57 +193,91 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
         order[j - 1] = t;
       }
     for (int idx = tid; idx < m * m; idx += 256) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
-    if (tid < m) piv[tid] = 0;
+    if (tid < m) {
+      piv[tid] = 0;
+      sc[tid] = 1u;
+    }
     __syncthreads();
     for (int oi = 0; oi < m; ++oi) {
       const int i = order[oi];
       int first = -1;
-      for (int c = 0; c < n && first < 0; ++c)
-        if (Dl[i][c]) first = c;
+      uint32_t rowv[SB_MAXN];
+#pragma unroll
+      for (int c = 0; c < SB_MAXN; ++c) rowv[c] = c < n ? Dl[i][c] : 0u;  // independent loads
+#pragma unroll
+      for (int c = SB_MAXN - 1; c >= 0; --c)
+        if (rowv[c]) first = c;
       if (first < 0) continue;  // the same answer in every lane
-      const uint32_t inv = finv(Dl[i][first], F);
-      if (tid > oi && tid < m) {
-        const uint32_t x = Dl[order[tid]][first];
-        fr[tid] = x ? F.p - fmul(x, inv, F) : 0u;  // minus the factor of the row at position tid
-      }
+      // fraction free: row_j <- pv row_j - x_j row_i, which is the oracle's
+      // row_j - (x_j / pv) row_i times pv; sc[j] collects these factors
+      const uint32_t pv = rowv[first];
+      if (tid > oi && tid < m) fr[tid] = Dl[order[tid]][first];
       __syncthreads();
       const int w = n + m, later = m - oi - 1;
       for (int task = tid; task < later * w; task += 256) {
         const int pos = oi + 1 + task / w, col = task % w;
-        const uint32_t f = fr[pos];
-        if (!f) continue;
+        const uint32_t x = fr[pos];
+        if (!x) continue;
         const int j = order[pos];
+        const uint32_t nx = F.p - x;
         if (col < n) {
-          const uint32_t v = Dl[j][col] + fmul(f, Dl[i][col], F);
+          const uint32_t v = fmul(pv, Dl[j][col], F) + fmul(nx, Dl[i][col], F);
           Dl[j][col] = v >= F.p ? v - F.p : v;
         } else {
-          const uint32_t v = T[j][col - n] + fmul(f, T[i][col - n], F);
+          const uint32_t v = fmul(pv, T[j][col - n], F) + fmul(nx, T[i][col - n], F);
           T[j][col - n] = v >= F.p ? v - F.p : v;
         }
       }
+      if (tid > oi && tid < m && fr[tid]) sc[order[tid]] = fmul(sc[order[tid]], pv, F);
       if (tid == 0) {
         piv[i] = 1;
         dl[i] += 1;
       }
       __syncthreads();
     }
-    // M <- diag(x^piv) T M
-    const int nxt = cur ^ 1;
-    for (int idx = tid; idx < m * m * LC; idx += 256) {
-      const int i = idx / (m * LC), c = (idx / LC) % m, j = idx % LC;
-      const int js = piv[i] ? j - 1 : j;
-      uint32_t out = 0;
-      if (js >= 0 && js <= k) {  // M has degree <= k before order k
-        uint64_t lo = 0;
-        uint32_t hi = 0;
-        for (int q = 0; q < m; ++q) {
-          const uint64_t prod = (uint64_t)T[i][q] * Ms[cur][q][c][js];
-          lo += prod;
-          hi += lo < prod;
-        }
-        out = fold96(lo, hi, F);
+    // unscale: T_j <- T_j / sc[j], the inverses of all sc by one exponentiation
+    // (prefix products, one inverse, and back)
+    if (tid == 0) {
+      uint32_t pre[SB_MAXM + 1];
+      pre[0] = 1;
+      for (int j = 0; j < m; ++j) pre[j + 1] = fmul(pre[j], sc[j], F);
+      uint32_t inv = finv(pre[m], F);
+      for (int j = m - 1; j >= 0; --j) {
+        const uint32_t ij = fmul(inv, pre[j], F);
+        inv = fmul(inv, sc[j], F);
+        sc[j] = ij;
       }
-      Ms[nxt][i][c][j] = out;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int j = idx / m, q = idx % m;
+      T[j][q] = fmul(T[j][q], sc[j], F);
+    }
+    __syncthreads();
+    // M <- diag(x^piv) T M: one entry (i, c) per lane, T's row in registers.
+    // M has degree <= k before order k, so only coefficients 0..k+1 change
+    // (the buffers hold zeros above).
+    const int nxt = cur ^ 1;
+    {
+      const int i = tid / SB_MAXM, c = tid % SB_MAXM;
+      if (i < m && c < m) {
+        uint32_t t[SB_MAXM];
+#pragma unroll
+        for (int q = 0; q < SB_MAXM; ++q) t[q] = q < m ? T[i][q] : 0u;
+        const int sh = piv[i];
+        for (int j = 0; j <= k + 1 && j < LC; ++j) {
+          const int js = j - sh;
+          uint32_t out = 0;
+          if (js >= 0 && js <= k) {
+            Acc96<MERS> acc;
+#pragma unroll
+            for (int q = 0; q < SB_MAXM; ++q)
+              if (q < m) acc.add((uint64_t)t[q] * Ms[cur][q][c][js]);
+            out = acc.reduce(F);
+          }
+          Ms[nxt][i][c][j] = out;
+        }
+      }
     }
     cur = nxt;
     __syncthreads();
@@ -285,7 +342,12 @@ static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, s
   const int32_t dmin = *std::min_element(d.begin(), d.end());
   if (sigma <= SB_LEAF) {
     FFX_HIP(hipMemcpyAsync(X.d_dev, d.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, X.st));
-    hipLaunchKernelGGL(k_mbasis_leaf, dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm, X.F);
+    if (X.F.mersenne)
+      hipLaunchKernelGGL((k_mbasis_leaf<true>), dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm,
+                         X.F);
+    else
+      hipLaunchKernelGGL((k_mbasis_leaf<false>), dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm,
+                         X.F);
     FFX_HIP(hipGetLastError());
     FFX_HIP(hipMemcpyAsync(d.data(), X.d_dev, m * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
     FFX_HIP(hipStreamSynchronize(X.st));
