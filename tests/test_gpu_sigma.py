@@ -86,3 +86,24 @@ def test_c3_rank_full_size(dev):
     r, D, e, deg = sequence_rank(S, A.m)
     assert r == A.nrows - 1000
     assert e == 8 and D == sum(deg)
+
+
+@pytest.mark.parametrize("p", [M31, 65521])
+def test_sigma_basis_large_order(dev, p):
+    """Order 3,000 (several levels of 1,024-coefficient product tiles): M G = 0 mod x^3000 at sampled
+    coefficients computed here from the definition, every row within its degree bound, and the
+    degrees rising by n per order in all (G of full rank)."""
+    from paper_1004_3719_amd import sigma_basis
+    m, n, sig = 16, 8, 3000
+    G = synth.vector(p, 9, m * n * sig, 0, p - 1).reshape(m, n, sig)
+    shift = [0] * 8 + [1] * 8
+    print("[case] sigma basis large", p, flush=True)
+    Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    M = Mt.cpu().numpy().astype(np.int64)
+    assert sum(d) - sum(shift) == n * sig
+    for i in range(m):
+        assert not M[i, :, d[i] + 1:].any()
+    for k in [0, 1, 31, 32, 33, 1023, 1024, 1500, 2047, 2048, 2999]:
+        Grev = G[:, :, k::-1]  # G[.., k - j] for j = 0..k
+        prod = (M[:, :, None, :k + 1] * Grev[None, :, :, :]) % p
+        assert not (prod.sum(axis=(1, 3)) % p).any(), k
