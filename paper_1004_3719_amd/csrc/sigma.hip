@@ -94,60 +94,42 @@ struct Acc96 {
 // C[r][c][t] = sum_q sum_j A[r][q][j] B[q][c][k0 + t - j] for t < len.
 // A: R x Q entries of la coefficients (entry (r,q) at A + (r*Q+q)*sa); B: Q x NC
 // entries of lb coefficients (stride sb); C: R x NC entries (stride sc).
-// A workgroup computes PM_OUT = 4 * PM_TILE consecutive coefficients of one
-// entry, four consecutive ones per lane. For each chunk of PM_TILE coefficients
-// of A it stages them and the PM_OUT + PM_TILE - 1 coefficients of B they meet;
-// a lane keeps the four B values of its outputs in registers and, from one j to
-// the next, shifts them by one and loads a single new one, so each broadcast A
-// value and each B load serve four multiply-adds.
-constexpr int PM_OUT = 4 * PM_TILE;
-template <bool MERS>
 __global__ void __launch_bounds__(PM_TILE) k_polymul(const uint32_t* __restrict__ A, int64_t sa, int64_t la,
                                                      const uint32_t* __restrict__ B, int64_t sb, int64_t lb,
                                                      uint32_t* __restrict__ C, int64_t sc, int64_t k0, int64_t len,
                                                      int Q, int NC, Field F) {
   __shared__ uint32_t As[PM_TILE];
-  __shared__ uint32_t Bs[PM_OUT + PM_TILE];  // Bs[1 + u] = B[kbase - j0 - (PM_TILE - 1) + u]; Bs[0] padding
+  __shared__ uint32_t Bs[2 * PM_TILE];
   const int tid = threadIdx.x;
   const int r = blockIdx.y / NC, c = blockIdx.y % NC;
-  const int64_t kbase = k0 + (int64_t)blockIdx.x * PM_OUT;
-  Acc96<MERS> acc[4];
+  const int64_t kbase = k0 + (int64_t)blockIdx.x * PM_TILE;
+  uint64_t lo = 0;
+  uint32_t hi = 0;
   const int64_t jlo = std::max<int64_t>(0, kbase - (lb - 1));
-  const int64_t jhi = std::min<int64_t>(la - 1, kbase + PM_OUT - 1);
+  const int64_t jhi = std::min<int64_t>(la - 1, kbase + PM_TILE - 1);
   for (int q = 0; q < Q; ++q) {
     const uint32_t* a = A + (int64_t)(r * Q + q) * sa;
     const uint32_t* b = B + (int64_t)(q * NC + c) * sb;
     for (int64_t j0 = jlo; j0 <= jhi; j0 += PM_TILE) {
       __syncthreads();
       As[tid] = (j0 + tid <= jhi) ? a[j0 + tid] : 0u;
+      // Bs[u] = B[kbase - j0 - (PM_TILE-1) + u], u < 2*PM_TILE - 1
       const int64_t base = kbase - j0 - (PM_TILE - 1);
-      for (int u = tid; u < PM_OUT + PM_TILE - 1; u += PM_TILE) {
+      for (int u = tid; u < 2 * PM_TILE - 1; u += PM_TILE) {
         const int64_t idx = base + u;
-        Bs[1 + u] = (idx >= 0 && idx < lb) ? b[idx] : 0u;
+        Bs[u] = (idx >= 0 && idx < lb) ? b[idx] : 0u;
       }
-      if (tid == 0) Bs[0] = 0u;
       __syncthreads();
-      // output t = 4 tid + v meets A[j0 + jj] with B[kbase + t - j0 - jj] = Bs[1 + t - jj + PM_TILE - 1]
-      const int t0 = 4 * tid + PM_TILE;  // Bs index of (v = 0, jj = 0)
-      uint32_t bv0 = Bs[t0], bv1 = Bs[t0 + 1], bv2 = Bs[t0 + 2], bv3 = Bs[t0 + 3];
 #pragma unroll 8
       for (int jj = 0; jj < PM_TILE; ++jj) {
-        const uint64_t av = As[jj];
-        acc[0].add(av * bv0);
-        acc[1].add(av * bv1);
-        acc[2].add(av * bv2);
-        acc[3].add(av * bv3);
-        bv3 = bv2;
-        bv2 = bv1;
-        bv1 = bv0;
-        bv0 = Bs[t0 - jj - 1];  // index >= 4 tid >= 0 (Bs[0] is the padding)
+        const uint64_t prod = (uint64_t)As[jj] * Bs[tid - jj + PM_TILE - 1];
+        lo += prod;
+        hi += lo < prod;
       }
     }
   }
-  const int64_t t = (int64_t)blockIdx.x * PM_OUT + 4 * tid;
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    if (t + v < len) C[(int64_t)blockIdx.y * sc + t + v] = acc[v].reduce(F);
+  const int64_t t = (int64_t)blockIdx.x * PM_TILE + tid;
+  if (t < len) C[(int64_t)blockIdx.y * sc + t] = fold96(lo, hi, F);
 }
 
 // One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
@@ -338,13 +320,9 @@ static Field make_field(uint32_t p) {
 static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B, int64_t sb, int64_t lb, uint32_t* C,
                     int64_t sc, int64_t k0, int64_t len, int R, int Q, int NC, const Field& F, hipStream_t st) {
   if (len <= 0) return;
-  dim3 grid((unsigned)((len + PM_OUT - 1) / PM_OUT), (unsigned)(R * NC));
-  if (F.mersenne)
-    hipLaunchKernelGGL((k_polymul<true>), grid, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb, C,
-                       sc, k0, len, Q, NC, F);
-  else
-    hipLaunchKernelGGL((k_polymul<false>), grid, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb, C,
-                       sc, k0, len, Q, NC, F);
+  dim3 grid((unsigned)((len + PM_TILE - 1) / PM_TILE), (unsigned)(R * NC));
+  hipLaunchKernelGGL(k_polymul, grid, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb, C, sc, k0, len,
+                     Q, NC, F);
   FFX_HIP(hipGetLastError());
 }
 
