@@ -145,7 +145,6 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
   __shared__ uint32_t T[SB_MAXM][SB_MAXM];       // this order's row transformation
   __shared__ int piv[SB_MAXM];
   __shared__ int dl[SB_MAXM];
-  __shared__ uint32_t fr[SB_MAXM];              // entries of the later rows in the pivot column, by position
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   const int tid = threadIdx.x;
   for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += 256) {
@@ -157,7 +156,10 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
     Ms[0][r][c][k] = (r == c && k == 0) ? 1u : 0u;
     Ms[1][r][c][k] = 0u;
   }
-  if (tid < m) dl[tid] = d[tid];
+  if (tid < m) {
+    dl[tid] = d[tid];
+    sc[tid] = 1u;
+  }
   __syncthreads();
   int cur = 0;
   for (int k = 0; k < sg; ++k) {
@@ -167,8 +169,10 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
       Acc96<MERS> acc;
       const int r = o / SB_MAXN, c = o % SB_MAXN;
       if (r < m && c < n) {
-        for (int q = half; q < m; q += 2)
+        for (int q = half; q < m; q += 2) {
+#pragma unroll 8
           for (int j = 0; j <= k; ++j) acc.add((uint64_t)Ms[cur][r][q][j] * Gs[q][c][k - j]);
+        }
       }
       uint32_t part = (r < m && c < n) ? acc.reduce(F) : 0u;
       uint32_t other = __shfl_xor(part, 1);
@@ -193,32 +197,34 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
         order[j - 1] = t;
       }
     for (int idx = tid; idx < m * m; idx += 256) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
-    if (tid < m) {
-      piv[tid] = 0;
-      sc[tid] = 1u;
-    }
+    if (tid < m) piv[tid] = 0;
     __syncthreads();
+    // Fraction free: row_j <- pv row_j - x_j row_i is the oracle's
+    // row_j - (x_j / pv) row_i times pv. The rows of M (and so of the residual)
+    // stay scaled by the product sc[j] of these factors from order to order;
+    // the scales are divided out once, when the leaf writes its basis. The
+    // pivot column of the later rows becomes zero and is never written: the
+    // lanes read it in place, and the scans skip the columns of earlier pivots.
+    uint32_t used = 0;  // pivot columns so far (the same in every lane)
     for (int oi = 0; oi < m; ++oi) {
       const int i = order[oi];
       int first = -1;
       uint32_t rowv[SB_MAXN];
 #pragma unroll
-      for (int c = 0; c < SB_MAXN; ++c) rowv[c] = c < n ? Dl[i][c] : 0u;  // independent loads
+      for (int c = 0; c < SB_MAXN; ++c) rowv[c] = (c < n && !((used >> c) & 1u)) ? Dl[i][c] : 0u;
 #pragma unroll
       for (int c = SB_MAXN - 1; c >= 0; --c)
         if (rowv[c]) first = c;
       if (first < 0) continue;  // the same answer in every lane
-      // fraction free: row_j <- pv row_j - x_j row_i, which is the oracle's
-      // row_j - (x_j / pv) row_i times pv; sc[j] collects these factors
       const uint32_t pv = rowv[first];
-      if (tid > oi && tid < m) fr[tid] = Dl[order[tid]][first];
-      __syncthreads();
+      used |= 1u << first;
       const int w = n + m, later = m - oi - 1;
       for (int task = tid; task < later * w; task += 256) {
         const int pos = oi + 1 + task / w, col = task % w;
-        const uint32_t x = fr[pos];
-        if (!x) continue;
+        if (col < n && ((used >> col) & 1u)) continue;  // this pivot's column and the earlier ones
         const int j = order[pos];
+        const uint32_t x = Dl[j][first];
+        if (!x) continue;
         const uint32_t nx = F.p - x;
         if (col < n) {
           const uint32_t v = fmul(pv, Dl[j][col], F) + fmul(nx, Dl[i][col], F);
@@ -228,32 +234,13 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
           T[j][col - n] = v >= F.p ? v - F.p : v;
         }
       }
-      if (tid > oi && tid < m && fr[tid]) sc[order[tid]] = fmul(sc[order[tid]], pv, F);
+      if (tid > oi && tid < m && Dl[order[tid]][first]) sc[order[tid]] = fmul(sc[order[tid]], pv, F);
       if (tid == 0) {
         piv[i] = 1;
         dl[i] += 1;
       }
       __syncthreads();
     }
-    // unscale: T_j <- T_j / sc[j], the inverses of all sc by one exponentiation
-    // (prefix products, one inverse, and back)
-    if (tid == 0) {
-      uint32_t pre[SB_MAXM + 1];
-      pre[0] = 1;
-      for (int j = 0; j < m; ++j) pre[j + 1] = fmul(pre[j], sc[j], F);
-      uint32_t inv = finv(pre[m], F);
-      for (int j = m - 1; j >= 0; --j) {
-        const uint32_t ij = fmul(inv, pre[j], F);
-        inv = fmul(inv, sc[j], F);
-        sc[j] = ij;
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int j = idx / m, q = idx % m;
-      T[j][q] = fmul(T[j][q], sc[j], F);
-    }
-    __syncthreads();
     // M <- diag(x^piv) T M: one entry (i, c) per lane, T's row in registers.
     // M has degree <= k before order k, so only coefficients 0..k+1 change
     // (the buffers hold zeros above).
@@ -282,9 +269,23 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
     cur = nxt;
     __syncthreads();
   }
+  // divide out the row scales: all inverses from one exponentiation (prefix
+  // products, one inverse, and back)
+  if (tid == 0) {
+    uint32_t pre[SB_MAXM + 1];
+    pre[0] = 1;
+    for (int j = 0; j < m; ++j) pre[j + 1] = fmul(pre[j], sc[j], F);
+    uint32_t inv = finv(pre[m], F);
+    for (int j = m - 1; j >= 0; --j) {
+      const uint32_t ij = fmul(inv, pre[j], F);
+      inv = fmul(inv, sc[j], F);
+      sc[j] = ij;
+    }
+  }
+  __syncthreads();
   for (int idx = tid; idx < m * m * (sg + 1); idx += 256) {
     const int i = idx / (m * (sg + 1)), c = (idx / (sg + 1)) % m, j = idx % (sg + 1);
-    M[(int64_t)(i * m + c) * sm + j] = Ms[cur][i][c][j];
+    M[(int64_t)(i * m + c) * sm + j] = fmul(Ms[cur][i][c][j], sc[i], F);
   }
   if (tid < m) d[tid] = dl[tid];
 }
