@@ -329,7 +329,7 @@ def bench_rank(args):
         # the oracle's order basis, one order at a time, on a bounded prefix of the same sequence
         from oracle import sigma as osig
         Sh = S.cpu().numpy()
-        sig = 96
+        sig = 800  # about 10 s of numpy: the oracle's order basis costs O(sig^2) coefficient products
         t3 = time.perf_counter()
         osig.mbasis(osig.sequence_series(Sh[:sig], A.m), sig, [0] * s_ + [1] * s_, A.m)
         t_cpu = time.perf_counter() - t3
