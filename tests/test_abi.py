@@ -212,3 +212,32 @@ def test_reorder_needs_square():
     with pytest.raises(P.FfxError) as e:
         P.Matrix.from_csr(2, 3, rp, c, v, 7, reorder=True)
     assert e.value.status == ffx.FFX_EINVAL
+
+
+def test_sigma_and_rank_argument_errors():
+    """Bad arguments of the order basis and the rank are refused before any device work."""
+    L = P.lib()
+    sh = (ctypes.c_int32 * 16)()
+    d = (ctypes.c_int32 * 16)()
+    G = ctypes.c_void_p(16)
+    M = ctypes.c_void_p(32)
+    cases = [
+        (65520, 4, 2, 8, 8, 9),   # modulus not prime
+        (65521, 17, 8, 8, 8, 9),  # too many rows
+        (65521, 4, 9, 8, 8, 9),   # too many columns
+        (65521, 2, 3, 8, 8, 9),   # n > m
+        (65521, 4, 2, 0, 8, 9),   # empty order
+        (65521, 4, 2, 8, 7, 9),   # ldg < sigma
+        (65521, 4, 2, 8, 8, 8),   # ldm < sigma + 1
+    ]
+    for p, m, n, sig, ldg, ldm in cases:
+        st = L.ffx_sigma_basis(p, m, n, sig, G, ldg, sh, M, ldm, d, None)
+        assert st == ffx.FFX_EINVAL, (p, m, n, sig, ldg, ldm)
+    r, D, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    deg = (ctypes.c_int32 * 16)()
+    S = ctypes.c_void_p(16)
+    for p, s, Ln, dt in [(65521, 9, 10, 0), (65521, 0, 10, 0), (65521, 2, 0, 0), (65520, 2, 10, 0), (65521, 2, 10, 7)]:
+        st = L.ffx_sequence_rank(p, s, Ln, S, dt, deg, ctypes.byref(r), ctypes.byref(D), ctypes.byref(e), None)
+        assert st == ffx.FFX_EINVAL, (p, s, Ln, dt)
+    st = L.ffx_sequence_rank(65521, 2, 10, S, 0, None, ctypes.byref(r), ctypes.byref(D), ctypes.byref(e), None)
+    assert st == ffx.FFX_EINVAL
