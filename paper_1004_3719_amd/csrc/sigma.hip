@@ -358,9 +358,12 @@ static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, s
   const int64_t s1 = sigma / 2, s2 = sigma - s1;
   uint32_t *M1 = nullptr, *R = nullptr, *M2 = nullptr;
   const size_t b1 = (size_t)m * m * (s1 + 1) * 4, bR = (size_t)m * n * s2 * 4, b2 = (size_t)m * m * (s2 + 1) * 4;
-  FFX_HIP(hipMallocAsync((void**)&M1, b1, X.st));
-  FFX_HIP(hipMallocAsync((void**)&R, bR, X.st));
-  FFX_HIP(hipMallocAsync((void**)&M2, b2, X.st));
+  if (hipMallocAsync((void**)&M1, b1, X.st) != hipSuccess || hipMallocAsync((void**)&R, bR, X.st) != hipSuccess ||
+      hipMallocAsync((void**)&M2, b2, X.st) != hipSuccess) {
+    for (void* q : {(void*)M1, (void*)R, (void*)M2})
+      if (q) (void)hipFreeAsync(q, X.st);
+    fail(FFX_ENOMEM, "order basis workspace allocation failed (order %lld)", (long long)sigma);
+  }
   try {
     const int64_t l1 = pmbasis(X, G, sg, s1, d, M1, s1 + 1);
     // R = [x^s1 .. x^(sigma-1)] (M1 G)
@@ -424,7 +427,8 @@ void sigma_basis(uint32_t p, int m, int n, int64_t sigma, const uint32_t* G, int
   for (int32_t v : d)
     if (v < 0 || v > (1 << 28)) fail(FFX_EINVAL, "shift %d outside [0, 2^28]", v);
   SbCtx X{make_field(p), m, n, st, nullptr};
-  FFX_HIP(hipMallocAsync((void**)&X.d_dev, SB_MAXM * sizeof(int32_t), st));
+  if (hipMallocAsync((void**)&X.d_dev, SB_MAXM * sizeof(int32_t), st) != hipSuccess)
+    fail(FFX_ENOMEM, "order basis workspace allocation failed");
   try {
     const int64_t len = pmbasis(X, G, ldg, sigma, d, M, ldm);
     if (len < ldm) FFX_HIP(hipMemset2DAsync(M + len, ldm * 4, 0, (ldm - len) * 4, (size_t)m * m, st));
@@ -508,8 +512,12 @@ void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, in
   if (!is_prime(p)) fail(FFX_EINVAL, "the rank needs a prime modulus (%u is not prime)", p);
   const int m = 2 * s;
   uint32_t *G = nullptr, *M = nullptr;
-  FFX_HIP(hipMallocAsync((void**)&G, (size_t)m * s * L * 4, st));
-  FFX_HIP(hipMallocAsync((void**)&M, (size_t)m * m * (L + 1) * 4, st));
+  if (hipMallocAsync((void**)&G, (size_t)m * s * L * 4, st) != hipSuccess ||
+      hipMallocAsync((void**)&M, (size_t)m * m * (L + 1) * 4, st) != hipSuccess) {
+    if (G) (void)hipFreeAsync(G, st);
+    if (M) (void)hipFreeAsync(M, st);
+    fail(FFX_ENOMEM, "rank workspace allocation failed (L = %lld)", (long long)L);
+  }
   std::vector<int32_t> d(m);
   std::vector<uint32_t> Mh;
   try {
