@@ -146,6 +146,7 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
   __shared__ int piv[SB_MAXM];
   __shared__ int dl[SB_MAXM];
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
+  __shared__ int order[SB_MAXM];                // rows by (shifted degree, index)
   const int tid = threadIdx.x;
   for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += 256) {
     int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
@@ -188,16 +189,19 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
     // it at once, so each row meets the pivots before it in the order they were
     // found, as in the one-row-at-a-time elimination. T accumulates the row
     // combinations; pivot rows are multiplied by x below.
-    int order[SB_MAXM];
-    for (int i = 0; i < m; ++i) order[i] = i;
-    for (int i = 1; i < m; ++i)
-      for (int j = i; j > 0 && (dl[order[j]] < dl[order[j - 1]]); --j) {
-        const int t = order[j];
-        order[j] = order[j - 1];
-        order[j - 1] = t;
+    // row order: the position of row i is the number of rows before it by
+    // (shifted degree, index)
+    if (tid < m) {
+      const int di = dl[tid];
+      int pos = 0;
+      for (int j = 0; j < m; ++j) {
+        const int dj = dl[j];
+        pos += (dj < di) || (dj == di && j < tid);
       }
+      order[pos] = tid;
+      piv[tid] = 0;
+    }
     for (int idx = tid; idx < m * m; idx += 256) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
-    if (tid < m) piv[tid] = 0;
     __syncthreads();
     // Fraction free: row_j <- pv row_j - x_j row_i is the oracle's
     // row_j - (x_j / pv) row_i times pv. The rows of M (and so of the residual)
@@ -257,9 +261,20 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
           uint32_t out = 0;
           if (js >= 0 && js <= k) {
             Acc96<MERS> acc;
+            if (MERS) {  // four products of residues below 2^31 add below 2^64: one fold per four
 #pragma unroll
-            for (int q = 0; q < SB_MAXM; ++q)
-              if (q < m) acc.add((uint64_t)t[q] * Ms[cur][q][c][js]);
+              for (int q0 = 0; q0 < SB_MAXM; q0 += 4) {
+                uint64_t g = 0;
+#pragma unroll
+                for (int q = q0; q < q0 + 4; ++q)
+                  if (q < m) g += (uint64_t)t[q] * Ms[cur][q][c][js];
+                acc.lo += (g & 0x7FFFFFFFull) + (g >> 31);
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < SB_MAXM; ++q)
+                if (q < m) acc.add((uint64_t)t[q] * Ms[cur][q][c][js]);
+            }
             out = acc.reduce(F);
           }
           Ms[nxt][i][c][j] = out;
