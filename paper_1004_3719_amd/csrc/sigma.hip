@@ -132,6 +132,85 @@ __global__ void __launch_bounds__(PM_TILE) k_polymul(const uint32_t* __restrict_
   if (t < len) C[(int64_t)blockIdx.y * sc + t] = fold96(lo, hi, F);
 }
 
+// The same product with PM_OUT = 4 * PM_TILE coefficients per workgroup, four
+// consecutive ones per lane, for products large enough to fill the GPU with
+// such tiles: a lane keeps the B values of its four outputs in registers and
+// shifts them by one per j, reading the next four B values and four A values
+// (the same in every lane) with one aligned 16-byte read each, so each LDS read
+// serves eight multiply-adds. For p = 2^31 - 1 the four products an output
+// gets per group of four j are added raw (below 2^64) and folded once.
+constexpr int PM_OUT = 4 * PM_TILE;
+template <bool MERS>
+__global__ void __launch_bounds__(PM_TILE) k_polymul4(const uint32_t* __restrict__ A, int64_t sa, int64_t la,
+                                                      const uint32_t* __restrict__ B, int64_t sb, int64_t lb,
+                                                      uint32_t* __restrict__ C, int64_t sc, int64_t k0, int64_t len,
+                                                      int Q, int NC, Field F) {
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  __shared__ __align__(16) uint32_t As[PM_TILE];
+  __shared__ __align__(16) uint32_t Bs[PM_OUT + PM_TILE];  // Bs[1 + u] = B[kbase - j0 - (PM_TILE - 1) + u]
+  const int tid = threadIdx.x;
+  const int r = blockIdx.y / NC, c = blockIdx.y % NC;
+  const int64_t kbase = k0 + (int64_t)blockIdx.x * PM_OUT;
+  Acc96<MERS> acc[4];
+  const int64_t jlo = std::max<int64_t>(0, kbase - (lb - 1));
+  const int64_t jhi = std::min<int64_t>(la - 1, kbase + PM_OUT - 1);
+  for (int q = 0; q < Q; ++q) {
+    const uint32_t* a = A + (int64_t)(r * Q + q) * sa;
+    const uint32_t* b = B + (int64_t)(q * NC + c) * sb;
+    for (int64_t j0 = jlo; j0 <= jhi; j0 += PM_TILE) {
+      __syncthreads();
+      As[tid] = (j0 + tid <= jhi) ? a[j0 + tid] : 0u;
+      const int64_t base = kbase - j0 - (PM_TILE - 1);
+      for (int u = tid; u < PM_OUT + PM_TILE - 1; u += PM_TILE) {
+        const int64_t idx = base + u;
+        Bs[1 + u] = (idx >= 0 && idx < lb) ? b[idx] : 0u;
+      }
+      if (tid == 0) Bs[0] = 0u;
+      __syncthreads();
+      // output t = 4 tid + v meets A[j0 + jj] and Bs[t - jj + PM_TILE]
+      const int t0 = 4 * tid + PM_TILE;
+      uint32_t bv0 = Bs[t0], bv1 = Bs[t0 + 1], bv2 = Bs[t0 + 2], bv3 = Bs[t0 + 3];
+      for (int jj = 0; jj < PM_TILE; jj += 4) {
+        const u32x4_t a4 = *(const u32x4_t*)&As[jj];
+        const u32x4_t nb = *(const u32x4_t*)&Bs[t0 - jj - 4];  // index >= 4 tid >= 0
+        uint64_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+        auto step = [&](uint32_t av, uint32_t next) {
+          const uint64_t x = av;
+          if (MERS) {
+            g0 += x * bv0;
+            g1 += x * bv1;
+            g2 += x * bv2;
+            g3 += x * bv3;
+          } else {
+            acc[0].add(x * bv0);
+            acc[1].add(x * bv1);
+            acc[2].add(x * bv2);
+            acc[3].add(x * bv3);
+          }
+          bv3 = bv2;
+          bv2 = bv1;
+          bv1 = bv0;
+          bv0 = next;
+        };
+        step(a4.x, nb.w);
+        step(a4.y, nb.z);
+        step(a4.z, nb.y);
+        step(a4.w, nb.x);
+        if (MERS) {
+          acc[0].lo += (g0 & 0x7FFFFFFFull) + (g0 >> 31);
+          acc[1].lo += (g1 & 0x7FFFFFFFull) + (g1 >> 31);
+          acc[2].lo += (g2 & 0x7FFFFFFFull) + (g2 >> 31);
+          acc[3].lo += (g3 & 0x7FFFFFFFull) + (g3 >> 31);
+        }
+      }
+    }
+  }
+  const int64_t t = (int64_t)blockIdx.x * PM_OUT + 4 * tid;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (t + v < len) C[(int64_t)blockIdx.y * sc + t + v] = acc[v].reduce(F);
+}
+
 // One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
 // with shifted degrees d (in/out, device). M: m x m entries of sm >= sg + 1 coefficients.
 template <bool MERS>
@@ -336,6 +415,18 @@ static Field make_field(uint32_t p) {
 static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B, int64_t sb, int64_t lb, uint32_t* C,
                     int64_t sc, int64_t k0, int64_t len, int R, int Q, int NC, const Field& F, hipStream_t st) {
   if (len <= 0) return;
+  const int64_t tiles4 = (len + PM_OUT - 1) / PM_OUT;
+  if (tiles4 * R * NC >= 2048) {  // enough four-per-lane tiles to fill the GPU
+    dim3 grid4((unsigned)tiles4, (unsigned)(R * NC));
+    if (F.mersenne)
+      hipLaunchKernelGGL((k_polymul4<true>), grid4, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb,
+                         C, sc, k0, len, Q, NC, F);
+    else
+      hipLaunchKernelGGL((k_polymul4<false>), grid4, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb,
+                         C, sc, k0, len, Q, NC, F);
+    FFX_HIP(hipGetLastError());
+    return;
+  }
   dim3 grid((unsigned)((len + PM_TILE - 1) / PM_TILE), (unsigned)(R * NC));
   hipLaunchKernelGGL(k_polymul, grid, dim3(PM_TILE), 0, st, A, sa, std::max<int64_t>(la, 1), B, sb, lb, C, sc, k0, len,
                      Q, NC, F);

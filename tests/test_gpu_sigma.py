@@ -107,3 +107,36 @@ def test_sigma_basis_large_order(dev, p):
         Grev = G[:, :, k::-1]  # G[.., k - j] for j = 0..k
         prod = (M[:, :, None, :k + 1] * Grev[None, :, :, :]) % p
         assert not (prod.sum(axis=(1, 3)) % p).any(), k
+
+
+def _coeff_mod(M, G, k, p):
+    """[x^k](M G) mod p exactly in int64: B split into 16-bit halves keeps every sum below 2^63."""
+    m, n = M.shape[0], G.shape[1]
+    out = np.zeros((m, n), np.int64)
+    for q in range(M.shape[1]):
+        A = M[:, q, :k + 1]
+        B = G[q, :, k::-1][:, :A.shape[1]]
+        lo = (A @ (B & 0xFFFF).T) % p
+        hi = (A @ (B >> 16).T) % p
+        out = (out + lo + hi * 65536 % p) % p
+    return out
+
+
+@pytest.mark.parametrize("p", [M31, 65521])
+def test_sigma_basis_order_40k(dev, p):
+    """Order 40,000, where the top products of the recursion run on the four-coefficients-per-lane
+    tiles: the order condition at sampled coefficients (computed here from the definition), the
+    degree bounds and the total degree increase."""
+    from paper_1004_3719_amd import sigma_basis
+    m, n, sig = 16, 8, 40_000
+    G = synth.vector(p + 1, 10, m * n * sig, 0, p - 1).reshape(m, n, sig)
+    shift = [0] * 8 + [1] * 8
+    print("[case] sigma basis 40k", p, flush=True)
+    Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    M = Mt.cpu().numpy().astype(np.int64)
+    assert sum(d) - sum(shift) == n * sig
+    top = max(d) + 1
+    assert not M[:, :, top:].any()
+    M = M[:, :, :top]
+    for k in [0, 20_000, 20_001, 31_999, 39_999]:
+        assert not _coeff_mod(M, G, k, p).any(), k
