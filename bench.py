@@ -561,7 +561,7 @@ def bench_sequence(args):
     ev_ms = a.elapsed_time(b)
     per_iter_ms = ev_ms / L
     work = A.nnz * 8 * L
-    # survey per-iteration bytes: A (col 4 B + val 4 B + row pointers), W read and written, U read
+    # per-iteration bytes: A (col 4 B + val 4 B + row pointers), W read and written, U read
     b_iter = A.nnz * 8 + 4 * (A.nrows + 1) + 3 * A.nrows * 8 * 8
     cpu = None
     if not args.no_cpu_baseline:
@@ -804,7 +804,7 @@ def main():
                     os.path.join(ROOT, "profiles", "spmv_powerlaw_2M_counters.json"), args.pmc_command)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.config == "c2":
         bench_spmv(args, big=True)

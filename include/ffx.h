@@ -47,7 +47,7 @@ typedef enum {
   FFX_EBOUND = 2,       /* requested accumulator cannot hold one product exactly */
   FFX_ENOMEM = 3,       /* host or device allocation failed */
   FFX_EDEVICE = 4,      /* a HIP runtime call failed */
-  FFX_EUNSUPPORTED = 5  /* valid request outside what this build implements */
+  FFX_EUNSUPPORTED = 5  /* valid request outside what the library implements */
 } ffx_status;
 
 typedef enum { FFX_I32 = 0, FFX_I64 = 1 } ffx_dtype;
