@@ -337,13 +337,22 @@ def bench_rank(args):
                "sample": "order basis of the first %d terms (one order at a time, numpy, single thread)" % sig,
                "seconds": round(t_cpu, 2)}
     total = t2 - t0
+    # the dominant kernel is the sequence step: the same per-iteration algorithmic bytes as the
+    # sequence workload (A's columns and values and row pointers, W read and written, U read),
+    # over the mean time of one iteration of this run's sequence
+    b_iter = A.nnz * 8 + 4 * (A.nrows + 1) + 3 * A.nrows * s_ * 8
+    it_s = (t1 - t0) / L
+    roofline = {"bound": "hbm", "achieved": round(b_iter / it_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(b_iter / it_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_seq_step (sequence; order basis and rank not included)",
+                "kernel_ms": round(it_s * 1e3, 5), "algorithmic_bytes": int(b_iter)}
     config = {"workload": "block Wiedemann rank: n=200,000, 15 nnz/row from n-1,000 live columns, m=2^31-1, s=8, "
                           "L=%d; sequence + order basis + generator + rank" % L, "n": A.nrows, "nnz": A.nnz, "L": L,
               "s": s_}
     extra = {"rank": r, "planted_rank": planted, "rank_correct": r == planted, "deg_det": D, "codeg_det": e,
              "generator_degrees": deg, "sequence_s": round(t1 - t0, 3), "sigma_basis_and_rank_s": round(t2 - t1, 3)}
     args.steps, args.warmup = 1, 1
-    line(A.nnz * s_ * L / total, total * 1e3, args, "u32 (mod 2^31-1)", config, None, cpu, extra)
+    line(A.nnz * s_ * L / total, total * 1e3, args, "u32 (mod 2^31-1)", config, roofline, cpu, extra)
 
 
 # ---------------------------------------------------------------- reorder
