@@ -108,7 +108,7 @@ typedef struct {
                                (-1 = when x exceeds 1 MiB, 0 = never, 1 = always); never changes a result */
   const char* model_path;   /* learned selector weights; NULL = none */
   int32_t reorder;          /* square matrices: 1 = store P A P^T under the reverse Cuthill-McKee order
-                               of the pattern of A + A^T (Section 5, reordering A), so the x entries
+                               of the pattern of A + A^T (Section 4, reordering A), so the x entries
                                of a tile come from a narrow window; every entry point then takes and
                                returns vectors in the caller's order (one gather in, one scatter out
                                per call, once per call for ffx_power and ffx_sequence); never changes
@@ -268,7 +268,12 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
 
 /* Y_k <- A_k X_k for all k, one launch. X and Y are HOST arrays of `count`
  * DEVICE pointers; ldx[k] >= s[k], ldy[k] >= s[k] (host arrays). X_k has
- * ncols_k rows, Y_k nrows_k rows, all of element type dtype. */
+ * ncols_k rows, Y_k nrows_k rows, all of element type dtype.
+ * Unlike a matrix handle, a batch handle holds per-call device state (the
+ * operand table and the work counters that each call rewrites on its stream):
+ * calls on one batch handle (ffx_batch_spmm, ffx_batch_tune) must not overlap,
+ * so issue them on one stream, or order the streams, and from one host thread
+ * at a time. Separate batch handles over the same matrices are independent. */
 ffx_status ffx_batch_spmm(ffx_batch B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
                           ffx_dtype dtype, void* stream);
 
@@ -369,7 +374,7 @@ ffx_status ffx_sequence_rank(uint32_t p, int32_t s, int64_t L, const void* S, ff
  * 1971) on the pattern of A + A^T of the square n x n pattern (rowptr,
  * colidx), each connected part started from a pseudo-peripheral node (George
  * and Liu 1979), neighbours visited by increasing degree, ties by index.
- * perm (host, n entries) receives perm[new] = old. Section 5 names reordering
+ * perm (host, n entries) receives perm[new] = old. Section 4 names reordering
  * A as a way to faster products. */
 ffx_status ffx_reorder_rcm(int64_t n, const int64_t* rowptr, const int32_t* colidx, int32_t* perm);
 

@@ -28,22 +28,6 @@ def _inv(a, p):
     return pow(int(a) % p, p - 2, p)
 
 
-def poly_matmul(A, B, p, length=None):
-    """C = A B for polynomial matrices stored (rows, cols, coefficients), truncated to `length`."""
-    la, lb = A.shape[2], B.shape[2]
-    L = la + lb - 1 if length is None else length
-    C = np.zeros((A.shape[0], B.shape[1], L), np.int64)
-    for i in range(min(la, L)):
-        a = A[:, :, i]
-        if not a.any():
-            continue
-        hi = min(lb, L - i)
-        # (r, q) x (q, c, j) -> (r, c, j), each product reduced before the sums
-        prod = (a[:, :, None, None] * B[None, :, :, :hi]) % p
-        C[:, :, i:i + hi] = (C[:, :, i:i + hi] + prod.sum(axis=1)) % p
-    return C
-
-
 def mbasis(G, sigma, shift, p):
     """Order basis of G (m x n x >= sigma coefficients, residues mod the prime p) to order sigma
     with the given shifted degrees. Returns (M, d): M is m x m x (sigma + 1), d the final shifted
@@ -104,9 +88,11 @@ def generator(S, p):
 def det_valuation(F, p, K=8):
     """x-adic valuation of det F for a square polynomial matrix F (s x s x len) over F_p, by
     Gaussian elimination over the truncated power series F_p[[x]]/x^K, K doubling until the
-    determinant is nonzero mod x^K. None when F is singular up to order 2^20."""
+    determinant is nonzero mod x^K. det F is a polynomial of degree at most s * (len - 1), so once
+    K exceeds that degree a determinant that vanishes mod x^K is zero: None (F singular)."""
     s = F.shape[0]
-    while K <= 1 << 20:
+    limit = s * max(F.shape[2] - 1, 0) + 1
+    while True:
         A = np.zeros((s, s, K), np.int64)
         t = min(K, F.shape[2])
         A[:, :, :t] = F[:, :, :t] % p
@@ -137,8 +123,9 @@ def det_valuation(F, p, K=8):
                     A[r, cc] = (A[r, cc] - _series_mul(f, A[c, cc], p, K)) % p
         if ok and val < K:
             return val
+        if K >= limit:
+            return None
         K *= 2
-    return None
 
 
 def _series_mul(a, b, p, K):

@@ -21,9 +21,17 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
+def _newest_header():
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads.append(os.path.join(os.path.dirname(HERE), "include", "ffx.h"))
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def _compile(src, force=True, newest_header=0.0):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(path), newest_header):
+        return obj
     cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = DEVICE_FLAGS
@@ -35,12 +43,14 @@ def _compile(src):
     return obj
 
 
-def build(verbose=True, jobs=None):
+def build(verbose=True, jobs=None, force=True):
+    """Compiles every source (force) or only those older than their object file and the headers."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(8, len(srcs))
+    nh = _newest_header()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, force, nh), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-fopenmp", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,4 +63,4 @@ def build(verbose=True, jobs=None):
 
 
 if __name__ == "__main__":
-    build()
+    build(force="--changed" not in sys.argv)

@@ -25,24 +25,6 @@ void fail(ffx_status st, const char* fmt, ...) {
   throw Error{st, buf};
 }
 
-template <class F>
-static ffx_status guard(F&& f) {
-  try {
-    f();
-    g_last_error.clear();
-    return FFX_OK;
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return FFX_ENOMEM;
-  } catch (...) {
-    g_last_error = "unexpected internal error";
-    return FFX_EDEVICE;
-  }
-}
-
 // iterations per hipGraph replay of ffx_sequence (0: direct launches)
 static std::atomic<int> g_seq_graph_batch{64};
 
@@ -166,7 +148,7 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
     if (b < 1)
       fail(FFX_EBOUND, "the %s accumulator cannot hold one product of residues modulo %u exactly",
            acc_name(po.acc), m);
-    // reordering (Section 5): the handle stores B = P A P^T and keeps perm
+    // reordering (Section 4, the conclusion): the handle stores B = P A P^T and keeps perm
     RCsr B;
     if (po.reorder) {
       if (A.nrows != A.ncols)
@@ -253,8 +235,6 @@ static void check_disjoint(const char* a, const void* pa, int64_t na, int64_t ld
   if (a0 < b1 && b0 < a1) fail(FFX_EINVAL, "%s and %s overlap", a, b);
 }
 
-static void product_core(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
-                         void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st, int64_t nin, int64_t nout);
 
 // For a reordered handle: gathers the caller's n x s block X (and Y when
 // y_in) into compact copies in the stored order, runs f(xp, yp), which leaves
@@ -285,8 +265,9 @@ static void permuted(const ffx_matrix_s& M, int64_t n, int s, size_t esz, const 
   FFX_HIP(e);
 }
 
-static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
-                    void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st) {
+// Checks the arguments of a product; returns false when there is nothing to compute.
+static bool check_product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx,
+                          uint32_t beta, const void* Y, int64_t ldy, ffx_dtype dt) {
   if (!M) fail(FFX_EINVAL, "matrix handle is NULL");
   check_dtype(dt);
   if (s < 1 || s > MAX_S) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, MAX_S);
@@ -296,62 +277,86 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
   check_block("x", X, nin, s, ldx);
   check_block("y", Y, nout, s, ldy);
   check_disjoint("x", X, nin, ldx, "y", Y, nout, ldy, s, dt);
-  if (nout == 0) return;
-  if (M->perm && !(trans && !M->has_t)) {
-    // square and stored as P A P^T: gather x into the stored order (into the 16-bit copy when the
-    // product takes one) and let the tiles write each row of y to its caller's row
-    const Encoded& E = trans ? M->AT : M->A;
-    DevMat dm = E.dm;
-    dm.rowmap = M->perm;
-    const bool c16 = s == 1 && M->compact_x;
-    const size_t bytes = c16 ? (size_t)nin * 2 : (size_t)nin * s * esize(dt);
-    warm_pool(st);
-    void* xp = nullptr;
-    if (hipMallocAsync(&xp, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
-    hipError_t e = c16 ? launch_permute_to_u16(dt, X, ldx, (uint16_t*)xp, M->perm, nin, st)
-                       : launch_permute_rows(esize(dt), X, ldx, xp, s, M->perm, nin, s, false, st);
-    if (e == hipSuccess)
-      e = launch_tiles(arith_kind(*M), dm, E.max_tile_entries, dt, c16 ? nullptr : xp, s, Y, ldy, s, alpha, beta, st,
-                       c16 ? (const uint16_t*)xp : nullptr);
-    (void)hipFreeAsync(xp, st);
+  return nout > 0;
+}
+
+// A row product runs the tiles of an encoded operator: A, or the stored A^T.
+// The other transposed product scatters the entries of A.
+static bool row_product(const ffx_matrix_s& M, bool trans) { return !trans || M.has_t; }
+
+// Device bytes of the temporary a row product with s vectors needs: the
+// 16-bit copy of x (one vector, m <= 65536, compact_x), or x gathered into the
+// stored order of a reordered handle (into that 16-bit copy when there is one).
+static size_t row_scratch_bytes(const ffx_matrix_s& M, bool trans, int s, ffx_dtype dt) {
+  const int64_t nin = trans ? M.info.nrows : M.info.ncols;
+  const bool c16 = s == 1 && M.compact_x;
+  if (nin == 0) return 0;
+  if (c16) return (size_t)nin * 2;
+  return M.perm ? (size_t)nin * s * esize(dt) : 0;
+}
+
+// The row product with its temporary in `scratch` (row_scratch_bytes of device
+// memory, or null when that is 0). Allocates nothing.
+static hipError_t row_product_in(const ffx_matrix_s& M, bool trans, int s, uint32_t alpha, const void* X,
+                                 int64_t ldx, uint32_t beta, void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st,
+                                 void* scratch) {
+  const Encoded& E = trans ? M.AT : M.A;
+  const int64_t nin = trans ? M.info.nrows : M.info.ncols;
+  const int ak = arith_kind(M);
+  const bool c16 = s == 1 && M.compact_x && nin > 0;
+  DevMat dm = E.dm;
+  if (M.perm) {
+    // stored as P A P^T: gather x into the stored order (into the 16-bit copy when the product takes
+    // one) and let the tiles write each row of y to its caller's row
+    dm.rowmap = M.perm;
+    hipError_t e = c16 ? launch_permute_to_u16(dt, X, ldx, (uint16_t*)scratch, M.perm, nin, st)
+                       : launch_permute_rows(esize(dt), X, ldx, scratch, s, M.perm, nin, s, false, st);
+    if (e != hipSuccess) return e;
+    return launch_tiles(ak, dm, E.max_tile_entries, dt, c16 ? nullptr : scratch, s, Y, ldy, s, alpha, beta, st,
+                        c16 ? (const uint16_t*)scratch : nullptr);
+  }
+  if (c16) {
+    hipError_t e = launch_compact_x(dt, X, ldx, (uint16_t*)scratch, nin, st);
+    if (e != hipSuccess) return e;
+    return launch_tiles(ak, dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st,
+                        (const uint16_t*)scratch);
+  }
+  return launch_tiles(ak, dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st);
+}
+
+static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
+                    void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st) {
+  if (!check_product(M, trans, s, alpha, X, ldx, beta, Y, ldy, dt)) return;
+  const int64_t nin = trans ? M->info.nrows : M->info.ncols;
+  const int64_t nout = trans ? M->info.ncols : M->info.nrows;
+  if (row_product(*M, trans)) {
+    const size_t bytes = row_scratch_bytes(*M, trans, s, dt);
+    void* scratch = nullptr;
+    if (bytes) {
+      warm_pool(st);
+      if (hipMallocAsync(&scratch, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+    }
+    hipError_t e = row_product_in(*M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, scratch);
+    if (scratch) (void)hipFreeAsync(scratch, st);
     FFX_HIP(e);
     return;
   }
-  if (M->perm) {  // the scatter form of A^T: gather x (and y when beta != 0), scatter y back
-    permuted(*M, nin, s, esize(dt), X, ldx, Y, ldy, beta != 0, st, [&](void* xp, void* yp) {
-      product_core(M, trans, s, alpha, xp, s, beta, yp, s, dt, st, nin, nout);
-    });
-    return;
-  }
-  product_core(M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, nin, nout);
-}
-
-static void product_core(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
-                         void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st, int64_t nin, int64_t nout) {
-  if (trans && !M->has_t) {  // scatter the entries of A with 64-bit integer atomics
+  // the scatter form of A^T, with 64-bit integer atomics into a temporary
+  auto scatter = [&](const void* xs, int64_t ldxs, void* ys, int64_t ldys) {
     warm_pool(st);
     unsigned long long* acc = nullptr;
     size_t bytes = (size_t)nout * s * sizeof(uint64_t);
     if (hipMallocAsync((void**)&acc, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes", bytes);
-    hipError_t e = launch_transpose_scatter(M->md.small(), M->A.dm, dt, X, ldx, Y, ldy, s, alpha, beta, acc, st);
+    hipError_t e = launch_transpose_scatter(M->md.small(), M->A.dm, dt, xs, ldxs, ys, ldys, s, alpha, beta, acc, st);
     (void)hipFreeAsync(acc, st);
     FFX_HIP(e);
+  };
+  if (M->perm) {  // gather x (and y when beta != 0) into the stored order, scatter y back
+    permuted(*M, nin, s, esize(dt), X, ldx, Y, ldy, beta != 0, st,
+             [&](void* xp, void* yp) { scatter(xp, s, yp, s); });
     return;
   }
-  const Encoded& E = trans ? M->AT : M->A;
-  const int ak = arith_kind(*M);
-  if (s == 1 && M->compact_x && nin > 0) {
-    warm_pool(st);
-    uint16_t* x16 = nullptr;
-    if (hipMallocAsync((void**)&x16, (size_t)nin * 2, st) != hipSuccess)
-      fail(FFX_ENOMEM, "hipMallocAsync of %lld bytes failed", (long long)nin * 2);
-    hipError_t e = launch_compact_x(dt, X, ldx, x16, nin, st);
-    if (e == hipSuccess) e = launch_tiles(ak, E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st, x16);
-    (void)hipFreeAsync(x16, st);
-    FFX_HIP(e);
-    return;
-  }
-  FFX_HIP(launch_tiles(ak, E.dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st));
+  scatter(X, ldx, Y, ldy);
 }
 
 // W = A^k V for k >= 1 on the stored operator; the last product writes its

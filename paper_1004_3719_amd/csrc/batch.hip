@@ -288,23 +288,6 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
     if (B->cls_n[c]) FFX_HIP(launch_class(c, st));
 }
 
-template <class F>
-static ffx_status bguard(F&& f) {
-  try {
-    f();
-    set_last_error("");
-    return FFX_OK;
-  } catch (const Error& e) {
-    set_last_error(e.msg);
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return FFX_ENOMEM;
-  } catch (...) {
-    set_last_error("unexpected internal error");
-    return FFX_EDEVICE;
-  }
-}
 
 static std::string device_name() {
   int dev = 0;
@@ -359,7 +342,7 @@ extern "C" {
 
 ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t* s, const ffx_batch_params* params,
                             void* stream, ffx_batch* out) {
-  return bguard([&] {
+  return guard([&] {
     if (!out) fail(FFX_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || !mats || !s) fail(FFX_EINVAL, "empty batch");
@@ -414,21 +397,21 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
 
 ffx_status ffx_batch_spmm(ffx_batch B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
                           ffx_dtype dtype, void* stream) {
-  return bguard([&] {
+  return guard([&] {
     if (!B) fail(FFX_EINVAL, "batch is NULL");
     batch_run(B, X, ldx, Y, ldy, dtype, (hipStream_t)stream);
   });
 }
 
 ffx_status ffx_batch_get_params(ffx_batch B, ffx_batch_params* p) {
-  return bguard([&] {
+  return guard([&] {
     if (!B || !p) fail(FFX_EINVAL, "NULL argument");
     *p = B->params;
   });
 }
 
 ffx_status ffx_batch_set_params(ffx_batch B, const ffx_batch_params* p) {
-  return bguard([&] {
+  return guard([&] {
     if (!B || !p) fail(FFX_EINVAL, "NULL argument");
     check_params(*p);
     bool relist = p->order != B->params.order || p->max_chunk != B->params.max_chunk;
@@ -440,7 +423,7 @@ ffx_status ffx_batch_set_params(ffx_batch B, const ffx_batch_params* p) {
 
 ffx_status ffx_batch_tune(ffx_batch B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
                           ffx_dtype dtype, int32_t reps, const char* cache_path, void* stream, ffx_batch_params* best) {
-  return bguard([&] {
+  return guard([&] {
     if (!B) fail(FFX_EINVAL, "batch is NULL");
     hipStream_t st = (hipStream_t)stream;
     const std::string key = device_name() + "|" + B->signature;
@@ -496,7 +479,7 @@ ffx_status ffx_batch_tune(ffx_batch B, const void* const* X, const int64_t* ldx,
 }
 
 ffx_status ffx_batch_destroy(ffx_batch B) {
-  return bguard([&] {
+  return guard([&] {
     if (!B) return;
     B->drop_graph();
     if (B->d_mats) (void)hipFree(B->d_mats);

@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <new>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,26 @@ struct Error {
 };
 [[noreturn]] void fail(ffx_status st, const char* fmt, ...);
 void set_last_error(const std::string& s);
+// Runs the body of a C entry point: a thrown Error becomes its status and the
+// calling thread's last error; anything else thrown becomes FFX_ENOMEM (a host
+// allocation) or FFX_EDEVICE.
+template <class F>
+ffx_status guard(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return FFX_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return FFX_ENOMEM;
+  } catch (...) {
+    set_last_error("unexpected internal error");
+    return FFX_EDEVICE;
+  }
+}
 #define FFX_HIP(call)                                                                         \
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \

@@ -1,5 +1,5 @@
 // Symmetric reordering of a square matrix before it is encoded (the
-// reordering of A that Section 5 expects to improve the products): reverse
+// reordering of A that Section 4 (the conclusion) expects to improve the products): reverse
 // Cuthill-McKee (Cuthill and McKee 1969, with the reversal of George 1971) on
 // the pattern of A + A^T, started from a pseudo-peripheral node (George and
 // Liu 1979). Rows that are coupled end up close together, so the x entries a

@@ -27,24 +27,6 @@ namespace ffx {
 
 namespace {
 
-template <class F>
-ffx_status sguard(F&& f) {
-  try {
-    f();
-    set_last_error("");
-    return FFX_OK;
-  } catch (const Error& e) {
-    set_last_error(e.msg);
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return FFX_ENOMEM;
-  } catch (...) {
-    set_last_error("unexpected internal error");
-    return FFX_EDEVICE;
-  }
-}
-
 uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
@@ -140,7 +122,7 @@ using namespace ffx;
 extern "C" {
 
 ffx_status ffx_selector_create(uint64_t seed, ffx_selector* out) {
-  return sguard([&] {
+  return guard([&] {
     if (!out) fail(FFX_EINVAL, "out is NULL");
     *out = nullptr;
     ffx_selector_s* S = new_selector();
@@ -166,7 +148,7 @@ ffx_status ffx_selector_create(uint64_t seed, ffx_selector* out) {
 }
 
 ffx_status ffx_selector_set_params(ffx_selector S, const float* theta, const float* mean, const float* scale) {
-  return sguard([&] {
+  return guard([&] {
     if (!S) fail(FFX_EINVAL, "selector is NULL");
     if (theta) FFX_HIP(hipMemcpy(S->theta(), theta, MLP_NPARAM * 4, hipMemcpyHostToDevice));
     if (mean) FFX_HIP(hipMemcpy(S->mean(), mean, MLP_NIN * 4, hipMemcpyHostToDevice));
@@ -175,7 +157,7 @@ ffx_status ffx_selector_set_params(ffx_selector S, const float* theta, const flo
 }
 
 ffx_status ffx_selector_get_params(ffx_selector S, float* theta, float* mean, float* scale) {
-  return sguard([&] {
+  return guard([&] {
     if (!S) fail(FFX_EINVAL, "selector is NULL");
     if (theta) FFX_HIP(hipMemcpy(theta, S->theta(), MLP_NPARAM * 4, hipMemcpyDeviceToHost));
     if (mean) FFX_HIP(hipMemcpy(mean, S->mean(), MLP_NIN * 4, hipMemcpyDeviceToHost));
@@ -184,7 +166,7 @@ ffx_status ffx_selector_get_params(ffx_selector S, float* theta, float* mean, fl
 }
 
 ffx_status ffx_selector_predict(ffx_selector S, const float* X, int64_t n, float* out, void* stream) {
-  return sguard([&] {
+  return guard([&] {
     if (!S || (n > 0 && (!X || !out)) || n < 0) fail(FFX_EINVAL, "bad argument");
     FFX_HIP(mlp_predict(S->theta(), S->mean(), S->scale(), X, n, out, (hipStream_t)stream));
   });
@@ -212,12 +194,12 @@ static void gradient(ffx_selector S, const float* X, const float* T, const float
 
 ffx_status ffx_selector_gradient(ffx_selector S, const float* X, const float* T, const float* M, int64_t n,
                                  float* grad, double* loss, void* stream) {
-  return sguard([&] { gradient(S, X, T, M, n, grad, loss, (hipStream_t)stream); });
+  return guard([&] { gradient(S, X, T, M, n, grad, loss, (hipStream_t)stream); });
 }
 
 ffx_status ffx_selector_train_step(ffx_selector S, const float* X, const float* T, const float* M, int64_t n, float lr,
                                    double* loss, void* stream) {
-  return sguard([&] {
+  return guard([&] {
     hipStream_t st = (hipStream_t)stream;
     gradient(S, X, T, M, n, S ? S->grad() : nullptr, loss, st);
     S->t += 1;
@@ -226,7 +208,7 @@ ffx_status ffx_selector_train_step(ffx_selector S, const float* X, const float* 
 }
 
 ffx_status ffx_selector_save(ffx_selector S, const char* path) {
-  return sguard([&] {
+  return guard([&] {
     if (!S || !path) fail(FFX_EINVAL, "bad argument");
     std::vector<float> host(MLP_NPARAM + 2 * MLP_NIN);
     FFX_HIP(hipMemcpy(host.data(), S->mean(), MLP_NIN * 4, hipMemcpyDeviceToHost));
@@ -243,7 +225,7 @@ ffx_status ffx_selector_save(ffx_selector S, const char* path) {
 }
 
 ffx_status ffx_selector_load(const char* path, ffx_selector* out) {
-  return sguard([&] {
+  return guard([&] {
     if (!path || !out) fail(FFX_EINVAL, "bad argument");
     *out = nullptr;
     std::vector<float> host;
@@ -261,7 +243,7 @@ ffx_status ffx_selector_load(const char* path, ffx_selector* out) {
 }
 
 ffx_status ffx_selector_destroy(ffx_selector S) {
-  return sguard([&] {
+  return guard([&] {
     if (!S) return;
     (void)hipFree(S->d);
     delete S;

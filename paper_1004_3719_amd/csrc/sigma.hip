@@ -523,6 +523,7 @@ static bool is_prime(uint32_t p) {
 
 void sigma_basis(uint32_t p, int m, int n, int64_t sigma, const uint32_t* G, int64_t ldg, const int32_t* shift,
                  uint32_t* M, int64_t ldm, int32_t* d_out, hipStream_t st) {
+  if (p > 2147483647u) fail(FFX_EINVAL, "the order basis needs a prime p < 2^31 (p = %u)", p);
   if (!is_prime(p)) fail(FFX_EINVAL, "the order basis needs a prime modulus (%u is not prime)", p);
   if (m < 1 || m > SB_MAXM || n < 1 || n > SB_MAXN || n > m)
     fail(FFX_EINVAL, "m = %d, n = %d: need 1 <= n <= m <= %d and n <= %d", m, n, SB_MAXM, SB_MAXN);
@@ -615,6 +616,7 @@ void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, in
   if (s < 1 || s > SB_MAXN) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, SB_MAXN);
   if (L < 1) fail(FFX_EINVAL, "L = %lld < 1", (long long)L);
   if (!S) fail(FFX_EINVAL, "S is NULL");
+  if (p > 2147483647u) fail(FFX_EINVAL, "the rank needs a prime p < 2^31 (p = %u)", p);
   if (!is_prime(p)) fail(FFX_EINVAL, "the rank needs a prime modulus (%u is not prime)", p);
   const int m = 2 * s;
   uint32_t *G = nullptr, *M = nullptr;
@@ -668,14 +670,17 @@ void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, in
     if (det_valuation(A0, s, 1, p) != 0)
       fail(FFX_EUNSUPPORTED, "the generator is not row reduced (sequence too short or degenerate projections)");
   }
-  // codeg det F: F row i = lambda^deg_i Frev_i(1/lambda), so [lambda^k] F_i = [x^(deg_i - k)] Frev_i
+  // codeg det F: F row i = lambda^deg_i Frev_i(1/lambda), so [lambda^k] F_i = [x^(deg_i - k)] Frev_i.
+  // F is row reduced, so det F has degree D exactly and its valuation is at most D: a truncation
+  // order K > D always finds it.
   int64_t e = -1;
-  for (int64_t K = 16; e < 0 && K <= (int64_t)4 * (D + 1); K *= 2) {
+  for (int64_t K = 16;; K *= 2) {
     std::vector<uint64_t> A((size_t)s * s * K, 0);
     for (int r = 0; r < s; ++r)
       for (int c = 0; c < s; ++c)
         for (int64_t k = 0; k < K && k <= deg_out[r]; ++k) A[((size_t)r * s + c) * K + k] = coef(r, c, deg_out[r] - k);
     e = det_valuation(A, s, K, p);
+    if (e >= 0 || K > D) break;
   }
   if (e < 0) fail(FFX_EUNSUPPORTED, "det F vanishes: no rank from this sequence");
   *deg_det = D;

@@ -496,6 +496,9 @@ def sigma_basis(G, p, shift, stream=None):
     p) to order sigma with the given shifted degrees (ffx_sigma_basis): (M, d) with M a device int32
     tensor m x m x (sigma + 1) and d the final shifted degrees."""
     import torch
+    if G.dtype != torch.int32 or G.dim() != 3:
+        raise TypeError("sigma_basis takes an m x n x sigma int32 tensor of residues (got %s, %d dims)"
+                        % (G.dtype, G.dim()))
     m, n, sigma = (int(v) for v in G.shape)
     G = G.contiguous()
     M = torch.empty((m, m, sigma + 1), dtype=torch.int32, device=G.device)

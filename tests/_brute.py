@@ -140,3 +140,53 @@ def random_csr(rng, nrows, ncols, density, raw="mixed", dup=True, empty_rows=Tru
     else:
         val = rng.integers(raw[0], raw[1] + 1, size=nnz, dtype=np.int64)
     return synth.Csr(nrows, ncols, rp, col, val)
+
+
+def rank_mod_p(D, p):
+    """Rank of a matrix of Python ints over the prime field F_p, by Gauss-Jordan elimination."""
+    A = [[int(v) % p for v in row] for row in D]
+    rows, cols = len(A), len(A[0]) if A else 0
+    r = 0
+    for c in range(cols):
+        piv = next((i for i in range(r, rows) if A[i][c]), None)
+        if piv is None:
+            continue
+        A[r], A[piv] = A[piv], A[r]
+        inv = pow(A[r][c], p - 2, p)
+        A[r] = [v * inv % p for v in A[r]]
+        for i in range(rows):
+            if i != r and A[i][c]:
+                f = A[i][c]
+                A[i] = [(a - f * b) % p for a, b in zip(A[i], A[r])]
+        r += 1
+    return r
+
+
+def shifted_leading_matrix(M, d, shift):
+    """Leading coefficient matrix of a polynomial matrix M (rows x cols x coefficients) with respect
+    to the shifted row degrees d: entry (i, j) is the coefficient of x^(d_i - shift_j) in M[i][j]
+    (0 when that exponent is negative or beyond the stored coefficients). M is reduced with respect
+    to the shift, with shifted row degrees d, exactly when every row stays within d and this matrix
+    is nonsingular."""
+    rows, cols, ln = M.shape
+    out = [[0] * cols for _ in range(rows)]
+    for i in range(rows):
+        for j in range(cols):
+            e = int(d[i]) - int(shift[j])
+            if 0 <= e < ln:
+                out[i][j] = int(M[i, j, e])
+    return out
+
+
+def within_shifted_degrees(M, d, shift):
+    """Every entry M[i][j] has degree at most d_i - shift_j (the zero polynomial counts)."""
+    rows, cols, ln = M.shape
+    for i in range(rows):
+        for j in range(cols):
+            top = int(d[i]) - int(shift[j])
+            if top < 0:
+                if M[i, j].any():
+                    return False
+            elif top + 1 < ln and M[i, j, top + 1:].any():
+                return False
+    return True

@@ -223,6 +223,8 @@ def test_sigma_and_rank_argument_errors():
     M = ctypes.c_void_p(32)
     cases = [
         (65520, 4, 2, 8, 8, 9),   # modulus not prime
+        (4294967291, 4, 2, 8, 8, 9),  # prime above 2^31 - 1: the leaf's 32-bit sums would wrap
+        (2147483659, 4, 2, 8, 8, 9),  # the smallest prime above 2^31
         (65521, 17, 8, 8, 8, 9),  # too many rows
         (65521, 4, 9, 8, 8, 9),   # too many columns
         (65521, 2, 3, 8, 8, 9),   # n > m
@@ -236,7 +238,8 @@ def test_sigma_and_rank_argument_errors():
     r, D, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     deg = (ctypes.c_int32 * 16)()
     S = ctypes.c_void_p(16)
-    for p, s, Ln, dt in [(65521, 9, 10, 0), (65521, 0, 10, 0), (65521, 2, 0, 0), (65520, 2, 10, 0), (65521, 2, 10, 7)]:
+    for p, s, Ln, dt in [(65521, 9, 10, 0), (65521, 0, 10, 0), (65521, 2, 0, 0), (65520, 2, 10, 0), (65521, 2, 10, 7),
+                         (4294967291, 2, 10, 0), (2147483659, 2, 10, 0)]:
         st = L.ffx_sequence_rank(p, s, Ln, S, dt, deg, ctypes.byref(r), ctypes.byref(D), ctypes.byref(e), None)
         assert st == ffx.FFX_EINVAL, (p, s, Ln, dt)
     st = L.ffx_sequence_rank(65521, 2, 10, S, 0, None, ctypes.byref(r), ctypes.byref(D), ctypes.byref(e), None)

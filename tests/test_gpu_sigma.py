@@ -4,6 +4,7 @@ oracle's and the planted rank."""
 import numpy as np
 import pytest
 
+import _brute as bf
 import oracle
 import synth
 from oracle import sigma as osig
@@ -71,6 +72,39 @@ def test_sequence_rank_small(dev, n, s, ndead, seed, p):
     assert sequence_rank(Sg, p)[:3] == want
 
 
+@pytest.mark.parametrize("kind", ["zero", "rank1", "zero_s2"])
+def test_sequence_rank_tiny(dev, kind):
+    """Degenerate operands whose generator has degree at most 2 (the co-degree search must still
+    run): the zero matrix (F = lambda for s = 1, rank 0) and a dense rank-1 matrix, against the
+    oracle's rank and Gaussian elimination."""
+    from paper_1004_3719_amd import Matrix, sequence_rank
+    p = 65521
+    n, s = (6, 2) if kind == "zero_s2" else (6, 1)
+    if kind == "rank1":
+        u = synth.vector(31, 1, n, 1, p - 1)
+        v = synth.vector(31, 2, n, 1, p - 1)
+        rp = np.arange(0, n * n + 1, n, dtype=np.int64)
+        col = np.tile(np.arange(n, dtype=np.int32), n)
+        val = (u[:, None] * v[None, :] % p).reshape(-1).astype(np.int64)
+    else:
+        rp = np.zeros(n + 1, np.int64)
+        col = np.zeros(0, np.int32)
+        val = np.zeros(0, np.int64)
+    A = synth.Csr(n, n, rp, col, val, m=p, name=kind)
+    want_rank = 1 if kind == "rank1" else 0
+    U = synth.vector(32, 1, n * s, 0, p - 1).reshape(n, s)
+    V = synth.vector(32, 2, n * s, 0, p - 1).reshape(n, s)
+    L = 2 * n // s + 3
+    print("[case] rank tiny", kind, flush=True)
+    So = oracle.get().sequence(A, U, V, L)
+    want = osig.rank(So, p)
+    assert want[0] == want_rank
+    assert sequence_rank(torch.from_numpy(So).to(dev), p)[:3] == want
+    M = Matrix.from_synth(A)
+    Sg = M.sequence(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), L)
+    assert sequence_rank(Sg, p)[:3] == want
+
+
 def test_c3_rank_full_size(dev):
     """The block-Wiedemann operand at full size (n = 200,000, 15 entries per row drawn from
     n - 1,000 live columns, m = 2^31 - 1, s = 8, L = 50,003): the GPU sequence and steps 2-3 give
@@ -103,6 +137,10 @@ def test_sigma_basis_large_order(dev, p):
     assert sum(d) - sum(shift) == n * sig
     for i in range(m):
         assert not M[i, :, d[i] + 1:].any()
+    # reduced: within the shifted degrees, with a nonsingular shifted leading coefficient matrix
+    # (with the order condition and the degree sum, this makes M an order basis)
+    assert bf.within_shifted_degrees(M, d, shift)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(M, d, shift), p) == m
     for k in [0, 1, 31, 32, 33, 1023, 1024, 1500, 2047, 2048, 2999]:
         Grev = G[:, :, k::-1]  # G[.., k - j] for j = 0..k
         prod = (M[:, :, None, :k + 1] * Grev[None, :, :, :]) % p
@@ -137,6 +175,8 @@ def test_sigma_basis_order_40k(dev, p):
     assert sum(d) - sum(shift) == n * sig
     top = max(d) + 1
     assert not M[:, :, top:].any()
+    assert bf.within_shifted_degrees(M, d, shift)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(M, d, shift), p) == m
     M = M[:, :, :top]
     for k in [0, 20_000, 20_001, 31_999, 39_999]:
         assert not _coeff_mod(M, G, k, p).any(), k

@@ -7,6 +7,7 @@ import itertools
 import numpy as np
 import pytest
 
+import _brute as bf
 import oracle
 import synth
 from oracle import sigma
@@ -95,6 +96,10 @@ def test_order_condition(m, n, sigma_, shift):
     for i in range(m):
         nz = np.nonzero(M[i].any(axis=0))[0]
         assert nz.max() <= d[i] - min(shift)
+    # reduced with respect to the shift: entries within the shifted degrees and a nonsingular
+    # shifted leading coefficient matrix
+    assert bf.within_shifted_degrees(M, d, shift)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(M, d, shift), P) == m
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -177,5 +182,22 @@ def test_det_valuation_brute(seed):
     det = _poly_det(F, P)
     nz = [k for k, v in enumerate(det) if v]
     want = nz[0] if nz else None
-    got = sigma.det_valuation(F, P, K=4) if want is not None else None
-    assert got == want
+    assert (want is None) == bool(seed % 2)
+    assert sigma.det_valuation(F, P, K=4) == want
+
+
+def test_reducedness_check_rejects_degenerate():
+    """The reducedness check that the order-basis tests apply fails a degenerate basis with the
+    right degrees (all zero, or one row a multiple of another) and passes the oracle's."""
+    m, n, sig, shift = 4, 2, 9, [0, 0, 1, 1]
+    G = synth.vector(77, 3, m * n * sig, 0, P - 1).reshape(m, n, sig)
+    M, d = sigma.mbasis(G, sig, shift, P)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(M, d, shift), P) == m
+    Z = np.zeros_like(M)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(Z, d, shift), P) < m
+    D = M.copy()
+    i, j = sorted(range(m), key=lambda r: d[r])[:2]
+    D[j] = 0
+    D[j, :, d[j] - d[i]:] = M[i, :, :M.shape[2] - (d[j] - d[i])]  # row j = x^(d_j - d_i) row i
+    assert bf.within_shifted_degrees(D, d, shift)
+    assert bf.rank_mod_p(bf.shifted_leading_matrix(D, d, shift), P) < m
