@@ -210,6 +210,23 @@ ffx_status ffx_spmv(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, 
 ffx_status ffx_spmv_t(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
                       void* stream);
 
+/* y <- alpha*A*x + beta*y (mod m), as ffx_spmv, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): this call allocates nothing. The
+ * temporary that ffx_spmv allocates per call (the 16-bit copy of x when
+ * m <= 65536, or x gathered into the stored order of a reordered handle)
+ * lives instead in a static device array of FFX_NOALLOC_SCRATCH_BYTES bytes,
+ * one per GPU, held from the first call on that GPU until the process ends.
+ * FFX_EINVAL when the product needs more than that (2 bytes per column of A
+ * for the 16-bit copy; 4 or 8 bytes per column for a reordered handle whose
+ * x is not copied to 16 bits), checked before anything is enqueued. Every
+ * call on one GPU shares that GPU's array: calls on one stream are ordered,
+ * but calls that overlap on different streams of the same GPU race. The
+ * result is identical to ffx_spmv's. */
+#define FFX_NOALLOC_SCRATCH_BYTES (32u << 20)
+ffx_status ffx_spmv_noalloc(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                            void* stream);
+
 /* Y <- alpha*A*X + beta*Y (mod m) for s in [1, 16] vectors. X: ncols x s
  * (ldx), Y: nrows x s (ldy). */
 ffx_status ffx_spmm(ffx_matrix A, int32_t s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta, void* Y,

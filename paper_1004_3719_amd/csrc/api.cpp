@@ -324,6 +324,30 @@ static hipError_t row_product_in(const ffx_matrix_s& M, bool trans, int s, uint3
   return launch_tiles(ak, dm, E.max_tile_entries, dt, X, ldx, Y, ldy, s, alpha, beta, st);
 }
 
+// The temporary of ffx_spmv_noalloc: a static device array, one copy per GPU.
+// Host code never passes its name to a kernel (that is a host-side stand-in);
+// it takes the device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char noalloc_scratch[FFX_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's copy of noalloc_scratch.
+static void* noalloc_scratch_ptr() {
+  int dev = 0;
+  FFX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(FFX_EUNSUPPORTED, "device ordinal %d", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p)
+      fail(FFX_EDEVICE, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  return g_noalloc_ptr[dev];
+}
+
 static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void* X, int64_t ldx, uint32_t beta,
                     void* Y, int64_t ldy, ffx_dtype dt, hipStream_t st) {
   if (!check_product(M, trans, s, alpha, X, ldx, beta, Y, ldy, dt)) return;
@@ -474,6 +498,19 @@ ffx_status ffx_matrix_destroy(ffx_matrix A) {
 ffx_status ffx_spmv(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
                     void* stream) {
   return guard([&] { product(A, false, 1, alpha, x, 1, beta, y, 1, dtype, (hipStream_t)stream); });
+}
+
+ffx_status ffx_spmv_noalloc(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,
+                            void* stream) {
+  return guard([&] {
+    if (!check_product(A, false, 1, alpha, x, 1, beta, y, 1, dtype)) return;
+    const size_t bytes = row_scratch_bytes(*A, false, 1, dtype);
+    if (bytes > (size_t)FFX_NOALLOC_SCRATCH_BYTES)
+      fail(FFX_EINVAL, "this product needs %zu bytes of temporary; the static scratch holds %zu", bytes,
+           (size_t)FFX_NOALLOC_SCRATCH_BYTES);
+    void* tmp = bytes ? noalloc_scratch_ptr() : nullptr;
+    FFX_HIP(row_product_in(*A, false, 1, alpha, x, 1, beta, y, 1, dtype, (hipStream_t)stream, tmp));
+  });
 }
 
 ffx_status ffx_spmv_t(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta, void* y, ffx_dtype dtype,

@@ -68,6 +68,8 @@ _SIGS = {
     "ffx_matrix_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ffx_spmv": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                 ctypes.c_int, ctypes.c_void_p]),
+    "ffx_spmv_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "ffx_spmv_t": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                                   ctypes.c_int, ctypes.c_void_p]),
     "ffx_spmm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int64,
@@ -303,7 +305,7 @@ class Matrix:
         py, sy, ldy = _block(Y, nout, "y")
         if sy != s:
             raise ValueError("x has %d columns, y has %d" % (s, sy))
-        if X.dim() == 1 and fn in ("ffx_spmv", "ffx_spmv_t"):
+        if X.dim() == 1 and fn in ("ffx_spmv", "ffx_spmv_t", "ffx_spmv_noalloc"):
             _check(getattr(lib(), fn)(self._h, int(alpha), ctypes.c_void_p(px), int(beta), ctypes.c_void_p(py),
                                       _dt(X), _stream(stream)))
         else:
@@ -314,6 +316,12 @@ class Matrix:
 
     def spmv(self, x, alpha=1, beta=0, y=None, stream=None):
         return self._prod("ffx_spmv", False, x, alpha, beta, y, stream)
+
+    def spmv_noalloc(self, x, alpha=1, beta=0, y=None, stream=None):
+        """As spmv, through ffx_spmv_noalloc (the library allocates nothing; y must be given for that)."""
+        if x.dim() != 1:
+            raise ValueError("spmv_noalloc takes one vector")
+        return self._prod("ffx_spmv_noalloc", False, x, alpha, beta, y, stream)
 
     def spmv_t(self, x, alpha=1, beta=0, y=None, stream=None):
         return self._prod("ffx_spmv_t", True, x, alpha, beta, y, stream)
