@@ -15,10 +15,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+OMP_PATH = os.path.join(HERE, "liboracle_omp.so")  # the same source, rows of a product over all cores
 
 
 def build(force=False, src=SRC, out=LIB_PATH, extra=()):
-    """Compile oracle.c (single-threaded, -O2) into a shared library."""
+    """Compile oracle.c (single-threaded, -O2) into a shared library; with force, also the OpenMP build."""
+    if force and out == LIB_PATH and src == SRC and not extra:
+        build(True, src, OMP_PATH, ("-fopenmp",))
     if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
         return out
     tmp = out + ".tmp%d" % os.getpid()
@@ -135,6 +138,7 @@ class Oracle:
 
 
 _default = None
+_omp = None
 
 
 def get():
@@ -142,3 +146,13 @@ def get():
     if _default is None:
         _default = Oracle()
     return _default
+
+
+def get_all_cores():
+    """The oracle built with OpenMP: product rows split over every core (OMP_NUM_THREADS)."""
+    global _omp
+    if _omp is None:
+        path = OMP_PATH if os.path.exists(OMP_PATH) and os.path.getmtime(OMP_PATH) >= os.path.getmtime(SRC) \
+            else build(True, SRC, OMP_PATH, ("-fopenmp",))
+        _omp = Oracle(path)
+    return _omp

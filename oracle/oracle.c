@@ -29,6 +29,9 @@
  * leading dimension ld >= s (the layout Section 2.5 describes as traversing
  * A once with x and y read and written contiguously).
  *
+ * Threads: built plainly it runs on one thread; built with -fopenmp (liboracle_omp.so) the
+ * rows of a product run on all cores, with identical results.
+ *
  * Return value of each entry point: 0 on success, -1 on invalid arguments
  * (modulus out of range, a vector entry not canonical, a column index out
  * of range, a null pointer).
@@ -72,6 +75,9 @@ int oracle_spmm(i64 nrows, i64 ncols, const i64* rowptr, const int32_t* col, con
   if (bad_modulus(m) || alpha >= m || beta >= m || s < 1 || ldx < s || ldy < s) return -1;
   if (check_csr(nrows, ncols, rowptr, col)) return -1;
   if (check_vec(X, ncols, s, ldx, m) || check_vec(Y, nrows, s, ldy, m)) return -1;
+  /* rows are independent: the all-cores build (-fopenmp) splits them over threads; the result is the
+     same, and the single-thread build ignores the pragma */
+#pragma omp parallel for schedule(dynamic, 1024)
   for (i64 i = 0; i < nrows; ++i) {
     for (i64 b = 0; b < s; ++b) {
       u64 acc = 0;
