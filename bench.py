@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 METRIC = "exact nnz·vec/s (bit-exact) + HBM GB/s % peak; learned/batched vs plain"
 UNIT = "nnz·vec/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "launch.h"]  # the one-vector product kernels
+KERNEL_SOURCES = ["tiles.h", "ffx_impl.h", "k_small.hip", "launch.h", "sg.h", "sg.hip"]  # the one-vector product kernels
 
 
 def log(*a):
@@ -77,8 +77,8 @@ def algorithmic_bytes(A, m, vec_bytes=4, s=1):
     return 4 * A.nnz + vb * n_gen + 4 * (A.nrows + 1) + vec_bytes * s * (A.ncols + A.nrows)
 
 
-def line(value, ms, args, dtype, config, roofline, cpu, extra=None):
-    out = {"metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+def line(value, ms, args, dtype, config, roofline, cpu, extra=None, metric=None, unit=None):
+    out = {"metric": metric or METRIC, "value": round(value, 1), "unit": unit or UNIT, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline,
            "cpu_baseline": cpu}
@@ -149,6 +149,37 @@ def pmc_summary(fetch_csv, write_csv, mib, out_path, command):
     print(json.dumps(out))
 
 
+def time_oracle(call, seconds, check=None):
+    """Repeats an oracle call for at least `seconds`: (calls, seconds, every result passed check)."""
+    reps, t, ok = 0, 0.0, True
+    while t < seconds or reps < 1:
+        t1 = time.perf_counter()
+        r = call()
+        t += time.perf_counter() - t1
+        reps += 1
+        if check is not None:
+            ok = ok and check(r)
+    return reps, t, ok
+
+
+def omp_threads():
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
 # --------------------------------------------------------------------- c2 / c1
 def bench_spmv(args, big=True):
     import torch
@@ -164,7 +195,7 @@ def bench_spmv(args, big=True):
     log("generated n=%d nnz=%d in %.1fs" % (A.nrows, A.nnz, time.time() - t0))
     t0 = time.time()
     opts = dict(acc=args.acc, selector=args.selector, tile_entries=args.tile_entries, fixed_format=args.fixed_format,
-                build_transpose=not big, compact_x=args.compact_x)
+                build_transpose=not big, compact_x=args.compact_x, col_sorted=args.col_sorted)
     if args.selector == "learned":
         opts["model_path"] = args.model
     M = Matrix.from_synth(A, **opts)
@@ -202,39 +233,82 @@ def bench_spmv(args, big=True):
         extra["transpose_ms_per_step"] = round((time.perf_counter() - t1) * 1e3 / args.steps, 5)
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    main_kernel = "k_sg (column-sorted groups)" if info["sg_groups"] else "k_tiles"
     khash = kernel_hash()
     copy_gbs = copy_bandwidth() if big else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counters_traffic("spmv_powerlaw_2M_counters.json" if big else "none", khash),
-                "kernel": ("k_to_u16 + k_tiles (the product's launches)"
+                "kernel": ("k_to_u16 + %s (the product's launches)" % main_kernel
                            if m <= 65536 and (args.compact_x == 1 or (args.compact_x == -1 and A.ncols * 4 > 2**20))
-                           else "k_tiles"),
+                           else main_kernel),
                 "kernel_ms": round(kernel_ms, 5),
-                "algorithmic_bytes": int(b_alg), "format_bytes": int(info["stream_bytes"] + 4 * A.ncols + 4 * A.nrows),
+                "algorithmic_bytes": int(b_alg),
+                "format_bytes": int((info["sg_stream_bytes"] if info["sg_groups"] else info["stream_bytes"])
+                                    + 4 * A.ncols + 4 * A.nrows),
                 "achievable_copy_GBps": copy_gbs}
+    if big:
+        # one gather of x per entry: the product's gather rate against the GPU's random-gather rate
+        # from a table the size of the gathered x (the 16-bit copy when the product takes one)
+        x16 = m <= 65536 and (args.compact_x == 1 or (args.compact_x == -1 and A.ncols * 4 > 2**20))
+        row_b = 2 if x16 else 4
+        ceil = gather_ceiling(A.ncols * row_b, row_b, A.nnz)
+        got = A.nnz / (kernel_ms * 1e-3)
+        roofline["gather"] = {"achieved": round(got, 1), "ceiling": round(ceil, 1), "unit": "gathers/s",
+                              "frac": round(got / ceil, 4),
+                              "ceiling_kernel": "ffx_gather_rate: %d random %d-byte gathers from a %d-byte table"
+                                                % (A.nnz, row_b, A.ncols * row_b)}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        orc = oracle.get()
         got = y.cpu().numpy()
-        reps, t_cpu, exact = 0, 0.0, True
-        while t_cpu < args.cpu_seconds or reps < 1:
-            t1 = time.perf_counter()
-            want = orc.spmv(A, x_np)
-            t_cpu += time.perf_counter() - t1
-            reps += 1
-            exact = exact and bool(np.array_equal(got, want))
+        check = lambda want: bool(np.array_equal(got, want))  # noqa: E731
+        reps, t_cpu, exact = time_oracle(lambda: oracle.get().spmv(A, x_np), args.cpu_seconds, check)
+        reps_a, t_a, exact_a = time_oracle(lambda: oracle.get_all_cores().spmv(A, x_np), args.cpu_seconds / 2, check)
         cpu = {"value": round(A.nnz * reps / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
                "sample": "%d full products y = A x over the same matrix (single thread)" % reps,
-               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
-        if not exact:
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact and exact_a,
+               "all_cores": {"value": round(A.nnz * reps_a / t_a, 1), "cores": omp_threads(),
+                             "sample": "%d full products, rows over all cores (OpenMP build)" % reps_a,
+                             "seconds": round(t_a, 2)},
+               "host": host_info()}
+        if not (exact and exact_a):
             log("GPU result differs from the oracle")
     workload = ("power-law hybrid SpMV mod 32749: n=2,000,000, truncated Zipf(1.8) rows on [1,5000] + diagonals "
                 "-2..2, 60% +-1, x int32") if big else "plain SpMV mod 65521: n=10,000, 10 nnz/row, x int32"
     config = {"workload": workload, "n": A.nrows, "nnz": A.nnz, "m": m, "acc": args.acc, "selector": args.selector,
-              "formats": info["format_blocks"], "kernel_hash": khash}
+              "formats": info["format_blocks"], "col_sorted_groups": info["sg_groups"], "kernel_hash": khash}
     line(A.nnz / (ms * 1e-3), ms, args, args.acc, config, roofline, cpu, extra)
+
+
+# ------------------------------------------------------------------ gather
+def gather_ceiling(table_bytes, row_bytes, count, window=0):
+    """Random gathers per second of the library's calibration kernel (ffx_gather_rate)."""
+    from paper_1004_3719_amd.ffx import gather_rate
+    return gather_rate(int(table_bytes), int(row_bytes), int(min(count, 2**31 - 1)), int(window), reps=5)
+
+
+def bench_gather(args):
+    """The gather-rate table behind the rooflines: random gathers of 2- to 64-byte rows from tables of
+    40 KB to 64 MB, indices streamed coalesced as the products stream their column words, and the same
+    gathers kept inside windows of 4,096 rows."""
+    import torch
+    torch.cuda.init()  # the library's calls run on the device torch initialised
+    rows = []
+    count = 32 * 2**20
+    for row_bytes in (2, 4, 32, 64):
+        for table in (40 * 2**10, 2**20, 4 * 2**20, 6553600, 8 * 2**20, 32 * 2**20, 64 * 2**20):
+            r = gather_ceiling(table, row_bytes, count)
+            rw = gather_ceiling(table, row_bytes, count, window=min(4096, table // row_bytes))
+            rows.append({"row_bytes": row_bytes, "table_bytes": table, "gathers_per_s": round(r, 1),
+                         "gathers_per_s_window4096": round(rw, 1), "row_GBps": round(r * row_bytes / 1e9, 1)})
+            log("rows of %2d B from %9d B: %.1f G/s random, %.1f G/s within 4096-row windows"
+                % (row_bytes, table, r / 1e9, rw / 1e9))
+    best = max(rows, key=lambda q: q["gathers_per_s"])
+    config = {"workload": "random gathers: %d per launch, rows of 2-64 bytes, tables of 40 KB to 64 MB" % count}
+    args.steps, args.warmup = len(rows), 0
+    line(best["gathers_per_s"], 0.0, args, "u32", config, None, None, {"table": rows}, metric="gathers/s",
+         unit="gathers/s")
 
 
 # ------------------------------------------------------------ accumulators
@@ -407,6 +481,7 @@ def bench_reorder(args):
         M.close()
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    main_kernel = "k_sg (column-sorted groups)" if info["sg_groups"] else "k_tiles"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_permute_to_u16 (x gathered into the stored order) + k_tiles (y written through the row map)",
@@ -584,13 +659,34 @@ def bench_sequence(args):
         So = orc.sequence(A, U, V, Lc)
         t_cpu = time.perf_counter() - t1
         exact = bool(np.array_equal(S[:Lc].cpu().numpy(), So))
+        t1 = time.perf_counter()
+        So_a = oracle.get_all_cores().sequence(A, U, V, Lc)
+        t_a = time.perf_counter() - t1
+        exact = exact and bool(np.array_equal(So_a, So))
         cpu = {"value": round(A.nnz * 8 * Lc / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
                "sample": "sequence prefix i = 0..%d at full size (single thread)" % (Lc - 1),
-               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact,
+               "all_cores": {"value": round(A.nnz * 8 * Lc / t_a, 1), "cores": omp_threads(), "seconds": round(t_a, 2),
+                             "sample": "the same prefix; the products' rows over all cores (OpenMP build), the "
+                                       "projection on one"},
+               "host": host_info()}
     roofline = {"bound": "hbm", "achieved": round(b_iter / (per_iter_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(b_iter / (per_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "traffic": None, "kernel": "k_seq_step", "kernel_ms": round(per_iter_ms, 5),
                 "algorithmic_bytes": int(b_iter)}
+    # the bound that matters: one 32-byte row of W_i (8 int32 residues) gathered per entry, from a table
+    # of n * 32 bytes, against the GPU's random row-gather rate from a table of that size
+    ceil = gather_ceiling(A.ncols * 32, 32, A.nnz)
+    got = A.nnz / (per_iter_ms * 1e-3)
+    roofline["gather"] = {"achieved": round(got, 1), "ceiling": round(ceil, 1), "unit": "row gathers/s",
+                          "frac": round(got / ceil, 4),
+                          "ceiling_kernel": "ffx_gather_rate: random 32-byte rows from a %d-byte table" % (A.ncols * 32)}
+    # integer multiply-adds per iteration (product 8 per entry, projection 64 per row), each one
+    # v_mad_u64_u32 at a quarter of the 32-bit rate: 256 CUs x 64 lanes x 2.4 GHz / 4
+    macs = A.nnz * 8 + A.nrows * 64
+    alu_peak = 256 * 64 * 2.4e9 / 4
+    roofline["alu"] = {"macs_per_iteration": int(macs), "achieved": round(macs / (per_iter_ms * 1e-3), 1),
+                       "peak": alu_peak, "unit": "MAC/s", "frac": round(macs / (per_iter_ms * 1e-3) / alu_peak, 4)}
     config = {"workload": "block-Wiedemann sequence U^T A^i V mod 2^31-1: n=200,000, 15 nnz/row, s=8 int64, "
                           "L=%d" % L, "n": A.nrows, "nnz": A.nnz, "s": 8, "L": L}
     # the same steps launched one per iteration from the host, against the hipGraph replay
@@ -657,7 +753,7 @@ def bench_batch(args):
         t_per_gpu += ev_time(lambda: M.spmm(X, Y=Y), 3)
     B = Batch(Ms, S)
     t_default = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
-    best = B.tune(Xs, Ys, reps=3)
+    best = B.tune(Xs, Ys, reps=3, cache_path=args.tune_cache or None)
     t_batch = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
     cpu = None
     if not args.no_cpu_baseline:
@@ -672,9 +768,21 @@ def bench_batch(args):
             t_cpu += time.perf_counter() - t1
             w_cpu += A.nnz * A.s
             exact = exact and bool(np.array_equal(Ys[k].cpu().numpy(), want))
+        nk = k + 1
+        # all cores, on the same leading matrices (the batch's other matrices were not kept on the host)
+        orc_a = oracle.get_all_cores()
+        t_a, w_a = 0.0, 0
+        for k, A in enumerate(mats[:nk]):
+            t1 = time.perf_counter()
+            orc_a.spmm(A, synth.c4_rhs(k, A))
+            t_a += time.perf_counter() - t1
+            w_a += A.nnz * A.s
         cpu = {"value": round(w_cpu / t_cpu, 1), "unit": UNIT, "cores": 1, "kind": "oracle",
-               "sample": "the first %d matrices of the batch, all right-hand sides (single thread)" % (k + 1),
-               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
+               "sample": "the first %d matrices of the batch, all right-hand sides (single thread)" % nk,
+               "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact,
+               "all_cores": {"value": round(w_a / t_a, 1), "cores": omp_threads(), "seconds": round(t_a, 2),
+                             "sample": "the same matrices, rows over all cores (OpenMP build)"},
+               "host": host_info()}
     config = {"workload": "256 uneven matrices mod 65521, n log-uniform [2000, 500000], 3..60 nnz/row, "
                           "uniform/banded/block-diagonal, 70% +-1, 1..16 int32 right-hand sides",
               "count": count, "sum_nnz_times_s": work, "tuned": best}
@@ -685,6 +793,14 @@ def bench_batch(args):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch (persistent)",
                 "kernel_ms": round(t_batch, 5), "algorithmic_bytes": int(b_alg)}
+    # one row gather of X per entry and column chunk (at most 8 columns): against the GPU's random
+    # gather rate of 32-byte rows (a chunk of 8 int32 columns) from a 16 MB table (a large X block)
+    nnz_chunks = sum(Ms[k].info()["nnz"] * ((S[k] + 7) // 8) for k in range(count))
+    ceil = gather_ceiling(16 * 2**20, 32, nnz_chunks)
+    got = nnz_chunks / (t_batch * 1e-3)
+    roofline["gather"] = {"achieved": round(got, 1), "ceiling": round(ceil, 1), "unit": "row gathers/s",
+                          "frac": round(got / ceil, 4),
+                          "ceiling_kernel": "ffx_gather_rate: random 32-byte rows from a 16 MiB table"}
     line(work / (t_batch * 1e-3), t_batch, args, "int64", config, roofline, cpu, extra)
 
 
@@ -713,9 +829,7 @@ def bench_selector(args):
             r0, r1 = b0 * BR, min(sp.nrows, (b0 + args.train_blocks) * BR)
             A = ST.shift_columns(synth.rows(sp, r0, r1), r0)
             A.m = synth.M_C5
-            x = torch.from_numpy(synth.vector(k, 7, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
-            y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
-            F, T, H = ST.window_labels(A, x, y)
+            F, T, H = ST.window_labels(A, seed=k)
             Xs.append(F)
             Ts.append(T)
             Hs.append(H)
@@ -728,13 +842,12 @@ def bench_selector(args):
             np.savez(args.labels, X=X, T=T, H=H)
     log("training on %d blocks" % len(X))
     nval = max(1, len(X) // 10)
-    S, hist = ST.fit(X[nval:], T[nval:], epochs=args.epochs, lr=args.lr, seed=args.seed, val=(X[:nval], T[:nval]),
-                     log=lambda r: log(json.dumps(r)))
-    mu, mu_costs = ST.pick_margin(S, X[:nval], T[:nval])
-    log("decision margin %.2f (validation block cost by margin: %s)" % (mu, json.dumps(mu_costs)))
     model = args.model_out
     os.makedirs(os.path.dirname(model), exist_ok=True)
-    S.save(model)
+    S, rep = ST.train(X, T, H, epochs=args.epochs, lr=args.lr, seed=args.seed, n_val=nval, out_model=model)
+    mu = rep["margin"]
+    hist = [{"train_loss": rep["train_loss"], "val_loss": rep["val_loss"], "steps": rep["steps"]}]
+    log("trained in the library: %s" % json.dumps(rep))
     # held-out blocks: summed block time of each choice relative to the best per block
     learned, _ = ST.choose(S, X[:nval])
     block_cost = {"learned": round(ST.choice_cost(T[:nval], learned), 4),
@@ -742,32 +855,47 @@ def bench_selector(args):
     for f, name in enumerate(FORMATS):
         block_cost["all_" + name] = round(ST.choice_cost(T[:nval], np.full(nval, f)), 4)
     log("validation blocks, summed time / best: %s" % json.dumps(block_cost))
-    # held-out matrices: whole-product time, heuristic vs learned
-    tot_h, tot_l, tot_s, tot_b, same, nev = 0.0, 0.0, 0.0, 0.0, True, 0
+    # held-out matrices: whole-product time of the learned formats, the heuristic's and each format forced
+    # on every block (medians of 3 interleaved rounds); every product checked against the oracle
+    import oracle
+    orc = oracle.get()
+    tot = {}
+    same, nev = True, 0
     for k in range(1800, 1800 + args.eval_mats):
         sp, p = synth.c5_spec(k)
         r1 = min(sp.nrows, args.eval_rows) if args.eval_rows else sp.nrows
         A = synth.rows(sp, 0, r1)
         A.m = synth.M_C5
-        x = torch.from_numpy(synth.vector(k, 8, A.ncols, 0, A.m - 1).astype(np.int32)).to(dev)
-        r = ST.evaluate(A, model, x, fixed=("STREAM", "BAND_STREAM"))
-        tot_h += r["heuristic_us"]
-        tot_l += r["learned_us"]
-        tot_s += r["fixed_STREAM_us"]
-        tot_b += r["fixed_BAND_STREAM_us"]
-        same = same and r["same_result"]
+        xh = synth.vector(k, 8, A.ncols, 0, A.m - 1)
+        x = torch.from_numpy(xh.astype(np.int32)).to(dev)
+        r = ST.evaluate(A, model, x, reps=10, fixed=FORMATS, rounds=3)
+        want = orc.spmv(A, xh)
+        for y in r["results"].values():
+            same = same and np.array_equal(y.cpu().numpy(), want)
+        for key, v in r.items():
+            if key.endswith("_us"):
+                tot[key] = tot.get(key, 0.0) + v
         nev += 1
         if nev % 10 == 0:
-            log("held-out %d: heuristic %.1f us, learned %.1f us so far" % (nev, tot_h, tot_l))
-    log("held-out: heuristic %.1f us, learned %.1f us, identical results %s" % (tot_h, tot_l, same))
-    config = {"workload": "learned format selection mod 65521: %d training matrices x %d blocks, %d held-out "
-                          "matrices (first %s rows), 32->64->64->6 FP32" % (args.train_mats, args.train_blocks, nev,
-                                                                           args.eval_rows or "all"),
+            log("held-out %d: heuristic %.1f us, learned %.1f us so far" % (nev, tot["heuristic_us"],
+                                                                              tot["learned_us"]))
+    tot_h, tot_l = tot["heuristic_us"], tot["learned_us"]
+    fixed = {f: tot["fixed_%s_us" % f] for f in FORMATS}
+    best_fixed = min(fixed, key=fixed.get)
+    log("held-out: heuristic %.1f us, learned %.1f us, best fixed %s %.1f us, all equal to the oracle %s"
+        % (tot_h, tot_l, best_fixed, fixed[best_fixed], same))
+    config = {"workload": "learned format selection mod 65521: %d training windows x %d blocks, %d held-out "
+                          "matrices (%s), 32->64->64->6 FP32"
+                          % (args.train_mats, args.train_blocks, nev,
+                             "first %d rows each" % args.eval_rows if args.eval_rows else "whole"),
               "train_blocks": int(len(X)), "history": hist[-1:]}
     extra = {"validation_block_cost_vs_best": block_cost, "decision_margin_log2": mu,
              "heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
-             "all_STREAM_total_us": round(tot_s, 1), "all_BAND_STREAM_total_us": round(tot_b, 1),
-             "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4), "results_identical": same}
+             "fixed_total_us": {f: round(v, 1) for f, v in fixed.items()}, "best_fixed_format": best_fixed,
+             "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4),
+             "learned_speedup_vs_best_fixed": round(fixed[best_fixed] / max(tot_l, 1e-9), 4),
+             "timing": "per matrix: median of 3 interleaved rounds of 10 launches",
+             "results_equal_oracle": same}
     args.steps, args.warmup = nev, 0
     line(0.0, tot_l / 1e3, args, "fp32 network / int64 products", config, None, None, extra)
 
@@ -777,7 +905,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc", "reorder", "rank"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "gf2", "gf2seq", "acc", "reorder", "rank",
+                                                      "gather"])
     ap.add_argument("--gf2-words", type=int, default=8, help="32-bit words per row in the GF(2) product")
     ap.add_argument("--acc", default="int64", choices=ACC_NAMES)
     ap.add_argument("--selector", default="learned", choices=["heuristic", "learned"],
@@ -788,10 +917,13 @@ def main():
     ap.add_argument("--compact-x", type=int, default=-1, choices=[-1, 0, 1],
                     help="16-bit copy of x for m <= 65536: -1 auto (x above 1 MiB), 0 never, 1 always")
     ap.add_argument("--fixed-format", default=None)
+    ap.add_argument("--col-sorted", type=int, default=-1, choices=[-1, 0, 1],
+                    help="column-sorted row groups for the one-vector product: -1 auto, 0 never, 1 always")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seq-length", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--tune-cache", default="", help="JSON cache of the batch tuner (read if it holds this batch)")
     ap.add_argument("--train-mats", type=int, default=600)
     ap.add_argument("--train-blocks", type=int, default=16)
     ap.add_argument("--eval-mats", type=int, default=200)
@@ -831,6 +963,8 @@ def main():
         bench_reorder(args)
     elif args.config == "rank":
         bench_rank(args)
+    elif args.config == "gather":
+        bench_gather(args)
     elif args.config == "c4":
         args.steps = min(args.steps, 10)
         bench_batch(args)

@@ -114,6 +114,12 @@ typedef struct {
                                per call, once per call for ffx_power and ffx_sequence); never changes
                                a result. 0 (default): the caller's order. Batches refuse reordered
                                matrices. */
+  int32_t col_sorted;       /* m <= 65536 with the int64 accumulator: 1 = also store A as column-sorted
+                               row groups (about one per compute unit, entries sorted by column inside
+                               a group) that ffx_spmv and ffx_spmv_noalloc use for y = alpha*A*x +
+                               beta*y: the lanes of one gather then share cache lines of x. Costs a
+                               second copy of A on the device. 0 = never; -1 (default) = when A has
+                               at least 4 Mi entries and 256 Ki columns. Never changes a result. */
 } ffx_build_opts;
 
 typedef struct ffx_matrix_s* ffx_matrix;
@@ -138,6 +144,8 @@ typedef struct {
   int32_t reordered;        /* 1 when the handle stores P A P^T (ffx_build_opts.reorder) */
   int64_t bandwidth_input;  /* max |i - j| over the entries of A */
   int64_t bandwidth_stored; /* the same for the stored operator (P A P^T when reordered) */
+  int64_t sg_groups;        /* column-sorted row groups (ffx_build_opts.col_sorted), 0 when not built */
+  int64_t sg_stream_bytes;  /* bytes a one-vector product streams from them (excluding x and y) */
 } ffx_matrix_info;
 
 /* Fill *opts with the defaults. */
@@ -263,7 +271,8 @@ ffx_status ffx_set_sequence_graph_batch(int32_t batch);
  * each with its own number s_k of right-hand sides, in one persistent launch.
  * It generalises the paper's treatment of submatrices in parallel
  * (Section 2.4, "New formats": split A into submatrices treated in parallel)
- * to independent matrices; the launch parameters come from a tuner that
+ * to independent matrices; the launch parameters (workgroups per CU, item
+ * order, column chunk, XCD queues, 16-bit X) come from a tuner that
  * times candidates on the batch itself, as the paper suggests tuning the
  * format parameters for the machine (Section 2.4, "Heuristic format chooser").
  * ------------------------------------------------------------------------ */
@@ -274,6 +283,12 @@ typedef struct {
   int32_t order;       /* 0: work items by decreasing estimated cost, 1: matrix order */
   int32_t max_chunk;   /* right-hand sides per work item: 4 or 8 (wider blocks are split) */
   int32_t use_graph;   /* 1: replay a captured hipGraph of the launch */
+  int32_t xcd;         /* 1: matrices split over 8 work queues, one per XCD (L2), workgroup g starting on
+                          queue g mod 8 and helping the others when its own is empty; 0: one queue */
+  int32_t compact_x;   /* m <= 65536, int64 accumulator: 1 gathers X from 16-bit copies made by the launch
+                          (the batch keeps the copies' memory, 2 bytes per element of every X_k), 0 never,
+                          -1 (default) as 0: a row gather costs a cache line either way, so on MI355X the
+                          copy has not paid for itself on multi-vector batches; the tuner tries both */
 } ffx_batch_params;
 
 /* Group `count` matrices (all with the same modulus and accumulator) with
@@ -353,6 +368,68 @@ ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowpt
                               const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts, float* out,
                               int64_t cap, int64_t* nblocks);
 
+/* Labels for training the selector, measured by the library on this GPU
+ * (Section 2.4, "Heuristic format chooser": the chooser's thresholds depend on
+ * the machine, so they are replaced by measurement). The window is a host CSR
+ * matrix given as to ffx_matrix_create_csr, m <= 65536. It is built once per
+ * format with every block forced to that format (the rest of the build from
+ * opts: block_rows, tile_entries, split_pm1, acc, compact_x; never with
+ * column-sorted groups, which would bypass the formats), and its whole
+ * product y = A x is timed in place on `stream` with HIP events: the median of
+ * `reps` launches (1..10000) after two warm-ups, x int32 residues drawn from
+ * `seed`. Timing the whole product keeps x at its real size, so the gathers
+ * cost what they cost in use. Outputs (host, cap rows each; FFX_EINVAL when
+ * cap is below the block count): feat, nblocks x 32 block features as the
+ * builder computes them; labels, nblocks x FFX_NUM_FORMATS, log2 of the
+ * window's product time per block in microseconds (every block of the window
+ * gets the window's label); heur (or NULL), the heuristic's format of each
+ * block. *nblocks (when not NULL) receives the block count. Waits for the
+ * stream. */
+ffx_status ffx_selector_label(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                              const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts,
+                              int32_t reps, uint64_t seed, void* stream, int64_t cap, float* feat, float* labels,
+                              int32_t* heur, int64_t* nblocks);
+
+typedef struct {
+  uint32_t size;         /* sizeof(ffx_train_opts) */
+  int32_t epochs;        /* passes over the training samples; default 60 */
+  int32_t batch;         /* samples per Adam step; default 512 */
+  float lr;              /* peak rate, decayed as lr * (1 + cos(pi * epoch / epochs)) / 2; default 2e-3 */
+  uint64_t seed;         /* initial weights (as ffx_selector_create) and sample order; default 0 */
+  int64_t n_val;         /* the first n_val samples are held out; -1 (default): n / 10 */
+  int32_t n_margins;     /* candidate decision margins in log2 units; 0 (default): 0, .05, .1, .2, .3, .5 */
+  const float* margins;  /* n_margins values (host) */
+} ffx_train_opts;
+
+typedef struct {
+  double train_loss, val_loss;  /* final masked half mean squared errors, targets relative to STREAM */
+  float margin;                 /* the decision margin folded into the output biases */
+  double val_cost;              /* held out: summed label time of the network's choices / of the best choices */
+  double val_cost_stream;       /* the same for STREAM on every block */
+  double val_cost_heuristic;    /* the same for heur (0 when heur is NULL) */
+  int32_t steps;                /* Adam steps taken */
+} ffx_train_report;
+
+void ffx_train_opts_default(ffx_train_opts* opts);
+
+/* Trains a selector from scratch on n labelled blocks (host arrays): X (n x 32
+ * raw features), T (n x FFX_NUM_FORMATS, log2 microseconds as
+ * ffx_selector_label writes them), mask (n x FFX_NUM_FORMATS of 0/1, or NULL:
+ * every label present), heur (n heuristic formats, or NULL; only reported).
+ * The steps, all in the library: input standardisation from the training
+ * samples (mean and 1/sd of each feature, scale 1 where sd < 1e-6); targets
+ * relative to STREAM (T[., f] - T[., 0]); minibatch Adam on the library's
+ * forward/backward kernels with the samples reshuffled every epoch and a
+ * cosine-decayed rate; then, on the held-out samples, the decision margin
+ * with the least summed label time (a block leaves STREAM only when the
+ * network predicts a gain above it), folded into the output biases. The model
+ * is written to out_model (when not NULL) and returned in *out (when not
+ * NULL; the caller destroys it). FFX_EINVAL for non-finite inputs or options
+ * out of range. Waits for the stream. */
+ffx_status ffx_selector_train(const float* X, const float* T, const float* mask, const int32_t* heur, int64_t n,
+                              const ffx_train_opts* opts, const char* out_model, ffx_selector* out,
+                              ffx_train_report* report, void* stream);
+
 /* Order basis (sigma-basis) of an m x n power series over the prime field
  * F_p, p < 2^31 (block Wiedemann step 2, Section 3.2; PM-Basis of Giorgi,
  * Jeannerod and Villard 2003 with one-order-at-a-time M-Basis below 32 orders):
@@ -370,6 +447,14 @@ ffx_status ffx_block_features(int64_t nrows, int64_t ncols, const int64_t* rowpt
  * (FFX_EINVAL otherwise). Waits for the stream. */
 ffx_status ffx_sigma_basis(uint32_t p, int32_t m, int32_t n, int64_t sigma, const uint32_t* G, int64_t ldg,
                            const int32_t* shift, uint32_t* M, int64_t ldm, int32_t* d_out, void* stream);
+
+/* Polynomial matrix products of the order basis whose two operands both have
+ * at least min_length coefficients go through number-theoretic transforms
+ * over three primes below 2^31 and a CRT (the paper's DFT multiplication,
+ * Section 3.2); smaller ones are schoolbook convolutions. Default 1024; 1
+ * sends every product through the transforms, 0 none. Process-wide; a tuning
+ * knob only: results never depend on it. FFX_EINVAL for a negative value. */
+ffx_status ffx_set_ntt_threshold(int64_t min_length);
 
 /* Block Wiedemann steps 2 and 3 (Section 3) on a sequence S_i = U^T A^i V,
  * i < L (as ffx_sequence writes it: device, L x s x s, residues mod the prime
@@ -402,6 +487,23 @@ ffx_status ffx_reorder_rcm(int64_t n, const int64_t* rowptr, const int32_t* coli
  * dtype (device). The outputs written meanwhile are the product's rows. */
 ffx_status ffx_matrix_block_times(ffx_matrix A, const void* x, void* y, ffx_dtype dtype, int32_t reps, float* us_out,
                                   void* stream);
+
+/* Calibration of the roofline of the products. A product streams its matrix
+ * coalesced and gathers one element (or one row of s elements) of x per entry
+ * at the entry's column; Section 2.5 ("Performance issues") names memory
+ * access as what limits sparse products, and on MI355X the limit of the large
+ * products is the rate at which random gathers are served by the vector L1/L2
+ * caches, well before HBM bandwidth. This call measures that rate in the
+ * products' pattern: count gathers of row_bytes-byte rows (2, 4, 8, 16, 32 or
+ * 64) from a device table of table_bytes bytes, each lane reading a streamed
+ * index word and gathering the row it names; indices are uniform over the
+ * table (window 0) or uniform inside aligned windows of `window` rows visited
+ * in order (the locality of a banded or reordered matrix). *rate (host)
+ * receives gathers per second, the median of `reps` launches (1..1000) after
+ * a warm-up launch. Allocates and frees its own buffers; waits for the
+ * stream. */
+ffx_status ffx_gather_rate(int64_t table_bytes, int32_t row_bytes, int64_t count, int64_t window, int32_t reps,
+                           void* stream, double* rate);
 
 /* Status name and the calling thread's last error message. */
 const char* ffx_status_str(ffx_status st);

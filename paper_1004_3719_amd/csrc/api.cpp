@@ -89,6 +89,8 @@ static PlanOpts plan_opts(const ffx_build_opts* o) {
   if (d.model_path) p.model_path = d.model_path;
   if (d.reorder < 0 || d.reorder > 1) fail(FFX_EINVAL, "reorder %d not in {0, 1}", d.reorder);
   p.reorder = d.reorder != 0;
+  if (d.col_sorted < -1 || d.col_sorted > 1) fail(FFX_EINVAL, "col_sorted %d not in {-1, 0, 1}", d.col_sorted);
+  p.col_sorted = d.col_sorted;
   return p;
 }
 
@@ -176,6 +178,16 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
     }
     M->chunk = maxterms > b;
     M->compact_x = M->md.small() && (po.compact_x == 1 || (po.compact_x == -1 && A.ncols * 4 > (1 << 20)));
+    // column-sorted groups for one-vector products: integer sums of terms below 2^32
+    const bool sg_ok = M->md.small() && M->acc == FFX_ACC_INT64 && S.nrows > 0;
+    const bool sg_auto = S.nnz() >= ((int64_t)1 << 22) && S.ncols >= ((int64_t)1 << 18);
+    if (sg_ok && (po.col_sorted == 1 || (po.col_sorted == -1 && sg_auto))) {
+      int dev = 0, ncu = 0;
+      FFX_HIP(hipGetDevice(&dev));
+      FFX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      encode_sg(S, M->md, po.split_pm1, ncu, st, &M->sg);
+      M->sg.dm.rowmap = M->perm;
+    }
     M->A.dm.reduce_every = b;
     M->AT.dm.reduce_every = b;
     ffx_matrix_info& I = M->info;
@@ -200,9 +212,13 @@ static ffx_matrix_s* build(const RCsr& A, uint32_t m, const ffx_build_opts* opts
     I.bandwidth_input = bandwidth(A);
     I.bandwidth_stored = po.reorder ? bandwidth(B) : I.bandwidth_input;
     I.device_bytes += po.reorder ? A.nrows * (int64_t)sizeof(uint32_t) : 0;
+    I.sg_groups = M->sg.ngroups;
+    I.sg_stream_bytes = M->sg.stream_bytes;
+    I.device_bytes += M->sg.device_bytes;
   } catch (...) {
     M->A.release();
     M->AT.release();
+    M->sg.release();
     if (M->perm) (void)hipFree(M->perm);
     delete M;
     throw;
@@ -304,6 +320,21 @@ static hipError_t row_product_in(const ffx_matrix_s& M, bool trans, int s, uint3
   const int64_t nin = trans ? M.info.nrows : M.info.ncols;
   const int ak = arith_kind(M);
   const bool c16 = s == 1 && M.compact_x && nin > 0;
+  if (!trans && s == 1 && M.sg.ngroups) {
+    // column-sorted groups: x (its 16-bit copy when the product takes one) in the stored order, and
+    // y written through the row map of a reordered handle (set in the groups' descriptor)
+    const void* xs = X;
+    if (M.perm) {
+      hipError_t e = c16 ? launch_permute_to_u16(dt, X, ldx, (uint16_t*)scratch, M.perm, nin, st)
+                         : launch_permute_rows(esize(dt), X, ldx, scratch, 1, M.perm, nin, 1, false, st);
+      if (e != hipSuccess) return e;
+      xs = scratch;
+    } else if (c16) {
+      hipError_t e = launch_compact_x(dt, X, ldx, (uint16_t*)scratch, nin, st);
+      if (e != hipSuccess) return e;
+    }
+    return launch_sg(M.sg.dm, dt, xs, c16 ? (const uint16_t*)scratch : nullptr, Y, alpha, beta, st);
+  }
   DevMat dm = E.dm;
   if (M.perm) {
     // stored as P A P^T: gather x into the stored order (into the 16-bit copy when the product takes
@@ -490,6 +521,7 @@ ffx_status ffx_matrix_destroy(ffx_matrix A) {
     if (!A) return;
     A->A.release();
     A->AT.release();
+    A->sg.release();
     if (A->perm) (void)hipFree(A->perm);
     delete A;
   });

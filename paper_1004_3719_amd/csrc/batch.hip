@@ -1,11 +1,24 @@
 // Batched products Y_k = A_k X_k over many matrices in one persistent launch.
 //
 // A work item is (matrix k, tile t, a group of at most 8 right-hand-side
-// columns). Persistent workgroups take items from a device counter in the
-// order of a list sorted by decreasing estimated cost (longest-processing-
+// columns). Persistent workgroups take items from device counters in the
+// order of lists sorted by decreasing estimated cost (longest-processing-
 // time first), so large tiles start early and small ones fill the tail. The
-// counter is cleared by a one-thread kernel before the launch (no memset), and
-// both launches can be captured into a hipGraph and replayed.
+// counters are cleared by a one-thread kernel before the launch (no memset),
+// and the launches can be captured into a hipGraph and replayed.
+//
+// XCD-affine queues: MI355X has 8 XCDs, each with its own L2, and hands out
+// consecutive workgroups to the XCDs in turn. With `xcd` set, the matrices are
+// split over 8 queues by estimated cost (longest first, to the least loaded
+// queue) and workgroup g works on queue g mod 8 first, so one matrix's X is
+// gathered through one L2 instead of all eight; a workgroup whose queue is
+// empty helps the others in turn. Results never depend on which workgroup
+// takes an item.
+//
+// 16-bit X: for m <= 65536 every residue fits 16 bits; with `compact_x` the
+// launch first copies each X_k to 16 bits (one kernel over the whole batch)
+// and the tiles gather half the bytes (off by default: a row gather costs a
+// cache line whatever its width, so the copy has not paid for itself).
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -32,7 +45,12 @@ struct BatchOperand {
   const void* X;
   void* Y;
   int64_t ldx, ldy;
+  uint16_t* X16;   // 16-bit copy of X (leading dimension s), or null
+  int64_t ncols;   // rows of X
+  int32_t s, pad;
 };
+
+constexpr int NQ = 8;  // work queues per chunk class: one per XCD
 
 // Right-hand-side column chunks fall in four classes (1, 2, 3..4, 5..8
 // columns), each with its own persistent kernel: a kernel holding every class's
@@ -46,37 +64,75 @@ inline int chunk_class(int sc) { return sc <= 1 ? 0 : sc <= 2 ? 1 : sc <= 4 ? 2 
 template <class AR>
 constexpr int batch_min_blocks() { return std::is_same<AR, ArSmall>::value ? 4 : 1; }
 
-template <class AR, typename Tv, int SC>
+// One class's items: queue q holds items [qfirst[q], qfirst[q] + qn[q]) of `items`; counter[q]
+// hands them out. Every workgroup sweeps all NQ queues, its own first, until each is exhausted.
+template <class AR, typename Tx, typename Tv, int SC>
 __global__ __launch_bounds__(TILE_THREADS, batch_min_blocks<AR>()) void k_batch(const DevMat* __restrict__ mats,
                                                         const BatchOperand* __restrict__ ops,
-                                                        const BatchItem* __restrict__ items, uint32_t nitems,
-                                                        uint32_t* counter) {
+                                                        const BatchItem* __restrict__ items,
+                                                        const uint32_t* __restrict__ qinfo, uint32_t* counter) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint32_t next;
-  for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t it = next;
-    __syncthreads();  // every lane has read `next` before thread 0 may overwrite it
-    if (it >= nitems) break;
-    const BatchItem I = items[it];
-    const DevMat A = mats[I.k];
-    const BatchOperand O = ops[I.k];
-    const Tile T = A.tiles[I.t];
-    const Tv* X = (const Tv*)O.X + I.c0;
-    Tv* Y = (Tv*)O.Y + I.c0;
-    const int sc = I.sc;
-    const uint32_t kind = tile_kind(T.kind);
-    if constexpr (SC == 1) {
-      if (kind == TK_SELL) sell_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0);
-      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, 1, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 1, 0, lds);
-      else stream_tile_1<AR, Tv, Tv, 2>(A, T, X, O.ldx, Y, O.ldy, 1, 0, lds);
-    } else {
-      if (kind == TK_SELL) sell_tile_rc<AR, Tv, Tv, SC>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0);
-      else if (kind == TK_LONG) long_tile<AR, Tv, Tv, SC, 1>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
-      else stream_tile_s<AR, Tv, Tv, SC>(A, T, X, O.ldx, Y, O.ldy, sc, 1, 0, lds);
+  const uint32_t home = blockIdx.x % NQ;
+  for (uint32_t j = 0; j < NQ; ++j) {
+    const uint32_t q = (home + j) % NQ;
+    const uint32_t qf = qinfo[q], qn = qinfo[NQ + q];
+    for (;;) {
+      if (threadIdx.x == 0) next = atomicAdd(&counter[q], 1u);
+      __syncthreads();
+      const uint32_t it = next;
+      __syncthreads();  // every lane has read `next` before thread 0 may overwrite it
+      if (it >= qn) break;
+      const BatchItem I = items[qf + it];
+      const DevMat A = mats[I.k];
+      const BatchOperand O = ops[I.k];
+      const Tile T = A.tiles[I.t];
+      const bool x16 = sizeof(Tx) == 2;
+      const Tx* X = x16 ? (const Tx*)O.X16 + I.c0 : (const Tx*)O.X + I.c0;
+      const int64_t ldx = x16 ? (int64_t)O.s : O.ldx;
+      Tv* Y = (Tv*)O.Y + I.c0;
+      const int sc = I.sc;
+      const uint32_t kind = tile_kind(T.kind);
+      if constexpr (SC == 1) {
+        if (kind == TK_SELL) sell_tile<AR, Tx, Tv, 1, 2>(A, T, X, ldx, Y, O.ldy, 1, 1, 0);
+        else if (kind == TK_LONG) long_tile<AR, Tx, Tv, 1, 2>(A, T, X, ldx, Y, O.ldy, 1, 1, 0, lds);
+        else stream_tile_1<AR, Tx, Tv, 2>(A, T, X, ldx, Y, O.ldy, 1, 0, lds);
+      } else {
+        if (kind == TK_SELL) sell_tile_rc<AR, Tx, Tv, SC>(A, T, X, ldx, Y, O.ldy, sc, 1, 0);
+        else if (kind == TK_LONG) long_tile<AR, Tx, Tv, SC, 1>(A, T, X, ldx, Y, O.ldy, sc, 1, 0, lds);
+        else stream_tile_s<AR, Tx, Tv, SC>(A, T, X, ldx, Y, O.ldy, sc, 1, 0, lds);
+      }
+      __syncthreads();  // LDS is reused by the next item
     }
-    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+// X16 of every operand with one: element e = row * s + c of X_k, row-major with leading dimension s.
+// blockIdx.y is the matrix; blocks stride over its elements.
+template <typename Tv>
+__global__ void k_batch_x16(const BatchOperand* __restrict__ ops) {
+  const BatchOperand O = ops[blockIdx.y];
+  if (!O.X16) return;
+  const int64_t total = O.ncols * O.s;
+  const Tv* X = (const Tv*)O.X;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (O.ldx == O.s) {  // contiguous rows: a plain converting copy
+    for (int64_t e = first; e < total; e += stride) O.X16[e] = (uint16_t)X[e];
+    return;
+  }
+  // strided rows: walk (row, column) without dividing (a 64-bit division per element is slow)
+  const int64_t s = O.s;
+  int64_t row = first / s, c = first - row * s;
+  const int64_t drow = stride / s, dc = stride - drow * s;
+  for (int64_t e = first; e < total; e += stride) {
+    O.X16[e] = (uint16_t)X[row * O.ldx + c];
+    row += drow;
+    c += dc;
+    if (c >= s) {
+      c -= s;
+      ++row;
+    }
   }
 }
 
@@ -90,21 +146,30 @@ static size_t batch_lds(int64_t mte, int sc) {
   return a < 16 ? 16 : a;
 }
 
-// One class's persistent launch over items [first, first + n).
-static hipError_t batch_launch_class(int ak, ffx_dtype dt, int cls, const DevMat* mats, const BatchOperand* ops,
-                                     const BatchItem* items, uint32_t n, uint32_t* counter, int grid, int64_t mte,
-                                     hipStream_t st) {
+// One class's persistent launch over its items (qinfo: the class's queue table, counter: its NQ counters).
+static hipError_t batch_launch_class(int ak, ffx_dtype dt, bool x16, int cls, const DevMat* mats,
+                                     const BatchOperand* ops, const BatchItem* items, const uint32_t* qinfo,
+                                     uint32_t* counter, int grid, int64_t mte, hipStream_t st) {
   auto go = [&](auto ar) {
     using AR = decltype(ar);
-    auto launch = [&](auto tv, auto scv) {
+    auto launch = [&](auto tx, auto tv, auto scv) {
+      using Tx = decltype(tx);
       using Tv = decltype(tv);
       constexpr int SC = decltype(scv)::value;
-      hipLaunchKernelGGL((k_batch<AR, Tv, SC>), dim3(grid), dim3(TILE_THREADS), batch_lds<AR>(mte, SC), st, mats, ops,
-                         items, n, counter);
+      hipLaunchKernelGGL((k_batch<AR, Tx, Tv, SC>), dim3(grid), dim3(TILE_THREADS), batch_lds<AR>(mte, SC), st, mats,
+                         ops, items, qinfo, counter);
     };
     auto by_dt = [&](auto scv) {
-      if (dt == FFX_I32) launch(int32_t{}, scv);
-      else launch(int64_t{}, scv);
+      // the 16-bit gathers are built for the integer class of m <= 65536 only
+      if constexpr (std::is_same<AR, ArSmall>::value) {
+        if (x16) {
+          if (dt == FFX_I32) launch(uint16_t{}, int32_t{}, scv);
+          else launch(uint16_t{}, int64_t{}, scv);
+          return;
+        }
+      }
+      if (dt == FFX_I32) launch(int32_t{}, int32_t{}, scv);
+      else launch(int64_t{}, int64_t{}, scv);
     };
     switch (cls) {
       case 0: by_dt(std::integral_constant<int, 1>{}); break;
@@ -150,9 +215,13 @@ struct ffx_batch_s {
   DevMat* d_mats = nullptr;
   BatchOperand* d_ops = nullptr;
   BatchItem* d_items = nullptr;
-  uint32_t* d_counter = nullptr;  // one per chunk class
+  uint32_t* d_counter = nullptr;  // NQ per chunk class
+  uint32_t* d_qinfo = nullptr;    // per chunk class: NQ queue starts, then NQ queue lengths (items of the class)
+  uint16_t* d_x16 = nullptr;      // 16-bit copies of every X_k (compact_x)
+  std::vector<int64_t> x16_off;   // element offset of each X_k's copy
   uint32_t nitems = 0;
   uint32_t cls_first[NCLS] = {0, 0, 0, 0}, cls_n[NCLS] = {0, 0, 0, 0};
+  bool small = false;             // m <= 65536 on the integer class: 16-bit X is available
   std::vector<BatchOperand> h_ops;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -176,6 +245,7 @@ static void batch_items(ffx_batch_s* B) {
   std::vector<BatchItem> items;
   std::vector<uint64_t> cost;
   const int chunk = B->params.max_chunk == 4 ? 4 : 8;
+  std::vector<uint64_t> mcost(B->count, 0);
   for (int k = 0; k < B->count; ++k) {
     const auto& tc = matrix_tile_cost(*B->mats[k]);
     for (uint32_t t = 0; t < (uint32_t)tc.size(); ++t)
@@ -183,28 +253,51 @@ static void batch_items(ffx_batch_s* B) {
         int sc = std::min(chunk, B->s[k] - c0);
         items.push_back(BatchItem{(uint32_t)k, t, (uint16_t)c0, (uint16_t)sc, 0});
         cost.push_back((uint64_t)tc[t] * (uint64_t)(sc + 3));
+        mcost[k] += cost.back();
       }
   }
-  // by chunk class (each class is one kernel), then by decreasing cost when order == 0
+  // queue of each matrix: all in queue 0, or (xcd) longest matrix first to the least loaded queue
+  std::vector<int> mq(B->count, 0);
+  if (B->params.xcd) {
+    std::vector<int> order(B->count);
+    for (int k = 0; k < B->count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mcost[a] > mcost[b]; });
+    uint64_t load[NQ] = {0};
+    for (int k : order) {
+      int q = (int)(std::min_element(load, load + NQ) - load);
+      mq[k] = q;
+      load[q] += mcost[k];
+    }
+  }
+  // by chunk class (each class is one kernel), then queue, then by decreasing cost when order == 0
   std::vector<size_t> idx(items.size());
   for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
   const bool by_cost = B->params.order == 0;
   std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
     int ca = chunk_class(items[a].sc), cb = chunk_class(items[b].sc);
     if (ca != cb) return ca < cb;
+    int qa = mq[items[a].k], qb = mq[items[b].k];
+    if (qa != qb) return qa < qb;
     return by_cost && cost[a] > cost[b];
   });
   std::vector<BatchItem> sorted(items.size());
   for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
   items.swap(sorted);
+  std::vector<uint32_t> qinfo(NCLS * 2 * NQ, 0);
   for (int c = 0; c < NCLS; ++c) B->cls_first[c] = B->cls_n[c] = 0;
   for (size_t i = 0; i < items.size(); ++i) {
     int c = chunk_class(items[i].sc);
     if (B->cls_n[c]++ == 0) B->cls_first[c] = (uint32_t)i;
   }
+  for (size_t i = 0; i < items.size(); ++i) {  // queue starts relative to the class's first item
+    int c = chunk_class(items[i].sc), q = mq[items[i].k];
+    uint32_t* qi = &qinfo[c * 2 * NQ];
+    if (qi[NQ + q]++ == 0) qi[q] = (uint32_t)i - B->cls_first[c];
+  }
   if (B->d_items) (void)hipFree(B->d_items);
   B->d_items = nullptr;
   B->nitems = (uint32_t)items.size();
+  FFX_HIP(hipMemcpy(B->d_qinfo, qinfo.data(), qinfo.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   if (items.empty()) return;
   FFX_HIP(hipMalloc(&B->d_items, items.size() * sizeof(BatchItem)));
   FFX_HIP(hipMemcpy(B->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
@@ -214,7 +307,12 @@ static void check_params(const ffx_batch_params& p) {
   if (p.wg_per_cu < 0 || p.wg_per_cu > 8) fail(FFX_EINVAL, "wg_per_cu %d outside [0, 8]", p.wg_per_cu);
   if (p.order != 0 && p.order != 1) fail(FFX_EINVAL, "order %d", p.order);
   if (p.max_chunk != 4 && p.max_chunk != 8) fail(FFX_EINVAL, "max_chunk %d (4 or 8)", p.max_chunk);
+  if (p.xcd != 0 && p.xcd != 1) fail(FFX_EINVAL, "xcd %d (0 or 1)", p.xcd);
+  if (p.compact_x < -1 || p.compact_x > 1) fail(FFX_EINVAL, "compact_x %d (-1, 0 or 1)", p.compact_x);
 }
+
+// whether this batch's launches gather from 16-bit copies of X
+static bool use_x16(const ffx_batch_s* B) { return B->small && B->params.compact_x == 1; }
 
 static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
                       ffx_dtype dt, hipStream_t st) {
@@ -231,13 +329,35 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
     B->h_ops[k] = BatchOperand{X[k], Y[k], ldx[k], ldy[k]};
   }
   if (B->nitems == 0) return;
+  const bool x16 = use_x16(B);
+  if (x16 && !B->d_x16) {
+    int64_t total = 0;
+    B->x16_off.assign(B->count, 0);
+    for (int k = 0; k < B->count; ++k) {
+      B->x16_off[k] = total;
+      total += (B->mats[k]->info.ncols * B->s[k] + 127) / 128 * 128;  // 256-byte aligned copies
+    }
+    FFX_HIP(hipMalloc((void**)&B->d_x16, (size_t)std::max<int64_t>(total, 1) * 2));
+  }
+  for (int k = 0; k < B->count; ++k) {
+    BatchOperand& o = B->h_ops[k];
+    o.X16 = x16 ? B->d_x16 + B->x16_off[k] : nullptr;
+    o.ncols = B->mats[k]->info.ncols;
+    o.s = B->s[k];
+  }
   // operand table: pageable host memory, so the copy is staged before the call returns
   FFX_HIP(hipMemcpyAsync(B->d_ops, B->h_ops.data(), B->h_ops.size() * sizeof(BatchOperand), hipMemcpyHostToDevice, st));
   const int wpc = B->params.wg_per_cu ? B->params.wg_per_cu : 4;
   auto grid_of = [&](int c) { return (int)std::min<int64_t>((int64_t)B->ncu * wpc, B->cls_n[c]); };
   auto launch_class = [&](int c, hipStream_t s) {
-    return batch_launch_class(B->ak, dt, c, B->d_mats, B->d_ops, B->d_items + B->cls_first[c], B->cls_n[c],
-                              B->d_counter + c, grid_of(c), B->mte, s);
+    return batch_launch_class(B->ak, dt, x16, c, B->d_mats, B->d_ops, B->d_items + B->cls_first[c],
+                              B->d_qinfo + c * 2 * NQ, B->d_counter + c * NQ, grid_of(c), B->mte, s);
+  };
+  auto launch_x16 = [&](hipStream_t s) -> hipError_t {
+    if (!x16) return hipSuccess;
+    if (dt == FFX_I32) hipLaunchKernelGGL(k_batch_x16<int32_t>, dim3(64, B->count), dim3(256), 0, s, B->d_ops);
+    else hipLaunchKernelGGL(k_batch_x16<int64_t>, dim3(64, B->count), dim3(256), 0, s, B->d_ops);
+    return hipGetLastError();
   };
   if (B->params.use_graph) {
     if (B->exec && B->graph_dt != (int)dt) B->drop_graph();
@@ -256,8 +376,9 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
       if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, cs, B->d_counter, NCLS);
-        hipError_t le = hipEventRecord(ev0, cs);
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, cs, B->d_counter, NCLS * NQ);
+        hipError_t le = launch_x16(cs);
+        if (le == hipSuccess) le = hipEventRecord(ev0, cs);
         for (int c = 0; c < NCLS && le == hipSuccess; ++c) {
           if (!B->cls_n[c]) continue;
           le = hipStreamWaitEvent(br[c], ev0, 0);
@@ -283,7 +404,8 @@ static void batch_run(ffx_batch_s* B, const void* const* X, const int64_t* ldx, 
     FFX_HIP(hipGraphLaunch(B->exec, st));
     return;
   }
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B->d_counter, NCLS);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B->d_counter, NCLS * NQ);
+  FFX_HIP(launch_x16(st));
   for (int c = 0; c < NCLS; ++c)
     if (B->cls_n[c]) FFX_HIP(launch_class(c, st));
 }
@@ -296,7 +418,8 @@ static std::string device_name() {
   return std::string(p.gcnArchName) + ":" + std::to_string(p.multiProcessorCount);
 }
 
-// tiny JSON cache: one line per entry, "key": {"wg_per_cu": a, "order": b, "max_chunk": c}
+// tiny JSON cache: one line per entry, "key": {"wg_per_cu": a, "order": b, "max_chunk": c, "xcd": d,
+// "compact_x": e}
 static bool cache_lookup(const char* path, const std::string& key, ffx_batch_params& p) {
   if (!path) return false;
   std::ifstream f(path);
@@ -304,12 +427,15 @@ static bool cache_lookup(const char* path, const std::string& key, ffx_batch_par
   while (std::getline(f, line)) {
     size_t q = line.find("\"" + key + "\"");
     if (q == std::string::npos) continue;
-    int a, b, c;
+    int a, b, c, d, e;
     const char* s = line.c_str() + q + key.size() + 2;
-    if (sscanf(s, " : {\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d", &a, &b, &c) == 3) {
+    if (sscanf(s, " : {\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d, \"xcd\": %d, \"compact_x\": %d", &a, &b, &c,
+               &d, &e) == 5) {
       p.wg_per_cu = a;
       p.order = b;
       p.max_chunk = c;
+      p.xcd = d;
+      p.compact_x = e;
       return true;
     }
   }
@@ -329,8 +455,8 @@ static void cache_store(const char* path, const std::string& key, const ffx_batc
       }
   }
   char buf[512];
-  snprintf(buf, sizeof buf, "  \"%s\": {\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d}", key.c_str(),
-           p.wg_per_cu, p.order, p.max_chunk);
+  snprintf(buf, sizeof buf, "  \"%s\": {\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d, \"xcd\": %d, \"compact_x\": %d}",
+           key.c_str(), p.wg_per_cu, p.order, p.max_chunk, p.xcd, p.compact_x);
   lines.push_back(buf);
   std::ofstream f(path);
   f << "{\n";
@@ -351,7 +477,7 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
       B->count = count;
       B->mats.assign(mats, mats + count);
       B->s.assign(s, s + count);
-      B->params = ffx_batch_params{0, 0, 8, 1};
+      B->params = ffx_batch_params{0, 0, 8, 1, 1, -1};
       if (params) {
         check_params(*params);
         B->params = *params;
@@ -379,7 +505,9 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
       FFX_HIP(hipMalloc(&B->d_mats, sizeof(DevMat) * count));
       FFX_HIP(hipMemcpy(B->d_mats, dm.data(), sizeof(DevMat) * count, hipMemcpyHostToDevice));
       FFX_HIP(hipMalloc(&B->d_ops, sizeof(BatchOperand) * count));
-      FFX_HIP(hipMalloc(&B->d_counter, NCLS * sizeof(uint32_t)));
+      FFX_HIP(hipMalloc(&B->d_counter, NCLS * NQ * sizeof(uint32_t)));
+      FFX_HIP(hipMalloc(&B->d_qinfo, NCLS * 2 * NQ * sizeof(uint32_t)));
+      B->small = B->ak == AK_SMALL;
       B->h_ops.resize(count);
       batch_items(B);
       (void)stream;
@@ -388,6 +516,7 @@ ffx_status ffx_batch_create(int32_t count, const ffx_matrix* mats, const int32_t
       if (B->d_ops) (void)hipFree(B->d_ops);
       if (B->d_items) (void)hipFree(B->d_items);
       if (B->d_counter) (void)hipFree(B->d_counter);
+      if (B->d_qinfo) (void)hipFree(B->d_qinfo);
       delete B;
       throw;
     }
@@ -414,7 +543,7 @@ ffx_status ffx_batch_set_params(ffx_batch B, const ffx_batch_params* p) {
   return guard([&] {
     if (!B || !p) fail(FFX_EINVAL, "NULL argument");
     check_params(*p);
-    bool relist = p->order != B->params.order || p->max_chunk != B->params.max_chunk;
+    bool relist = p->order != B->params.order || p->max_chunk != B->params.max_chunk || p->xcd != B->params.xcd;
     B->params = *p;
     B->drop_graph();
     if (relist) batch_items(B);
@@ -428,14 +557,16 @@ ffx_status ffx_batch_tune(ffx_batch B, const void* const* X, const int64_t* ldx,
     hipStream_t st = (hipStream_t)stream;
     const std::string key = device_name() + "|" + B->signature;
     ffx_batch_params p = B->params;
-    if (cache_lookup(cache_path, key, p)) {
-      check_params(p);
-      bool relist = p.order != B->params.order || p.max_chunk != B->params.max_chunk;
-      B->params.wg_per_cu = p.wg_per_cu;
-      B->params.order = p.order;
-      B->params.max_chunk = p.max_chunk;
+    auto apply = [&](const ffx_batch_params& c) {
+      bool relist = c.order != B->params.order || c.max_chunk != B->params.max_chunk || c.xcd != B->params.xcd;
+      B->params = c;
       B->drop_graph();
       if (relist) batch_items(B);
+    };
+    if (cache_lookup(cache_path, key, p)) {
+      check_params(p);
+      p.use_graph = B->params.use_graph;
+      apply(p);
       if (best) *best = B->params;
       return;
     }
@@ -446,33 +577,32 @@ ffx_status ffx_batch_tune(ffx_batch B, const void* const* X, const int64_t* ldx,
     float best_ms = 1e30f;
     ffx_batch_params bp = B->params;
     const int wpcs[] = {1, 2, 4, 8};
-    for (int chunk : {8, 4})
-      for (int order : {0, 1})
-        for (int wpc : wpcs) {
-          ffx_batch_params c{wpc, order, chunk, 0};
-          bool relist = c.order != B->params.order || c.max_chunk != B->params.max_chunk;
-          B->params = c;
-          B->drop_graph();
-          if (relist) batch_items(B);
-          batch_run(B, X, ldx, Y, ldy, dtype, st);  // warm
-          FFX_HIP(hipEventRecord(e0, st));
-          for (int r = 0; r < reps; ++r) batch_run(B, X, ldx, Y, ldy, dtype, st);
-          FFX_HIP(hipEventRecord(e1, st));
-          FFX_HIP(hipEventSynchronize(e1));
-          float ms = 0;
-          FFX_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (ms < best_ms) {
-            best_ms = ms;
-            bp = c;
-          }
-        }
+    const int x16s[] = {0, 1};
+    for (int x16 : x16s) {
+      if (x16 && !B->small) continue;
+      for (int xcd : {1, 0})
+        for (int chunk : {8, 4})
+          for (int order : {0, 1})
+            for (int wpc : wpcs) {
+              ffx_batch_params c{wpc, order, chunk, 0, xcd, x16};
+              apply(c);
+              batch_run(B, X, ldx, Y, ldy, dtype, st);  // warm
+              FFX_HIP(hipEventRecord(e0, st));
+              for (int r = 0; r < reps; ++r) batch_run(B, X, ldx, Y, ldy, dtype, st);
+              FFX_HIP(hipEventRecord(e1, st));
+              FFX_HIP(hipEventSynchronize(e1));
+              float ms = 0;
+              FFX_HIP(hipEventElapsedTime(&ms, e0, e1));
+              if (ms < best_ms) {
+                best_ms = ms;
+                bp = c;
+              }
+            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     bp.use_graph = 1;
-    bool relist = bp.order != B->params.order || bp.max_chunk != B->params.max_chunk;
-    B->params = bp;
-    B->drop_graph();
-    if (relist) batch_items(B);
+    apply(bp);
     cache_store(cache_path, key, bp);
     if (best) *best = bp;
   });
@@ -486,6 +616,8 @@ ffx_status ffx_batch_destroy(ffx_batch B) {
     if (B->d_ops) (void)hipFree(B->d_ops);
     if (B->d_items) (void)hipFree(B->d_items);
     if (B->d_counter) (void)hipFree(B->d_counter);
+    if (B->d_qinfo) (void)hipFree(B->d_qinfo);
+    if (B->d_x16) (void)hipFree(B->d_x16);
     delete B;
   });
 }

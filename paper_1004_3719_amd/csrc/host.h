@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "ffx_impl.h"
+#include "sg.h"
 
 namespace ffx {
 
@@ -92,6 +93,7 @@ struct PlanOpts {
   int compact_x = -1;
   std::string model_path;
   bool reorder = false;
+  int col_sorted = -1;
 };
 
 BlockStats block_stats(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, const PlanOpts& o);
@@ -127,6 +129,16 @@ Modulus make_modulus(uint32_t m);
 void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t stream, Encoded* out,
             const std::vector<int32_t>* forced_formats = nullptr);
 
+// Column-sorted row groups of a matrix for the one-vector product (sg.h).
+struct SgEncoded {
+  SgMat dm{};
+  void* alloc = nullptr;
+  int64_t ngroups = 0, device_bytes = 0, stream_bytes = 0;
+  void release();
+};
+// Encodes A (m <= 65536) in about target_groups groups and uploads it.
+void encode_sg(const RCsr& A, const Modulus& md, bool split_pm1, int target_groups, hipStream_t st, SgEncoded* out);
+
 // Learned selector hook: fills fmt for the blocks, returns false to fall back.
 bool learned_formats(const std::string& model_path, const std::vector<BlockStats>& blocks, std::vector<int32_t>& fmt,
                      hipStream_t stream);
@@ -147,6 +159,7 @@ struct ffx_matrix_s {
   bool chunk = false;   // some row needs reductions inside the row
   bool compact_x = false;  // one-vector products gather x from a 16-bit copy
   ffx::Encoded A, AT;
+  ffx::SgEncoded sg;  // column-sorted groups of A for one-vector products (when built)
   bool has_t = false;
   // reordered matrices: A and AT hold P A P^T; perm[new] = old on the device
   uint32_t* perm = nullptr;

@@ -1,0 +1,130 @@
+// The one-vector product on column-sorted row groups (layout in sg.h).
+#include <algorithm>
+#include <mutex>
+
+#include "sg.h"
+
+namespace ffx {
+
+constexpr int SG_THREADS = 1024;  // one workgroup per compute unit: 16 waves
+constexpr int SG_U = 2;           // chunks per wave in flight
+// Dynamic LDS of one group is at least this much, so that a compute unit never
+// holds two groups (the groups are sized to be about one per compute unit, and
+// two on one CU would leave another CU idle).
+constexpr size_t SG_LDS_FLOOR = 96 * 1024;
+
+__device__ inline uint32_t sg_lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename Tx, typename Tv, int NT, int U>
+__global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv* __restrict__ y, uint32_t alpha,
+                                           uint32_t beta) {
+  extern __shared__ __align__(16) unsigned long long acc[];
+  constexpr uint32_t NW = NT / WAVE;
+  const SgGroup g = G.groups[blockIdx.x];
+  const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  for (uint32_t r = tid; r < g.nrows; r += NT) acc[r] = 0ull;
+  __syncthreads();
+  // the entry words of the next U chunks are requested before the values and gathers of the
+  // current ones, so each pass waits on one round trip to memory instead of two
+  uint32_t w[U][4], vo[U], cb[U];
+  auto load_words = [&](uint32_t ch0, uint32_t (&ww)[U][4], uint32_t (&vv)[U], uint32_t (&cc)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t ch = ch0 + u * NW;
+      const bool ok = ch < g.nchunks;
+      const uint32_t* p = G.ent + (size_t)(g.c0 + (ok ? ch : 0)) * SG_CHUNK + lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ww[u][k] = ok ? __builtin_nontemporal_load(p + WAVE * k) : PAD_WORD;
+      vv[u] = ok ? G.choff[g.c0 + ch] : 0u;
+      cc[u] = ok ? G.cbase[g.c0 + ch] : 0u;
+    }
+  };
+  load_words(wave, w, vo, cb);
+  for (uint32_t ch0 = wave; ch0 < g.nchunks; ch0 += NW * U) {
+    uint32_t wn[U][4], von[U], cbn[U];
+    load_words(ch0 + NW * U, wn, von, cbn);
+    // values (compacted: the general entries before this one in the chunk give its index) and x
+    uint32_t v[U][4], xv[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t idx = vo[u];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t tag = w[u][k] >> TAG_SHIFT;
+        const bool gen = tag == TAG_GEN;
+        const uint64_t b = __ballot(gen);
+        const uint32_t my = idx + sg_lanes_below(b);
+        idx += (uint32_t)__popcll(b);
+        v[u][k] = gen ? (uint32_t)__builtin_nontemporal_load(G.val + my) : 0u;
+        xv[u][k] = tag != TAG_PAD ? (uint32_t)x[cb[u] + (w[u][k] & SG_COL_MASK)] : 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t tag = w[u][k] >> TAG_SHIFT;
+        if (tag != TAG_PAD) {
+          // a term is below 2^32: (m-1)^2, x or m - x
+          const uint32_t t = tag == TAG_GEN ? v[u][k] * xv[u][k] : tag == TAG_PLUS ? xv[u][k] : G.m - xv[u][k];
+          atomicAdd(&acc[(w[u][k] >> SG_ROW_SHIFT) & (SG_MAX_ROWS - 1)], (unsigned long long)t);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      vo[u] = von[u];
+      cb[u] = cbn[u];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[u][k] = wn[u][k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t r = tid; r < g.nrows; r += NT) {
+    const uint32_t row = g.row0 + r;
+    Tv* yr = y + (G.rowmap ? G.rowmap[row] : row);
+    const uint32_t res = mod_u64(acc[r], G.m, G.mu);
+    *yr = (Tv)((alpha == 1 && beta == 0) ? res : axpby(alpha, res, beta, beta ? (uint32_t)*yr : 0u, G.m, G.mu));
+  }
+}
+
+// The largest dynamic LDS a group can ask for: SG_MAX_ROWS 64-bit sums.
+constexpr size_t SG_LDS_MAX = (size_t)SG_MAX_ROWS * 8;
+
+template <typename Tx, typename Tv>
+static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint32_t beta, hipStream_t st) {
+  const size_t lds = std::max<size_t>((size_t)G.max_rows * 8, SG_LDS_FLOOR);
+  auto k = k_sg<Tx, Tv, SG_THREADS, SG_U>;
+  // the kernel's LDS limit is raised once per device to the most any group can need (the
+  // attribute is a host call that would otherwise cost a few microseconds per product)
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done[dev]) {
+      e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SG_LDS_MAX);
+      if (e != hipSuccess) return e;
+      done[dev] = true;
+    }
+  }
+  hipLaunchKernelGGL(k, dim3(G.ngroups), dim3(SG_THREADS), lds, st, G, x, y, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_sg(const SgMat& G, ffx_dtype dt, const void* x, const uint16_t* x16, void* y, uint32_t alpha,
+                     uint32_t beta, hipStream_t st) {
+  if (G.ngroups == 0) return hipSuccess;
+  if (dt == FFX_I32) {
+    if (x16) return sg_go<uint16_t, int32_t>(G, x16, (int32_t*)y, alpha, beta, st);
+    return sg_go<int32_t, int32_t>(G, (const int32_t*)x, (int32_t*)y, alpha, beta, st);
+  }
+  if (x16) return sg_go<uint16_t, int64_t>(G, x16, (int64_t*)y, alpha, beta, st);
+  return sg_go<int64_t, int64_t>(G, (const int64_t*)x, (int64_t*)y, alpha, beta, st);
+}
+
+}  // namespace ffx

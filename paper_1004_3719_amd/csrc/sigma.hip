@@ -12,15 +12,17 @@
 // divide-and-conquer result is the same basis, step for step, as M-Basis run
 // over the whole order.
 //
-// The polynomial matrix products are schoolbook convolutions on the vector
-// ALU (the paper multiplies through a DFT; p = 2^31 - 1 has no large
-// power-of-two roots of unity, so an NTT would need several primes and a CRT).
+// Large polynomial matrix products go through number-theoretic transforms over
+// three word-size primes and a CRT (the paper's DFT multiplication; see the
+// NTT section below); the small ones, where the transforms' passes cost more
+// than the convolution, are schoolbook convolutions on the vector ALU.
 // A workgroup computes 256 consecutive coefficients of one entry; for each
 // inner index q and each 256-coefficient chunk of A it stages the chunk of A and
 // the 511 coefficients of B that the tile needs in LDS, and every lane adds
 // 256 products into a 96-bit accumulator (64-bit sum plus a carry count), so a
 // coefficient is reduced once.
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "host.h"
@@ -412,9 +414,237 @@ static Field make_field(uint32_t p) {
   return F;
 }
 
+// ------------------------------------------------------------ NTT products
+// The paper multiplies the polynomial matrices of PM-Basis through a DFT
+// (Section 3.2, "Parallel polynomial matrix multiplication": transform the
+// entries, multiply the transformed matrices point by point, transform back).
+// F_p with p = 2^31 - 1 has no roots of unity of large power-of-two order, so
+// the product is taken over the integers: exactly modulo three primes below
+// 2^31 that have roots of unity of order 2^25 and more, with the coefficients
+// recovered by the Chinese remainder theorem (Garner's mixed-radix form) and
+// reduced mod p. An integer coefficient of the product is below
+// Q * min(la, lb) * (p-1)^2, checked on the host against the product of the
+// three primes (about 2^92.6).
+//
+// Transforms of length N (a power of two) run as log2 N radix-2 passes over
+// global memory, each pass one launch over every entry and prime: forward
+// passes are decimation in frequency (natural order in, bit-reversed out), the
+// pointwise products work in that order, and the inverse passes are
+// decimation in time (bit-reversed in, natural out). Products are cyclic of
+// length N; N covers the wanted coefficients k0 .. k0+len-1 and is large
+// enough that no coefficient of the full product wraps onto them.
+constexpr int NTT_NP = 3;
+static const uint32_t NTT_PRIME[NTT_NP] = {2013265921u, 1811939329u, 2113929217u};  // 15*2^27+1, 27*2^26+1, 63*2^25+1
+static const uint32_t NTT_GEN[NTT_NP] = {31u, 13u, 5u};                            // primitive roots
+
+struct NttPrimes {
+  uint32_t p[NTT_NP];
+  uint64_t mu[NTT_NP];
+};
+
+__device__ inline uint32_t nmul(uint32_t a, uint32_t b, uint32_t p, uint64_t mu) { return mod_u64((uint64_t)a * b, p, mu); }
+
+// dst[i][e][t] = t < len ? src[e][t] mod p_i : 0, for n entries (entry e of src at src + e*stride)
+__global__ void k_ntt_load(const uint32_t* __restrict__ src, int64_t stride, int64_t len, int ne, uint32_t* __restrict__ dst,
+                           int64_t N, int dst_ne, int e0, NttPrimes P) {
+  const int64_t total = (int64_t)NTT_NP * ne * N;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = g % N;
+    const int64_t e = (g / N) % ne;
+    const int i = (int)(g / (N * ne));
+    const uint32_t v = t < len ? src[e * stride + t] % P.p[i] : 0u;
+    dst[((int64_t)i * dst_ne + e0 + e) * N + t] = v;
+  }
+}
+
+// tw[i][k] = w_i^k and itw[i][k] = w_i^-k, k < N/2, w_i a root of unity of order N modulo p_i
+__global__ void k_ntt_twiddles(uint32_t* __restrict__ tw, int64_t half, const uint32_t* __restrict__ roots,
+                               NttPrimes P) {
+  const int64_t total = (int64_t)2 * NTT_NP * half;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = g % half;
+    const int q = (int)(g / half);  // 0..2: forward roots, 3..5: inverse roots
+    const int i = q % NTT_NP;
+    uint32_t r = 1, b = roots[q];
+    for (int64_t e = k; e; e >>= 1) {
+      if (e & 1) r = nmul(r, b, P.p[i], P.mu[i]);
+      b = nmul(b, b, P.p[i], P.mu[i]);
+    }
+    tw[g] = r;
+  }
+}
+
+// One radix-2 pass over ne entries of every prime, butterflies of span h: forward (decimation in
+// frequency) a, b -> a + b, (a - b) w^(j N / 2h); inverse (decimation in time) a, b -> a + b w', a - b w'.
+template <bool INV>
+__global__ void k_ntt_pass(uint32_t* __restrict__ X, int64_t N, int64_t h, int ne, const uint32_t* __restrict__ tw,
+                           NttPrimes P) {
+  const int64_t half = N / 2, total = (int64_t)NTT_NP * ne * half;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = g % half;
+    const int64_t row = g / half;  // prime * ne + entry
+    const int i = (int)(row / ne);
+    const uint32_t p = P.p[i];
+    const int64_t j = b % h, blk = b / h;
+    uint32_t* x = X + row * N + blk * 2 * h + j;
+    const uint32_t w = tw[((INV ? NTT_NP : 0) + i) * half + j * (half / h)];
+    const uint32_t u = x[0], v = x[h];
+    if (INV) {
+      const uint32_t t = nmul(v, w, p, P.mu[i]);
+      const uint32_t s = u + t;
+      x[0] = s >= p ? s - p : s;
+      x[h] = u >= t ? u - t : u + p - t;
+    } else {
+      const uint32_t s = u + v;
+      x[0] = s >= p ? s - p : s;
+      x[h] = nmul(u >= v ? u - v : u + p - v, w, p, P.mu[i]);
+    }
+  }
+}
+
+// C^[i][r][c][f] = sum_q A^[i][r][q][f] B^[i][q][c][f] mod p_i; AB holds the R*Q entries of A, then the Q*NC of B
+__global__ void k_ntt_pointwise(const uint32_t* __restrict__ AB, uint32_t* __restrict__ Cf, int64_t N, int R, int Q,
+                                int NC, NttPrimes P) {
+  const int nab = R * Q + Q * NC, nc = R * NC;
+  const int64_t total = (int64_t)NTT_NP * nc * N;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = g % N;
+    const int e = (int)((g / N) % nc);
+    const int i = (int)(g / (N * nc));
+    const int r = e / NC, c = e % NC;
+    const uint32_t* base = AB + (int64_t)i * nab * N;
+    uint64_t acc = 0;  // Q <= 16 reduced products: below 2^36
+    for (int q = 0; q < Q; ++q)
+      acc += nmul(base[(int64_t)(r * Q + q) * N + f], base[(int64_t)(R * Q + q * NC + c) * N + f], P.p[i], P.mu[i]);
+    Cf[((int64_t)i * nc + e) * N + f] = (uint32_t)(acc % P.p[i]);
+  }
+}
+
+struct Garner {
+  NttPrimes P;
+  uint32_t ninv[NTT_NP];  // N^-1 mod p_i
+  uint32_t inv1_2;        // p1^-1 mod p2
+  uint32_t inv12_3;       // (p1 p2)^-1 mod p3
+  uint32_t p12_3;         // p1 p2 mod p3
+  uint32_t p1_f, p12_f;   // p1 and p1 p2 mod the field prime
+};
+
+// C[e][t - k0] = the product's coefficient t mod the field prime, for k0 <= t < k0 + len
+__global__ void k_ntt_crt(const uint32_t* __restrict__ Cf, int64_t N, int nc, uint32_t* __restrict__ C, int64_t sc,
+                          int64_t k0, int64_t len, Garner G, Field F) {
+  const int64_t total = (int64_t)nc * len;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = g % len;
+    const int e = (int)(g / len);
+    uint32_t r[NTT_NP];
+#pragma unroll
+    for (int i = 0; i < NTT_NP; ++i)
+      r[i] = nmul(Cf[((int64_t)i * nc + e) * N + k0 + t], G.ninv[i], G.P.p[i], G.P.mu[i]);
+    const uint32_t p1 = G.P.p[0], p2 = G.P.p[1], p3 = G.P.p[2];
+    // x = r1 + p1 t1 + p1 p2 t2 with 0 <= t1 < p2, 0 <= t2 < p3
+    const uint32_t r1m2 = r[0] % p2;
+    const uint32_t t1 = nmul(r[1] >= r1m2 ? r[1] - r1m2 : r[1] + p2 - r1m2, G.inv1_2, p2, G.P.mu[1]);
+    const uint64_t x12 = (uint64_t)r[0] + (uint64_t)p1 * t1;  // < p1 p2 < 2^62
+    const uint32_t x12m3 = (uint32_t)(x12 % p3);
+    const uint32_t t2 = nmul(r[2] >= x12m3 ? r[2] - x12m3 : r[2] + p3 - x12m3, G.inv12_3, p3, G.P.mu[2]);
+    const uint64_t lo = (uint64_t)mod_u64(x12, F.p, F.mu) + mod_u64((uint64_t)G.p12_f * t2, F.p, F.mu);
+    C[(int64_t)e * sc + t] = (uint32_t)(lo >= F.p ? lo - F.p : lo);
+  }
+}
+
+static uint32_t host_pow(uint64_t b, uint64_t e, uint32_t p) {
+  uint64_t r = 1;
+  b %= p;
+  while (e) {
+    if (e & 1) r = r * b % p;
+    b = b * b % p;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+// process-wide: the smallest la and lb at which a product goes through the NTT (0: never)
+static std::atomic<int64_t> g_ntt_min{1024};
+
+static int ntt_grid(int64_t work) { return (int)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 8192)); }
+
+// The NTT form of polymul; returns false (nothing enqueued) when the coefficient bound exceeds the
+// three primes' product or the length exceeds the primes' roots of unity.
+static bool polymul_ntt(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B, int64_t sb, int64_t lb,
+                        uint32_t* C, int64_t sc, int64_t k0, int64_t len, int R, int Q, int NC, const Field& F,
+                        hipStream_t st) {
+  const long double bound = (long double)Q * (long double)std::min(la, lb) * (long double)(F.p - 1) * (long double)(F.p - 1);
+  const long double prod = (long double)NTT_PRIME[0] * NTT_PRIME[1] * NTT_PRIME[2];
+  if (!(bound < prod * 0.999L)) return false;
+  // cyclic length: covers k0 + len, and full coefficients at index >= N land below k0
+  const int64_t need = std::max<int64_t>(k0 + len, la + lb - 1 - k0);
+  int64_t N = 2;
+  while (N < need) N *= 2;
+  if (N > ((int64_t)1 << 25)) return false;
+  NttPrimes P;
+  uint32_t roots[2 * NTT_NP];
+  Garner G;
+  for (int i = 0; i < NTT_NP; ++i) {
+    P.p[i] = NTT_PRIME[i];
+    P.mu[i] = UINT64_MAX / NTT_PRIME[i];
+    const uint32_t w = host_pow(NTT_GEN[i], (NTT_PRIME[i] - 1) / (uint64_t)N, NTT_PRIME[i]);
+    if (host_pow(w, N / 2, NTT_PRIME[i]) != NTT_PRIME[i] - 1) fail(FFX_EDEVICE, "NTT root of unity check failed");
+    roots[i] = w;
+    roots[NTT_NP + i] = host_pow(w, NTT_PRIME[i] - 2, NTT_PRIME[i]);
+    G.ninv[i] = host_pow((uint64_t)N % NTT_PRIME[i], NTT_PRIME[i] - 2, NTT_PRIME[i]);
+  }
+  G.P = P;
+  const uint64_t p1 = NTT_PRIME[0], p2 = NTT_PRIME[1], p3 = NTT_PRIME[2];
+  G.inv1_2 = host_pow(p1 % p2, p2 - 2, (uint32_t)p2);
+  G.p12_3 = (uint32_t)((p1 * p2) % p3);
+  G.inv12_3 = host_pow(G.p12_3, p3 - 2, (uint32_t)p3);
+  G.p1_f = (uint32_t)(p1 % F.p);
+  G.p12_f = (uint32_t)((unsigned __int128)(p1 * p2) % F.p);
+  const int nab = R * Q + Q * NC, nc = R * NC;
+  const int64_t half = N / 2;
+  uint32_t *AB = nullptr, *Cf = nullptr, *tw = nullptr;
+  const size_t bab = (size_t)NTT_NP * nab * N * 4, bc = (size_t)NTT_NP * nc * N * 4,
+               btw = (size_t)2 * NTT_NP * half * 4 + 2 * NTT_NP * 4;
+  if (hipMallocAsync((void**)&AB, bab, st) != hipSuccess || hipMallocAsync((void**)&Cf, bc, st) != hipSuccess ||
+      hipMallocAsync((void**)&tw, btw, st) != hipSuccess) {
+    for (void* q : {(void*)AB, (void*)Cf, (void*)tw})
+      if (q) (void)hipFreeAsync(q, st);
+    fail(FFX_ENOMEM, "NTT workspace allocation failed (length %lld)", (long long)N);
+  }
+  uint32_t* d_roots = tw + 2 * NTT_NP * half;
+  hipError_t e = hipMemcpyAsync(d_roots, roots, sizeof roots, hipMemcpyHostToDevice, st);
+  // the roots are read by the next kernel before this function returns the host array
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_ntt_twiddles, dim3(ntt_grid(2 * NTT_NP * half)), dim3(256), 0, st, tw, half, d_roots, P);
+    hipLaunchKernelGGL(k_ntt_load, dim3(ntt_grid((int64_t)NTT_NP * R * Q * N)), dim3(256), 0, st, A, sa, la, R * Q, AB,
+                       N, nab, 0, P);
+    hipLaunchKernelGGL(k_ntt_load, dim3(ntt_grid((int64_t)NTT_NP * Q * NC * N)), dim3(256), 0, st, B, sb, lb, Q * NC,
+                       AB, N, nab, R * Q, P);
+    for (int64_t h = half; h >= 1; h /= 2)
+      hipLaunchKernelGGL((k_ntt_pass<false>), dim3(ntt_grid((int64_t)NTT_NP * nab * half)), dim3(256), 0, st, AB, N, h,
+                         nab, tw, P);
+    hipLaunchKernelGGL(k_ntt_pointwise, dim3(ntt_grid((int64_t)NTT_NP * nc * N)), dim3(256), 0, st, AB, Cf, N, R, Q,
+                       NC, P);
+    for (int64_t h = 1; h < N; h *= 2)
+      hipLaunchKernelGGL((k_ntt_pass<true>), dim3(ntt_grid((int64_t)NTT_NP * nc * half)), dim3(256), 0, st, Cf, N, h,
+                         nc, tw, P);
+    hipLaunchKernelGGL(k_ntt_crt, dim3(ntt_grid((int64_t)nc * len)), dim3(256), 0, st, Cf, N, nc, C, sc, k0, len, G, F);
+    e = hipGetLastError();
+    // the host array `roots` must outlive its copy
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  (void)hipFreeAsync(AB, st);
+  (void)hipFreeAsync(Cf, st);
+  (void)hipFreeAsync(tw, st);
+  FFX_HIP(e);
+  return true;
+}
+
 static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B, int64_t sb, int64_t lb, uint32_t* C,
                     int64_t sc, int64_t k0, int64_t len, int R, int Q, int NC, const Field& F, hipStream_t st) {
   if (len <= 0) return;
+  const int64_t nt = g_ntt_min.load();
+  if (nt > 0 && la >= nt && lb >= nt && polymul_ntt(A, sa, la, B, sb, lb, C, sc, k0, len, R, Q, NC, F, st)) return;
   const int64_t tiles4 = (len + PM_OUT - 1) / PM_OUT;
   if (tiles4 * R * NC >= 2048) {  // enough four-per-lane tiles to fill the GPU
     dim3 grid4((unsigned)tiles4, (unsigned)(R * NC));
@@ -689,3 +919,10 @@ void sequence_rank(uint32_t p, int s, int64_t L, const void* S, ffx_dtype dt, in
 }
 
 }  // namespace ffx
+
+extern "C" ffx_status ffx_set_ntt_threshold(int64_t min_length) {
+  return ffx::guard([&] {
+    if (min_length < 0) ffx::fail(FFX_EINVAL, "NTT threshold %lld < 0", (long long)min_length);
+    ffx::g_ntt_min.store(min_length);
+  });
+}

@@ -34,7 +34,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("acc", ctypes.c_int32), ("selector", ctypes.c_int32),
                 ("fixed_format", ctypes.c_int32), ("split_pm1", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("build_transpose", ctypes.c_int32), ("tile_entries", ctypes.c_int32),
-                ("compact_x", ctypes.c_int32), ("model_path", ctypes.c_char_p), ("reorder", ctypes.c_int32)]
+                ("compact_x", ctypes.c_int32), ("model_path", ctypes.c_char_p), ("reorder", ctypes.c_int32),
+                ("col_sorted", ctypes.c_int32)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -45,12 +46,25 @@ class MatrixInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("stream_bytes", ctypes.c_int64),
                 ("has_transpose", ctypes.c_int32), ("value_bytes", ctypes.c_int32),
                 ("format_blocks", ctypes.c_int64 * NUM_FORMATS), ("reordered", ctypes.c_int32),
-                ("bandwidth_input", ctypes.c_int64), ("bandwidth_stored", ctypes.c_int64)]
+                ("bandwidth_input", ctypes.c_int64), ("bandwidth_stored", ctypes.c_int64),
+                ("sg_groups", ctypes.c_int64), ("sg_stream_bytes", ctypes.c_int64)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("n_val", ctypes.c_int64),
+                ("n_margins", ctypes.c_int32), ("margins", ctypes.c_void_p)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("train_loss", ctypes.c_double), ("val_loss", ctypes.c_double), ("margin", ctypes.c_float),
+                ("val_cost", ctypes.c_double), ("val_cost_stream", ctypes.c_double),
+                ("val_cost_heuristic", ctypes.c_double), ("steps", ctypes.c_int32)]
 
 
 class BatchParams(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("max_chunk", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("xcd", ctypes.c_int32), ("compact_x", ctypes.c_int32)]
 
 
 _lib = None
@@ -125,6 +139,18 @@ _SIGS = {
                                           ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "ffx_matrix_block_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "ffx_selector_label": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(BuildOpts),
+                                          ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "ffx_train_opts_default": (None, [ctypes.c_void_p]),
+    "ffx_selector_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_char_p,
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]),
+    "ffx_gather_rate": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "ffx_set_ntt_threshold": (ctypes.c_int, [ctypes.c_int64]),
     "ffx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "ffx_last_error": (ctypes.c_char_p, []),
     "ffx_version": (ctypes.c_char_p, []),
@@ -189,7 +215,7 @@ PACKAGED_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "model
 
 
 def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=True, block_rows=4096,
-               build_transpose=False, tile_entries=0, compact_x=-1, model_path=None, reorder=False):
+               build_transpose=False, tile_entries=0, compact_x=-1, model_path=None, reorder=False, col_sorted=-1):
     o = BuildOpts()
     lib().ffx_build_opts_default(ctypes.byref(o))
     o.acc = ACC[acc]
@@ -206,6 +232,7 @@ def build_opts(acc="auto", selector="heuristic", fixed_format=None, split_pm1=Tr
         model_path = PACKAGED_MODEL  # the network trained for this GPU, shipped with the package
     o.model_path = model_path.encode() if model_path else None
     o.reorder = int(bool(reorder))
+    o.col_sorted = int(col_sorted)
     return o
 
 
@@ -418,13 +445,13 @@ def version():
 class Batch:
     """Many matrices (same modulus) with their own numbers of right-hand sides, one launch (ffx_batch)."""
 
-    def __init__(self, mats, s, wg_per_cu=0, order=0, max_chunk=8, use_graph=True):
+    def __init__(self, mats, s, wg_per_cu=0, order=0, max_chunk=8, use_graph=True, xcd=1, compact_x=-1):
         self.mats = list(mats)  # the handles must outlive the batch
         self.s = [int(v) for v in s]
         n = len(self.mats)
         hs = (ctypes.c_void_p * n)(*[m.handle.value for m in self.mats])
         ss = (ctypes.c_int32 * n)(*self.s)
-        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)))
+        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)), int(xcd), int(compact_x))
         h = ctypes.c_void_p()
         _check(lib().ffx_batch_create(n, hs, ss, ctypes.byref(p), None, ctypes.byref(h)))
         self._h = h
@@ -457,15 +484,15 @@ class Batch:
         p = BatchParams()
         _check(lib().ffx_batch_tune(self._h, X, lx, Y, ly, dt, int(reps),
                                     cache_path.encode() if cache_path else None, _stream(stream), ctypes.byref(p)))
-        return dict(wg_per_cu=p.wg_per_cu, order=p.order, max_chunk=p.max_chunk, use_graph=p.use_graph)
+        return {k: getattr(p, k) for k, _ in BatchParams._fields_}
 
     def params(self):
         p = BatchParams()
         _check(lib().ffx_batch_get_params(self._h, ctypes.byref(p)))
-        return dict(wg_per_cu=p.wg_per_cu, order=p.order, max_chunk=p.max_chunk, use_graph=p.use_graph)
+        return {k: getattr(p, k) for k, _ in BatchParams._fields_}
 
-    def set_params(self, wg_per_cu=0, order=0, max_chunk=8, use_graph=True):
-        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)))
+    def set_params(self, wg_per_cu=0, order=0, max_chunk=8, use_graph=True, xcd=1, compact_x=-1):
+        p = BatchParams(int(wg_per_cu), int(order), int(max_chunk), int(bool(use_graph)), int(xcd), int(compact_x))
         _check(lib().ffx_batch_set_params(self._h, ctypes.byref(p)))
 
     def close(self):
@@ -497,6 +524,64 @@ def block_features(nrows, ncols, rowptr, col, val, m, **opts):
     _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
                                     int(m), ctypes.byref(o), out.ctypes.data, nb.value, None))
     return out[:nb.value]
+
+
+def selector_label(nrows, ncols, rowptr, col, val, m, reps=6, seed=0, stream=None, **opts):
+    """Features, log2 microseconds per block of each format and the heuristic's formats of one training
+    window, measured by the library (ffx_selector_label): arrays (nb x 32), (nb x 6), (nb)."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    rp = rp - rp[0]
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.int64)
+    o = build_opts(**opts)
+    nb = ctypes.c_int64()
+    _check(lib().ffx_block_features(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
+                                    int(m), ctypes.byref(o), None, 0, ctypes.byref(nb)))
+    n = nb.value
+    F = np.zeros((max(1, n), NFEAT), np.float32)
+    T = np.zeros((max(1, n), NUM_FORMATS), np.float32)
+    H = np.zeros(max(1, n), np.int32)
+    _check(lib().ffx_selector_label(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
+                                    int(m), ctypes.byref(o), int(reps), int(seed) & (2**64 - 1),
+                                    _stream(stream), n, F.ctypes.data, T.ctypes.data, H.ctypes.data, None))
+    return F[:n], T[:n], H[:n]
+
+
+def selector_train(X, T, mask=None, heur=None, epochs=60, batch=512, lr=2e-3, seed=0, n_val=-1, margins=None,
+                   out_model=None, stream=None):
+    """Trains a selector in the library (ffx_selector_train) on labelled blocks: (Selector, report dict).
+    The first n_val samples (default n/10) are held out for the validation loss and the decision margin."""
+    X = np.ascontiguousarray(X, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    M = None if mask is None else np.ascontiguousarray(mask, np.float32)
+    H = None if heur is None else np.ascontiguousarray(heur, np.int32)
+    o = TrainOpts()
+    lib().ffx_train_opts_default(ctypes.byref(o))
+    o.epochs, o.batch, o.lr, o.seed, o.n_val = int(epochs), int(batch), float(lr), int(seed) & (2**64 - 1), int(n_val)
+    mg = None
+    if margins is not None:
+        mg = np.ascontiguousarray(margins, np.float32)
+        o.n_margins, o.margins = len(mg), mg.ctypes.data
+    rep = TrainReport()
+    h = ctypes.c_void_p()
+    _check(lib().ffx_selector_train(X.ctypes.data, T.ctypes.data, None if M is None else M.ctypes.data,
+                                    None if H is None else H.ctypes.data, X.shape[0], ctypes.byref(o),
+                                    out_model.encode() if out_model else None, ctypes.byref(h), ctypes.byref(rep),
+                                    _stream(stream)))
+    return Selector(handle=h), {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+
+
+def gather_rate(table_bytes, row_bytes, count, window=0, reps=5, stream=None):
+    """Random gathers per second of row_bytes-byte rows from a table_bytes table (ffx_gather_rate)."""
+    r = ctypes.c_double()
+    _check(lib().ffx_gather_rate(int(table_bytes), int(row_bytes), int(count), int(window), int(reps),
+                                 _stream(stream), ctypes.byref(r)))
+    return r.value
+
+
+def set_ntt_threshold(min_length):
+    """Smallest operand length at which order-basis products use the NTT (ffx_set_ntt_threshold)."""
+    _check(lib().ffx_set_ntt_threshold(int(min_length)))
 
 
 def sigma_basis(G, p, shift, stream=None):

@@ -401,22 +401,23 @@ def test_determinism(dev, ffx):
         assert np.array_equal(MB.spmv(tdev(xb, dev)).cpu().numpy(), want)
 
 
-def test_c2_full_size_sampled(dev, orc, ffx):
-    """The 2,000,000-row power-law matrix in the benchmark's configuration: sampled rows
-    (random ones and the longest ones) against the oracle, on both accumulators."""
+def test_c2_full_size(dev, orc, ffx):
+    """The 2,000,000-row power-law matrix in the benchmark's configuration: the whole product against
+    the oracle (a full oracle product takes well under a second), on both accumulators and both
+    selectors, with alpha and beta on one of them."""
     A = synth.c2()
     note("c2 full", A.nnz)
     x = vec(13, 1, A.ncols, A.m)
-    lens = np.diff(A.rowptr)
-    rng = np.random.default_rng(0)
-    rows = np.unique(np.concatenate([rng.choice(A.nrows, 4000, replace=False), np.argsort(lens)[-200:],
-                                     np.arange(10), np.arange(A.nrows - 10, A.nrows)]))
-    want = orc.spmv(subrows(A, rows), x)
+    want = orc.spmv(A, x)
     for acc, sel in [("int64", "learned"), ("int64", "heuristic"), ("fp64", "heuristic")]:
         M = ffx.from_synth(A, acc=acc, selector=sel)  # learned: the packaged model, as the benchmark runs
         got = M.spmv(tdev(x, dev)).cpu().numpy()
-        assert np.array_equal(got[rows], want), (acc, sel)
-        assert got.min() >= 0 and got.max() < A.m
+        assert np.array_equal(got, want), (acc, sel)
+        if sel == "learned":
+            y0 = vec(13, 2, A.nrows, A.m)
+            y = tdev(y0, dev)
+            M.spmv(tdev(x, dev), alpha=A.m - 1, beta=12345, y=y)
+            assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, A.m - 1, 12345, y0))
         M.close()
 
 
@@ -667,3 +668,94 @@ def test_stencil_full_size_sampled(dev, orc, ffx):
         assert np.array_equal(got[rows], want), reorder
         assert got.min() >= 0 and got.max() < A.m
         M.close()
+
+
+# ------------------------------------------------------- column-sorted groups --
+def sg_cases():
+    rng = np.random.default_rng(5)
+    # many empty rows: the 16,384-row cap of a group cuts the groups, not the entry count
+    n = 70_000
+    rows = np.sort(rng.choice(n, 900, replace=False))
+    lens = np.zeros(n, np.int64)
+    lens[rows] = rng.integers(1, 300, size=rows.size)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    col = rng.integers(0, 150_000, size=rp[-1]).astype(np.int32)
+    val = rng.integers(-(2**40), 2**40, size=rp[-1])
+    sparse = synth.Csr(n, 150_000, rp, col, val, m=65536)
+    return {"plain": synth.c1(n=9000), "powerlaw": synth.c2(n=150_000), "sparse_rows": sparse,
+            "stencil": synth.stencil(width=300, height=200, shuffle=True), "mod2": synth.c3(n=5000, ndead=50, m=2)}
+
+
+@pytest.mark.parametrize("case", ["plain", "powerlaw", "sparse_rows", "stencil", "mod2"])
+@pytest.mark.parametrize("compact,reorder", [(-1, False), (0, False), (1, True), (0, True)])
+def test_col_sorted_groups(dev, orc, ffx, case, compact, reorder):
+    """y = alpha*A*x + beta*y on the column-sorted row groups (entries sorted by column inside groups of
+    rows, row sums in LDS) against the oracle, for both dtypes, with and without the 16-bit x copy,
+    on reordered handles (y through the row map), with +-1 split on and off, and the same results as
+    the tile kernels of the same handle's A X with one column."""
+    A = sg_cases()[case]
+    if reorder and A.nrows != A.ncols:
+        pytest.skip("reordering needs a square matrix")
+    note("col_sorted", case, compact, reorder)
+    for split in (True, False):
+        M = ffx.from_synth(A, col_sorted=1, compact_x=compact, reorder=reorder, split_pm1=split)
+        inf = M.info()
+        assert inf["sg_groups"] >= 1
+        x = vec(41, 1, A.ncols, A.m)
+        y0 = vec(41, 2, A.nrows, A.m)
+        for dt in (torch.int32, torch.int64):
+            got = M.spmv(tdev(x, dev, dt)).cpu().numpy()
+            assert np.array_equal(got, orc.spmv(A, x)), (dt, split)
+            y = tdev(y0, dev, dt)
+            M.spmv(tdev(x, dev, dt), alpha=A.m - 1, beta=3 % A.m, y=y)
+            assert np.array_equal(y.cpu().numpy(), orc.spmv(A, x, A.m - 1, 3 % A.m, y0)), (dt, split)
+            # the tile path of the same handle (one column through the multi-vector entry point)
+            Y = M.spmm(tdev(x.reshape(-1, 1), dev, dt)).cpu().numpy().reshape(-1)
+            assert np.array_equal(Y, got)
+        M.close()
+
+
+def test_col_sorted_auto_and_off(dev, orc, ffx):
+    """col_sorted = -1 builds the groups only for large matrices (4 Mi entries and 256 Ki columns),
+    never for m > 65536 or a floating accumulator; 0 never."""
+    A = synth.c2(n=400_000)
+    for opts, want in [({}, A.nnz >= 2**22), ({"col_sorted": 0}, False), ({"col_sorted": 1}, True),
+                       ({"col_sorted": 1, "acc": "fp64"}, False)]:
+        M = ffx.from_synth(A, **opts)
+        assert (M.info()["sg_groups"] > 0) == want, opts
+        x = vec(42, 1, A.ncols, A.m)
+        assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x)), opts
+        M.close()
+    B = synth.c3(n=3000, ndead=20)
+    M = ffx.from_synth(B, col_sorted=1)
+    assert M.info()["sg_groups"] == 0
+    M.close()
+
+
+@pytest.mark.parametrize("m", [65536, 3, 65521])
+def test_col_sorted_bound_edges(dev, orc, ffx, m):
+    """Rows of up to 5,000 entries of value m-1 against x = m-1 (the largest terms, (m-1)^2 < 2^32 each,
+    summed in 64-bit LDS counters), empty rows, and a row whose columns run across the boundary of two
+    65,536-column panels (the panel bases of the chunks)."""
+    n, ncols = 300, 140_000
+    rng = np.random.default_rng(m)
+    rows = []
+    for i in range(n):
+        if i % 7 == 0:
+            rows.append(np.zeros(0, np.int32))
+            continue
+        c = rng.choice(ncols, 5000, replace=False)
+        if i == 1:
+            c = np.concatenate([c[:4990], np.arange(65531, 65541)])
+        rows.append(np.unique(c).astype(np.int32))
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum([len(r) for r in rows], out=rp[1:])
+    col = np.concatenate(rows).astype(np.int32)
+    A = synth.Csr(n, ncols, rp, col, np.full(len(col), m - 1, np.int64), m=m)
+    M = ffx.from_synth(A, col_sorted=1)
+    x = np.full(ncols, m - 1, np.int64)
+    assert np.array_equal(M.spmv(tdev(x, dev)).cpu().numpy(), orc.spmv(A, x))
+    x = vec(43, 1, ncols, m)
+    assert np.array_equal(M.spmv(tdev(x, dev, torch.int64)).cpu().numpy(), orc.spmv(A, x))
+    M.close()

@@ -40,6 +40,29 @@ def test_sigma_basis_matches_oracle(dev, m, n, sig, shift_kind, p):
     assert np.array_equal(M.cpu().numpy().astype(np.int64), Mo)
 
 
+@pytest.mark.parametrize("threshold", [1, 40, 0])
+@pytest.mark.parametrize("m,n,sig,shift_kind,p", [
+    (16, 8, 300, "gen", M31), (16, 8, 257, "zero", 65521), (6, 3, 200, "rand", 3), (16, 1, 130, "rand", M31)])
+def test_sigma_basis_ntt_products(dev, threshold, m, n, sig, shift_kind, p):
+    """The polynomial-matrix products through the NTT over three primes with a CRT (the paper's DFT
+    multiplication) at every level of the recursion (threshold 1), at the larger levels only (40), or
+    none (0, schoolbook): the basis is the oracle's M-Basis bit for bit either way."""
+    from paper_1004_3719_amd import sigma_basis
+    from paper_1004_3719_amd.ffx import set_ntt_threshold
+    G = synth.vector(m * 1000 + n * 10 + sig, 9, m * n * sig, 0, p - 1).reshape(m, n, sig)
+    shift = {"zero": [0] * m, "gen": [0] * (m // 2) + [1] * (m - m // 2),
+             "rand": list(synth.vector(sig, 10, m, 0, 5))}[shift_kind]
+    print("[case] sigma basis ntt", threshold, m, n, sig, shift_kind, p, flush=True)
+    set_ntt_threshold(threshold)
+    try:
+        M, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    finally:
+        set_ntt_threshold(1024)
+    Mo, do = osig.mbasis(G, sig, shift, p)
+    assert d == do
+    assert np.array_equal(M.cpu().numpy().astype(np.int64), Mo)
+
+
 def test_sigma_basis_rejects(dev):
     from paper_1004_3719_amd import sigma_basis
     G = torch.zeros((4, 2, 8), dtype=torch.int32, device=dev)
@@ -123,7 +146,8 @@ def test_c3_rank_full_size(dev):
 
 
 @pytest.mark.parametrize("p", [M31, 65521])
-def test_sigma_basis_large_order(dev, p):
+@pytest.mark.parametrize("ntt", [1024, 0])
+def test_sigma_basis_large_order(dev, p, ntt):
     """Order 3,000 (several levels of 1,024-coefficient product tiles): M G = 0 mod x^3000 at sampled
     coefficients computed here from the definition, every row within its degree bound, and the
     degrees rising by n per order in all (G of full rank)."""
@@ -131,8 +155,13 @@ def test_sigma_basis_large_order(dev, p):
     m, n, sig = 16, 8, 3000
     G = synth.vector(p, 9, m * n * sig, 0, p - 1).reshape(m, n, sig)
     shift = [0] * 8 + [1] * 8
-    print("[case] sigma basis large", p, flush=True)
-    Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    print("[case] sigma basis large", p, ntt, flush=True)
+    from paper_1004_3719_amd.ffx import set_ntt_threshold
+    set_ntt_threshold(ntt)  # 1024: the top products through the NTT; 0: all schoolbook
+    try:
+        Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    finally:
+        set_ntt_threshold(1024)
     M = Mt.cpu().numpy().astype(np.int64)
     assert sum(d) - sum(shift) == n * sig
     for i in range(m):
@@ -161,7 +190,8 @@ def _coeff_mod(M, G, k, p):
 
 
 @pytest.mark.parametrize("p", [M31, 65521])
-def test_sigma_basis_order_40k(dev, p):
+@pytest.mark.parametrize("ntt", [1024, 0])
+def test_sigma_basis_order_40k(dev, p, ntt):
     """Order 40,000, where the top products of the recursion run on the four-coefficients-per-lane
     tiles: the order condition at sampled coefficients (computed here from the definition), the
     degree bounds and the total degree increase."""
@@ -169,8 +199,13 @@ def test_sigma_basis_order_40k(dev, p):
     m, n, sig = 16, 8, 40_000
     G = synth.vector(p + 1, 10, m * n * sig, 0, p - 1).reshape(m, n, sig)
     shift = [0] * 8 + [1] * 8
-    print("[case] sigma basis 40k", p, flush=True)
-    Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    print("[case] sigma basis 40k", p, ntt, flush=True)
+    from paper_1004_3719_amd.ffx import set_ntt_threshold
+    set_ntt_threshold(ntt)  # 1024: the top products through the NTT; 0: the four-per-lane schoolbook tiles
+    try:
+        Mt, d = sigma_basis(torch.from_numpy(G.astype(np.int32)).to(dev), p, shift)
+    finally:
+        set_ntt_threshold(1024)
     M = Mt.cpu().numpy().astype(np.int64)
     assert sum(d) - sum(shift) == n * sig
     top = max(d) + 1

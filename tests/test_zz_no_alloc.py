@@ -47,7 +47,8 @@ def _cases():
 
 
 @pytest.mark.parametrize("dt", [torch.int32, torch.int64])
-@pytest.mark.parametrize("opts", [{}, {"reorder": True}, {"compact_x": 0, "reorder": True}])
+@pytest.mark.parametrize("opts", [{}, {"reorder": True}, {"compact_x": 0, "reorder": True}, {"col_sorted": 1},
+                                  {"col_sorted": 1, "reorder": True}])
 def test_noalloc_matches_spmv(dev, dt, opts):
     from paper_1004_3719_amd import Matrix
     orc = oracle.get()
