@@ -125,24 +125,30 @@ def copy_bandwidth(mib=512, reps=5):
 
 def pmc_summary(fetch_csv, write_csv, mib, out_path, command):
     """HBM bytes per product launch from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB
-    per dispatch), each scaled by what the same counter reads for the calibration copy."""
+    per dispatch), each scaled by what the same counter reads for the calibration copy. The product
+    is the 16-bit x copy plus its main kernel (the column-sorted groups, else the tiles)."""
     import csv
     res = {}
+    main = None
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         with open(path) as f:
             rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
         copy = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
         copy = [v for v in copy if v > 0.5 * mib * 1024]
-        tiles = [float(r["Counter_Value"]) for r in rows if "k_tiles" in r["Kernel_Name"]]
+        for name in ("k_sg", "k_tiles"):
+            prod = [float(r["Counter_Value"]) for r in rows if name + "<" in r["Kernel_Name"]]
+            if prod:
+                main = name
+                break
         u16 = [float(r["Counter_Value"]) for r in rows if "k_to_u16" in r["Kernel_Name"]]
-        if not copy or not tiles:
+        if not copy or not prod:
             raise SystemExit("%s: no calibration copy or product dispatch in %s" % (counter, path))
         scale = mib * 1024 / float(np.mean(copy))
         res[counter] = {"copy_kib": round(float(np.mean(copy)), 1), "scale": round(scale, 4),
-                        "k_tiles_kib": round(float(np.mean(tiles)), 1),
-                        "k_to_u16_kib": round(float(np.mean(u16)), 1) if u16 else 0.0, "dispatches": len(tiles)}
-    bpl = sum((v["k_tiles_kib"] + v["k_to_u16_kib"]) * 1024 * v["scale"] for v in res.values())
-    out = {"kernel": "k_to_u16 + k_tiles, one product of the 2,000,000-row power-law matrix",
+                        "main_kib": round(float(np.mean(prod)), 1),
+                        "k_to_u16_kib": round(float(np.mean(u16)), 1) if u16 else 0.0, "dispatches": len(prod)}
+    bpl = sum((v["main_kib"] + v["k_to_u16_kib"]) * 1024 * v["scale"] for v in res.values())
+    out = {"kernel": "k_to_u16 + %s, one product of the 2,000,000-row power-law matrix" % main,
            "kernel_hash": kernel_hash(), "counters": res, "bytes_per_launch": int(round(bpl)), "command": command}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
@@ -833,7 +839,7 @@ def bench_selector(args):
             Xs.append(F)
             Ts.append(T)
             Hs.append(H)
-            if k % 50 == 49:
+            if k % 20 == 19:
                 log("labels: %d matrices, %d blocks, %.0fs" % (k + 1, sum(len(f) for f in Xs), time.time() - t0))
         X = np.concatenate(Xs)
         T = np.concatenate(Ts)
@@ -879,6 +885,9 @@ def bench_selector(args):
         if nev % 10 == 0:
             log("held-out %d: heuristic %.1f us, learned %.1f us so far" % (nev, tot["heuristic_us"],
                                                                               tot["learned_us"]))
+    if not nev:  # training only (--eval-mats 0)
+        print(json.dumps({"trained": rep, "validation_block_cost_vs_best": block_cost, "model": model}), flush=True)
+        return
     tot_h, tot_l = tot["heuristic_us"], tot["learned_us"]
     fixed = {f: tot["fixed_%s_us" % f] for f in FORMATS}
     best_fixed = min(fixed, key=fixed.get)

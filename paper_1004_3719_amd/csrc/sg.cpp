@@ -57,7 +57,9 @@ void encode_group(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, bool split,
           w[t] = PAD_WORD;
         }
       }
-      P.ent.insert(P.ent.end(), w, w + SG_CHUNK);
+      // entry 64k + l at word 4l + k: one 16-byte load per lane
+      for (int l = 0; l < 64; ++l)
+        for (int k = 0; k < 4; ++k) P.ent.push_back(w[64 * k + l]);
     }
     q = q1;
   }

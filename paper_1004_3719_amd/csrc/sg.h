@@ -19,7 +19,9 @@
 // 65,536 columns (the last chunk of a panel is padded), and stores its panel
 // base in `cbase` and the offset of its general values in `choff`. Entry e of
 // a chunk is gathered by lane e mod 64 of the e/64-th gather instruction, so
-// one instruction covers 64 consecutive sorted columns.
+// one instruction covers 64 consecutive sorted columns; the chunk stores entry
+// 64k + l at word 4l + k, so lane l reads its four entries with one 16-byte
+// load. General values are stored in entry order.
 #pragma once
 
 #include "ffx_impl.h"

@@ -34,9 +34,13 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
     for (int u = 0; u < U; ++u) {
       const uint32_t ch = ch0 + u * NW;
       const bool ok = ch < g.nchunks;
-      const uint32_t* p = G.ent + (size_t)(g.c0 + (ok ? ch : 0)) * SG_CHUNK + lane;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) ww[u][k] = ok ? __builtin_nontemporal_load(p + WAVE * k) : PAD_WORD;
+      typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+      const u32x4_t q = ok ? __builtin_nontemporal_load((const u32x4_t*)(G.ent + (size_t)(g.c0 + ch) * SG_CHUNK) + lane)
+                           : (u32x4_t)(PAD_WORD);
+      ww[u][0] = q.x;
+      ww[u][1] = q.y;
+      ww[u][2] = q.z;
+      ww[u][3] = q.w;
       vv[u] = ok ? G.choff[g.c0 + ch] : 0u;
       cc[u] = ok ? G.cbase[g.c0 + ch] : 0u;
     }

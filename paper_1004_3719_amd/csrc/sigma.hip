@@ -215,10 +215,13 @@ __global__ void __launch_bounds__(PM_TILE) k_polymul4(const uint32_t* __restrict
 
 // One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
 // with shifted degrees d (in/out, device). M: m x m entries of sm >= sg + 1 coefficients.
+// LEAF_NT lanes: the residual takes 8 lanes per entry and the basis update 4 lanes per entry, each
+// over a share of the inner index or of the coefficients.
+constexpr int LEAF_NT = 1024;
 template <bool MERS>
-__global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldg, int m, int n,
-                                                     int sg, int32_t* __restrict__ d, uint32_t* __restrict__ M,
-                                                     int64_t sm, Field F) {
+__global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldg, int m, int n,
+                                                         int sg, int32_t* __restrict__ d, uint32_t* __restrict__ M,
+                                                         int64_t sm, Field F) {
   constexpr int LC = SB_LEAF + 1;
   __shared__ uint32_t Ms[2][SB_MAXM][SB_MAXM][LC];
   __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF + 1];  // padded: the 8 columns fall in different banks
@@ -229,11 +232,11 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   __shared__ int order[SB_MAXM];                // rows by (shifted degree, index)
   const int tid = threadIdx.x;
-  for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += 256) {
+  for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += LEAF_NT) {
     int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
     Gs[r][c][k] = (r < m && c < n && k < sg) ? G[(int64_t)(r * n + c) * ldg + k] : 0u;
   }
-  for (int i = tid; i < SB_MAXM * SB_MAXM * LC; i += 256) {  // both buffers: coefficients above the degree stay 0
+  for (int i = tid; i < SB_MAXM * SB_MAXM * LC; i += LEAF_NT) {  // both buffers: coefficients above the degree stay 0
     int r = i / (SB_MAXM * LC), c = (i / LC) % SB_MAXM, k = i % LC;
     Ms[0][r][c][k] = (r == c && k == 0) ? 1u : 0u;
     Ms[1][r][c][k] = 0u;
@@ -245,23 +248,25 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
   __syncthreads();
   int cur = 0;
   for (int k = 0; k < sg; ++k) {
-    // residual [x^k](M G): two lanes per entry, each over half of the inner index
+    // residual [x^k](M G): eight lanes per entry, each over an eighth of the inner index; the
+    // eight reduced parts meet through shuffles, each sum of two residues reduced at once
     {
-      const int o = tid >> 1, half = tid & 1;
+      const int o = tid >> 3, part8 = tid & 7;
       Acc96<MERS> acc;
       const int r = o / SB_MAXN, c = o % SB_MAXN;
       if (r < m && c < n) {
-        for (int q = half; q < m; q += 2) {
+        for (int q = part8; q < m; q += 8) {
 #pragma unroll 8
           for (int j = 0; j <= k; ++j) acc.add((uint64_t)Ms[cur][r][q][j] * Gs[q][c][k - j]);
         }
       }
-      uint32_t part = (r < m && c < n) ? acc.reduce(F) : 0u;
-      uint32_t other = __shfl_xor(part, 1);
-      if (half == 0 && r < m && c < n) {
-        uint32_t v = part + other;
-        Dl[r][c] = v >= F.p ? v - F.p : v;
+      uint32_t v = (r < m && c < n) ? acc.reduce(F) : 0u;
+#pragma unroll
+      for (int sh = 1; sh < 8; sh <<= 1) {
+        const uint32_t t = v + (uint32_t)__shfl_xor((int)v, sh);  // below 2p < 2^32
+        v = t >= F.p ? t - F.p : t;
       }
+      if (part8 == 0 && r < m && c < n) Dl[r][c] = v;
     }
     __syncthreads();
     // Echelon form of the residual, rows by increasing shifted degree (ties by
@@ -282,7 +287,7 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
       order[pos] = tid;
       piv[tid] = 0;
     }
-    for (int idx = tid; idx < m * m; idx += 256) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
+    for (int idx = tid; idx < m * m; idx += LEAF_NT) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
     __syncthreads();
     // Fraction free: row_j <- pv row_j - x_j row_i is the oracle's
     // row_j - (x_j / pv) row_i times pv. The rows of M (and so of the residual)
@@ -304,7 +309,7 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
       const uint32_t pv = rowv[first];
       used |= 1u << first;
       const int w = n + m, later = m - oi - 1;
-      for (int task = tid; task < later * w; task += 256) {
+      for (int task = tid; task < later * w; task += LEAF_NT) {
         const int pos = oi + 1 + task / w, col = task % w;
         if (col < n && ((used >> col) & 1u)) continue;  // this pivot's column and the earlier ones
         const int j = order[pos];
@@ -326,18 +331,19 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
       }
       __syncthreads();
     }
-    // M <- diag(x^piv) T M: one entry (i, c) per lane, T's row in registers.
-    // M has degree <= k before order k, so only coefficients 0..k+1 change
-    // (the buffers hold zeros above).
+    // M <- diag(x^piv) T M: four lanes per entry (i, c), each over every fourth coefficient, T's row
+    // in registers. M has degree <= k before order k, so only coefficients 0..k+1 change (the
+    // buffers hold zeros above).
     const int nxt = cur ^ 1;
     {
-      const int i = tid / SB_MAXM, c = tid % SB_MAXM;
+      const int e = tid >> 2, j0 = tid & 3;
+      const int i = e / SB_MAXM, c = e % SB_MAXM;
       if (i < m && c < m) {
         uint32_t t[SB_MAXM];
 #pragma unroll
         for (int q = 0; q < SB_MAXM; ++q) t[q] = q < m ? T[i][q] : 0u;
         const int sh = piv[i];
-        for (int j = 0; j <= k + 1 && j < LC; ++j) {
+        for (int j = j0; j <= k + 1 && j < LC; j += 4) {
           const int js = j - sh;
           uint32_t out = 0;
           if (js >= 0 && js <= k) {
@@ -379,7 +385,7 @@ __global__ void __launch_bounds__(256) k_mbasis_leaf(const uint32_t* __restrict_
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < m * m * (sg + 1); idx += 256) {
+  for (int idx = tid; idx < m * m * (sg + 1); idx += LEAF_NT) {
     const int i = idx / (m * (sg + 1)), c = (idx / (sg + 1)) % m, j = idx % (sg + 1);
     M[(int64_t)(i * m + c) * sm + j] = fmul(Ms[cur][i][c][j], sc[i], F);
   }
@@ -680,11 +686,11 @@ static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, s
   if (sigma <= SB_LEAF) {
     FFX_HIP(hipMemcpyAsync(X.d_dev, d.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, X.st));
     if (X.F.mersenne)
-      hipLaunchKernelGGL((k_mbasis_leaf<true>), dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm,
-                         X.F);
+      hipLaunchKernelGGL((k_mbasis_leaf<true>), dim3(1), dim3(LEAF_NT), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M,
+                         sm, X.F);
     else
-      hipLaunchKernelGGL((k_mbasis_leaf<false>), dim3(1), dim3(256), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M, sm,
-                         X.F);
+      hipLaunchKernelGGL((k_mbasis_leaf<false>), dim3(1), dim3(LEAF_NT), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M,
+                         sm, X.F);
     FFX_HIP(hipGetLastError());
     FFX_HIP(hipMemcpyAsync(d.data(), X.d_dev, m * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
     FFX_HIP(hipStreamSynchronize(X.st));

@@ -266,3 +266,24 @@ def test_trained_model_gain(dev):
           % (tot["heuristic_us"], tot["learned_us"], best), flush=True)
     assert tot["learned_us"] < tot["heuristic_us"]
     assert tot["learned_us"] <= 1.03 * best
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained model in the package")
+@pytest.mark.parametrize("k", [1808, 1840, 1875, 1926])
+def test_held_out_whole_matrices(dev, k):
+    """Whole held-out selection matrices (three of the smallest, 50k rows each, one row-length family
+    each, and one of about 3.9 M rows): the products built with the learned and the heuristic formats
+    (tiles) and with the column-sorted groups all equal the oracle's."""
+    from paper_1004_3719_amd import Matrix
+    sp, _ = synth.c5_spec(k)
+    A = synth.rows(sp)
+    A.m = synth.M_C5
+    print("[case] held-out whole", k, A.nrows, A.nnz, flush=True)
+    xh = synth.vector(k, 8, A.ncols, 0, A.m - 1)
+    x = torch.from_numpy(xh.astype(np.int32)).to(dev)
+    want = oracle.get_all_cores().spmv(A, xh)
+    for opts in ({"selector": "learned", "model_path": MODEL, "col_sorted": 0}, {"col_sorted": 0},
+                 {"col_sorted": 1}):
+        M = Matrix.from_synth(A, **opts)
+        assert np.array_equal(M.spmv(x).cpu().numpy(), want), opts
+        M.close()
