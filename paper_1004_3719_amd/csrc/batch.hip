@@ -454,10 +454,11 @@ static void cache_store(const char* path, const std::string& key, const ffx_batc
         lines.push_back(line);
       }
   }
-  char buf[512];
-  snprintf(buf, sizeof buf, "  \"%s\": {\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d, \"xcd\": %d, \"compact_x\": %d}",
-           key.c_str(), p.wg_per_cu, p.order, p.max_chunk, p.xcd, p.compact_x);
-  lines.push_back(buf);
+  // the key can be long (one term per matrix): the line is built without a fixed-size buffer
+  char buf[160];
+  snprintf(buf, sizeof buf, "{\"wg_per_cu\": %d, \"order\": %d, \"max_chunk\": %d, \"xcd\": %d, \"compact_x\": %d}",
+           p.wg_per_cu, p.order, p.max_chunk, p.xcd, p.compact_x);
+  lines.push_back("  \"" + key + "\": " + buf);
   std::ofstream f(path);
   f << "{\n";
   for (size_t i = 0; i < lines.size(); ++i) f << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");

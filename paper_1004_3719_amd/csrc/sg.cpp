@@ -45,6 +45,7 @@ void encode_group(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, bool split,
     for (size_t c = q; c < q1; c += SG_CHUNK) {
       P.choff.push_back((uint32_t)P.val.size());
       P.cbase.push_back(panel << 16);
+      uint16_t vv[SG_CHUNK];
       for (int t = 0; t < SG_CHUNK; ++t) {
         if (c + t < q1) {
           const uint64_t kk = key[c + t];
@@ -52,14 +53,19 @@ void encode_group(const RCsr& A, int64_t r0, int64_t r1, uint32_t m, bool split,
           const uint32_t v = (uint32_t)(kk & 0xFFFFu);
           const uint32_t tag = sg_tag(v, m, split);
           w[t] = (tag << TAG_SHIFT) | (lr << SG_ROW_SHIFT) | (col & SG_COL_MASK);
-          if (tag == TAG_GEN) P.val.push_back((uint16_t)v);
+          vv[t] = (uint16_t)v;
         } else {
           w[t] = PAD_WORD;
         }
       }
-      // entry 64k + l at word 4l + k: one 16-byte load per lane
+      // entry 64k + l at word 4l + k: one 16-byte load per lane; the general values in the same
+      // lane-major order, so a lane's values are consecutive
       for (int l = 0; l < 64; ++l)
-        for (int k = 0; k < 4; ++k) P.ent.push_back(w[64 * k + l]);
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t word = w[64 * k + l];
+          P.ent.push_back(word);
+          if ((word >> TAG_SHIFT) == TAG_GEN) P.val.push_back(vv[64 * k + l]);
+        }
     }
     q = q1;
   }

@@ -21,7 +21,9 @@
 // a chunk is gathered by lane e mod 64 of the e/64-th gather instruction, so
 // one instruction covers 64 consecutive sorted columns; the chunk stores entry
 // 64k + l at word 4l + k, so lane l reads its four entries with one 16-byte
-// load. General values are stored in entry order.
+// load. General values follow the same lane-major order, so a lane's (at most
+// four) values are consecutive and one 12-byte load fetches them: each chunk
+// costs a lane one entry load, one value load and four gathers.
 #pragma once
 
 #include "ffx_impl.h"

@@ -49,19 +49,33 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
   for (uint32_t ch0 = wave; ch0 < g.nchunks; ch0 += NW * U) {
     uint32_t wn[U][4], von[U], cbn[U];
     load_words(ch0 + NW * U, wn, von, cbn);
-    // values (compacted: the general entries before this one in the chunk give its index) and x
+    // values: a lane's general values are consecutive, after those of the lanes below it (four
+    // ballots give their count), and one 12-byte load brings all of them; then x
     uint32_t v[U][4], xv[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t idx = vo[u];
+      uint32_t idx = vo[u], ng = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool gen = (w[u][k] >> TAG_SHIFT) == TAG_GEN;
+        idx += sg_lanes_below(__ballot(gen));
+        ng += gen ? 1u : 0u;
+      }
+      uint32_t q0 = 0, q1 = 0, q2 = 0;
+      if (ng) {
+        typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
+        const u32x3_t q = __builtin_nontemporal_load((const u32x3_t*)((const uint32_t*)G.val + (idx >> 1)));
+        q0 = q.x;
+        q1 = q.y;
+        q2 = q.z;
+      }
+      uint32_t j = idx & 1u;  // position of the lane's first value in the 12 bytes (16-bit units)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint32_t tag = w[u][k] >> TAG_SHIFT;
-        const bool gen = tag == TAG_GEN;
-        const uint64_t b = __ballot(gen);
-        const uint32_t my = idx + sg_lanes_below(b);
-        idx += (uint32_t)__popcll(b);
-        v[u][k] = gen ? (uint32_t)__builtin_nontemporal_load(G.val + my) : 0u;
+        const uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
+        v[u][k] = tag == TAG_GEN ? (d >> ((j & 1u) * 16)) & 0xFFFFu : 0u;
+        j += tag == TAG_GEN ? 1u : 0u;
         xv[u][k] = tag != TAG_PAD ? (uint32_t)x[cb[u] + (w[u][k] & SG_COL_MASK)] : 0u;
       }
     }

@@ -92,8 +92,10 @@ def test_batch_full_size(dev):
 
 
 def test_batch_tune_and_cache(dev, tmp_path):
+    """The tuner's choice is stored in and read back from its JSON cache; 48 matrices give a cache key
+    of well over 512 characters."""
     from paper_1004_3719_amd import Batch, Matrix
-    mats = small_batch(12, nmax=20_000)
+    mats = small_batch(48, nmax=8_000)
     Ms = [Matrix.from_synth(A) for A in mats]
     B = Batch(Ms, [A.s for A in mats])
     Xs = [torch.from_numpy(synth.c4_rhs(k, A).astype(np.int64)).to(dev) for k, A in enumerate(mats)]
@@ -103,6 +105,7 @@ def test_batch_tune_and_cache(dev, tmp_path):
     assert best["max_chunk"] in (4, 8) and 1 <= best["wg_per_cu"] <= 8
     assert best["xcd"] in (0, 1) and best["compact_x"] in (0, 1)
     B2 = Batch(Ms, [A.s for A in mats])
+    assert len(open(cache).read()) > 600
     assert B2.tune(Xs, Ys, cache_path=cache) == best  # read back from the cache
     B2.spmm(Xs, Ys)
     orc = oracle.get()
