@@ -337,7 +337,9 @@ def bench_accumulators(args):
     stream = torch.cuda.current_stream()
     table, ms_main, khash = {}, None, kernel_hash()
     for acc in ACC_NAMES:
-        M = Matrix.from_synth(A, acc=acc, selector=args.selector, model_path=args.model)
+        # the tiles for every accumulator (the column-sorted groups are an int64-only path; their
+        # one-vector time is the "int64_col_sorted" row)
+        M = Matrix.from_synth(A, acc=acc, selector=args.selector, model_path=args.model, col_sorted=0)
         info = M.info()
         row = {"reduce_every": info["reduce_every"]}
         for s_ in (1, 8, 16):
@@ -363,6 +365,22 @@ def bench_accumulators(args):
         table[acc] = row
         log("acc %s: %s" % (acc, row))
         M.close()
+    M = Matrix.from_synth(A, col_sorted=1)
+    x1 = torch.from_numpy(synth.vector(synth.SEED0 + 1, 31, A.ncols, 0, m - 1).astype(np.int32)).to(dev)
+    y1 = torch.empty(A.nrows, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        M.spmv(x1, y=y1)
+    torch.cuda.synchronize()
+    ev = event_pairs(args.steps)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        M.spmv(x1, y=y1)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+    table["int64_col_sorted"] = {"s1_ms": round(k_ms, 5), "s1_Gnnz_vec_per_s": round(A.nnz / (k_ms * 1e-3) / 1e9, 1)}
+    log("int64, column-sorted groups: %s" % table["int64_col_sorted"])
+    M.close()
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (ms_main * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -453,9 +471,9 @@ def bench_reorder(args):
     x = torch.from_numpy(x_np.astype(np.int32)).to(dev)
     stream = torch.cuda.current_stream()
     res, y_main = {}, None
-    for reorder in (False, True):
+    for reorder, cs in ((False, 0), (True, 0), (False, 1), (True, 1)):
         t0 = time.time()
-        M = Matrix.from_synth(A, reorder=reorder, selector=args.selector, model_path=args.model)
+        M = Matrix.from_synth(A, reorder=reorder, selector=args.selector, model_path=args.model, col_sorted=cs)
         build_s = time.time() - t0
         info = M.info()
         y = torch.empty(A.nrows, dtype=torch.int32, device=dev)
@@ -477,20 +495,22 @@ def bench_reorder(args):
         M.power(10, x)
         b_.record(stream)
         torch.cuda.synchronize()
-        key = "reordered" if reorder else "caller_order"
+        key = ("reordered" if reorder else "caller_order") + ("_col_sorted" if cs else "_tiles")
         res[key] = {"build_s": round(build_s, 2), "bandwidth": info["bandwidth_stored"], "wall_ms": round(wall_ms, 5),
                     "event_ms": round(ev_ms, 5), "power10_ms_per_product": round(a_.elapsed_time(b_) / 10, 5),
-                    "formats": info["format_blocks"]}
+                    "formats": info["format_blocks"], "col_sorted_groups": info["sg_groups"]}
         log("%s: %s" % (key, res[key]))
-        if reorder:
-            y_main, ms, kernel_ms = y, wall_ms, ev_ms
+        if reorder and cs:
+            y_main, ms, kernel_ms, sg_info = y, wall_ms, ev_ms, info
         M.close()
+    info = sg_info
     b_alg = algorithmic_bytes(A, m)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
     main_kernel = "k_sg (column-sorted groups)" if info["sg_groups"] else "k_tiles"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_permute_to_u16 (x gathered into the stored order) + k_tiles (y written through the row map)",
+                "kernel": "k_permute_to_u16 (x gathered into the stored order) + %s (y written through the row map)"
+                          % main_kernel,
                 "kernel_ms": round(kernel_ms, 5), "algorithmic_bytes": int(b_alg)}
     cpu = None
     if not args.no_cpu_baseline:
@@ -509,7 +529,7 @@ def bench_reorder(args):
                "seconds": round(t_cpu, 2), "gpu_result_bit_exact": exact}
     config = {"workload": "shuffled 9-point stencil SpMV mod 32749: 2048 x 1024 grid, 2,097,152 rows, nodes numbered "
                           "at random, 60% +-1, x int32; stored in reverse Cuthill-McKee order",
-              "n": A.nrows, "nnz": A.nnz, "m": m, "selector": args.selector}
+              "n": A.nrows, "nnz": A.nnz, "m": m, "selector": args.selector, "col_sorted_groups": info["sg_groups"]}
     line(A.nnz / (ms * 1e-3), ms, args, "int64", config, roofline, cpu, {"orders": res})
 
 
@@ -752,13 +772,16 @@ def bench_batch(args):
         for M, X, Y in zip(Ms, Xs, Ys):
             M.spmm(X, Y=Y)
 
-    t_per = ev_time(per_matrix, args.steps)
-    # the same launches without host gaps: each matrix timed alone on the GPU, summed
-    t_per_gpu = 0.0
-    for M, X, Y in zip(Ms, Xs, Ys):
-        t_per_gpu += ev_time(lambda: M.spmm(X, Y=Y), 3)
     B = Batch(Ms, S)
-    t_default = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
+    if args.skip_compare:  # the batch alone (profiling runs): no per-matrix launches, tuner from its cache
+        t_per = t_per_gpu = t_default = float("nan")
+    else:
+        t_per = ev_time(per_matrix, args.steps)
+        # the same launches without host gaps: each matrix timed alone on the GPU, summed
+        t_per_gpu = 0.0
+        for M, X, Y in zip(Ms, Xs, Ys):
+            t_per_gpu += ev_time(lambda: M.spmm(X, Y=Y), 3)
+        t_default = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
     best = B.tune(Xs, Ys, reps=3, cache_path=args.tune_cache or None)
     t_batch = ev_time(lambda: B.spmm(Xs, Ys), args.steps)
     cpu = None
@@ -933,6 +956,7 @@ def main():
     ap.add_argument("--seq-length", type=int, default=0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--tune-cache", default="", help="JSON cache of the batch tuner (read if it holds this batch)")
+    ap.add_argument("--skip-compare", action="store_true", help="batch: skip the per-matrix comparison launches")
     ap.add_argument("--train-mats", type=int, default=600)
     ap.add_argument("--train-blocks", type=int, default=16)
     ap.add_argument("--eval-mats", type=int, default=200)

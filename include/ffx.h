@@ -430,6 +430,22 @@ ffx_status ffx_selector_train(const float* X, const float* T, const float* mask,
                               const ffx_train_opts* opts, const char* out_model, ffx_selector* out,
                               ffx_train_report* report, void* stream);
 
+/* Install-time tuning of the tile size (Section 2.4, "Heuristic format
+ * chooser": the parameters of the formats are tuned for the machine). The
+ * matrix (host CSR as to ffx_matrix_create_csr, the rest of the build from
+ * opts) is built with each candidate tile_entries (512, 1024, 2048, 4096),
+ * and the product with s vectors (s in [1, 16]; int32 residues drawn from
+ * seed) is timed on the tiles with HIP events, the median of `reps` launches
+ * (1..10000) after two warm-ups. *best_tile_entries receives the fastest;
+ * us_out (host, 4 floats, or NULL) the median microseconds of each candidate.
+ * The rows per wave are fixed by the formats (one row per lane in SELL slices,
+ * 64/s rows per wave in the multi-vector tiles), so the tile size is the
+ * shape left to tune. Waits for the stream. */
+ffx_status ffx_tune_tile_entries(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                                 const void* vals, ffx_dtype val_type, uint32_t m, const ffx_build_opts* opts,
+                                 int32_t s, int32_t reps, uint64_t seed, void* stream, int32_t* best_tile_entries,
+                                 float* us_out);
+
 /* Order basis (sigma-basis) of an m x n power series over the prime field
  * F_p, p < 2^31 (block Wiedemann step 2, Section 3.2; PM-Basis of Giorgi,
  * Jeannerod and Villard 2003 with one-order-at-a-time M-Basis below 32 orders):

@@ -431,6 +431,14 @@ static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, i
           fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
         }
     }
+    // one vector on a handle with column-sorted groups: every product on the groups (through a
+    // 16-bit copy of the current vector when the handle takes one); they write y with unit stride
+    const bool sg = s == 1 && M.sg.ngroups && ldw == 1;
+    uint16_t* x16 = nullptr;
+    if (sg && M.compact_x && n > 0 && hipMallocAsync((void**)&x16, (size_t)n * 2, st) != hipSuccess) {
+      for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+      fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", (size_t)n * 2);
+    }
     const void* cur = V;
     int64_t ldc = ldv;
     hipError_t e = hipSuccess;
@@ -438,13 +446,21 @@ static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, i
       bool last = it == k - 1;
       void* dst = last ? W : tmp[it & 1];
       int64_t ldd = last ? ldw : s;
-      DevMat dm = E.dm;
-      if (last) dm.rowmap = rowmap;
-      e = launch_tiles(ak, dm, E.max_tile_entries, dtype, cur, ldc, dst, ldd, s, 1, 0, st);
+      if (sg && (x16 || ldc == 1)) {
+        SgMat g = M.sg.dm;
+        g.rowmap = last ? rowmap : nullptr;
+        if (x16) e = launch_compact_x(dtype, cur, ldc, x16, n, st);
+        if (e == hipSuccess) e = launch_sg(g, dtype, cur, x16, dst, 1, 0, st);
+      } else {
+        DevMat dm = E.dm;
+        if (last) dm.rowmap = rowmap;
+        e = launch_tiles(ak, dm, E.max_tile_entries, dtype, cur, ldc, dst, ldd, s, 1, 0, st);
+      }
       cur = dst;
       ldc = ldd;
     }
     for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+    if (x16) (void)hipFreeAsync(x16, st);
     FFX_HIP(e);
   }
 }

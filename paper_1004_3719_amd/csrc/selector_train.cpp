@@ -326,3 +326,73 @@ ffx_status ffx_selector_train(const float* X, const float* T, const float* mask,
 }
 
 }  // extern "C"
+
+extern "C" ffx_status ffx_tune_tile_entries(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,
+                                            const void* vals, ffx_dtype val_type, uint32_t m,
+                                            const ffx_build_opts* opts, int32_t s, int32_t reps, uint64_t seed,
+                                            void* stream, int32_t* best_tile_entries, float* us_out) {
+  return guard([&] {
+    if (!best_tile_entries) fail(FFX_EINVAL, "best_tile_entries is NULL");
+    if (s < 1 || s > MAX_S) fail(FFX_EINVAL, "s = %d outside [1, %d]", s, MAX_S);
+    if (reps < 1 || reps > 10000) fail(FFX_EINVAL, "reps = %d outside [1, 10000]", reps);
+    if (m < 2 || m > 2147483647u) fail(FFX_EINVAL, "modulus %u", m);
+    hipStream_t st = (hipStream_t)stream;
+    ffx_build_opts o;
+    ffx_build_opts_default(&o);
+    if (opts) {
+      if (opts->size < sizeof(uint32_t) || opts->size > sizeof o) fail(FFX_EINVAL, "ffx_build_opts.size = %u", opts->size);
+      std::memcpy(&o, opts, opts->size);
+      o.size = sizeof o;
+    }
+    o.col_sorted = 0;  // the tiles are what is tuned
+    // X: ncols x s random residues (int32), Y: nrows x s
+    std::vector<int32_t> xh((size_t)std::max<int64_t>(ncols, 1) * s);
+    uint64_t r = seed;
+    for (auto& v : xh) v = (int32_t)(splitmix(r) % m);
+    DevBuf dx(xh.size() * 4), dy((size_t)std::max<int64_t>(nrows, 1) * s * 4);
+    FFX_HIP(hipMemcpyAsync(dx.p, xh.data(), xh.size() * 4, hipMemcpyHostToDevice, st));
+    static const int32_t cand[4] = {512, 1024, 2048, 4096};
+    double best = INFINITY;
+    int32_t pick = cand[2];
+    for (int c = 0; c < 4; ++c) {
+      o.tile_entries = cand[c];
+      MatrixGuard g;
+      check(ffx_matrix_create_csr(nrows, ncols, rowptr, colidx, vals, val_type, m, &o, st, &g.M));
+      auto run = [&]() {
+        return s == 1 ? ffx_spmv(g.M, 1, dx.p, 0, dy.p, FFX_I32, st)
+                      : ffx_spmm(g.M, s, 1, dx.p, s, 0, dy.p, s, FFX_I32, st);
+      };
+      for (int w = 0; w < 2; ++w) check(run());
+      hipEvent_t e0, e1;
+      FFX_HIP(hipEventCreate(&e0));
+      if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        fail(FFX_EDEVICE, "hipEventCreate failed");
+      }
+      std::vector<double> us;
+      hipError_t e = hipSuccess;
+      ffx_status fs = FFX_OK;
+      for (int k = 0; k < reps && e == hipSuccess && fs == FFX_OK; ++k) {
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) fs = run();
+        if (e == hipSuccess && fs == FFX_OK) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && fs == FFX_OK) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess && fs == FFX_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        us.push_back(ms * 1000.0);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      check(fs);
+      FFX_HIP(e);
+      std::sort(us.begin(), us.end());
+      const double med = us[us.size() / 2];
+      if (us_out) us_out[c] = (float)med;
+      if (med < best) {
+        best = med;
+        pick = cand[c];
+      }
+    }
+    *best_tile_entries = pick;
+  });
+}

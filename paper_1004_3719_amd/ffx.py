@@ -151,6 +151,11 @@ _SIGS = {
     "ffx_gather_rate": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "ffx_set_ntt_threshold": (ctypes.c_int, [ctypes.c_int64]),
+    "ffx_tune_tile_entries": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32,
+                                             ctypes.POINTER(BuildOpts), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.c_void_p]),
     "ffx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "ffx_last_error": (ctypes.c_char_p, []),
     "ffx_version": (ctypes.c_char_p, []),
@@ -582,6 +587,21 @@ def gather_rate(table_bytes, row_bytes, count, window=0, reps=5, stream=None):
 def set_ntt_threshold(min_length):
     """Smallest operand length at which order-basis products use the NTT (ffx_set_ntt_threshold)."""
     _check(lib().ffx_set_ntt_threshold(int(min_length)))
+
+
+def tune_tile_entries(nrows, ncols, rowptr, col, val, m, s=1, reps=5, seed=0, stream=None, **opts):
+    """(best tile_entries, {candidate: median microseconds}) of the s-vector product (ffx_tune_tile_entries)."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    rp = rp - rp[0]
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.int64)
+    o = build_opts(**opts)
+    best = ctypes.c_int32()
+    us = np.zeros(4, np.float32)
+    _check(lib().ffx_tune_tile_entries(int(nrows), int(ncols), rp.ctypes.data, c.ctypes.data, v.ctypes.data, FFX_I64,
+                                       int(m), ctypes.byref(o), int(s), int(reps), int(seed) & (2**64 - 1),
+                                       _stream(stream), ctypes.byref(best), us.ctypes.data))
+    return best.value, {k: float(t) for k, t in zip((512, 1024, 2048, 4096), us)}
 
 
 def sigma_basis(G, p, shift, stream=None):

@@ -130,3 +130,24 @@ def test_batch_float_accumulators(dev, acc, m):
     orc = oracle.get()
     for k, A in enumerate(mats):
         assert np.array_equal(Ys[k].cpu().numpy(), orc.spmm(A, rhs[k])), (k, A.params)
+
+
+@pytest.mark.parametrize("s", [1, 8])
+def test_tune_tile_entries(dev, s):
+    """The build-time tile tuner times each candidate tile size on the matrix itself; the matrix
+    built with its choice (STREAM tiles throughout) still equals the oracle."""
+    from paper_1004_3719_amd import Matrix
+    from paper_1004_3719_amd.ffx import tune_tile_entries
+    A = synth.c4_matrix(5, nmax=40_000)
+    print("[case] tune tile entries", s, A.nrows, A.nnz, flush=True)
+    best, us = tune_tile_entries(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, s=s, reps=3,
+                                 fixed_format="stream")
+    assert best in (512, 1024, 2048, 4096)
+    assert all(t > 0 for t in us.values()) and us[best] == min(us.values())
+    M = Matrix.from_synth(A, fixed_format="stream", tile_entries=best)
+    X = synth.vector(synth.SEED0 + 3, 9000 + s, A.ncols * s, 0, A.m - 1).reshape(A.ncols, s)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.int64)).to(dev)
+    Y = torch.zeros((A.nrows, s), dtype=torch.int64, device=dev)
+    M.spmm(Xd, Y=Y)
+    torch.cuda.synchronize()
+    assert np.array_equal(Y.cpu().numpy(), oracle.get().spmm(A, X))

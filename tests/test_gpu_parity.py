@@ -242,6 +242,27 @@ def test_power(dev, orc, ffx, k):
     assert np.array_equal(W, orc.power(A, k, V))
 
 
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("compact", [1, 0])
+def test_power_one_vector_col_sorted(dev, orc, ffx, reorder, compact):
+    """A^k x for one vector on a handle with column-sorted groups (every product on the groups, the
+    intermediate ones in the stored order, the last through the row map of a reordered handle), both
+    dtypes, with and without the 16-bit copy; a strided x takes the tiles for its first product."""
+    A = synth.stencil(width=120, height=90, shuffle=True, m=65521)
+    note("power col_sorted", reorder, compact)
+    M = ffx.from_synth(A, reorder=reorder, col_sorted=1, compact_x=compact)
+    x = vec(33, 1, A.nrows, A.m)
+    for k in (1, 2, 5):
+        for dt in (torch.int32, torch.int64):
+            got = M.power(k, tdev(x, dev, dt)).cpu().numpy()
+            assert np.array_equal(got, orc.power(A, k, x)), (k, dt)
+    wide = torch.zeros((A.nrows, 3), dtype=torch.int64, device=dev)
+    wide[:, 1] = tdev(x, dev, torch.int64)
+    got = M.power(3, wide[:, 1:2]).cpu().numpy().reshape(-1)
+    assert np.array_equal(got, orc.power(A, 3, x))
+    M.close()
+
+
 @pytest.mark.parametrize("m,s,dt", [(2**31 - 1, 8, torch.int64), (65521, 3, torch.int32), (32749, 1, torch.int32)])
 def test_sequence_full_length(dev, orc, ffx, m, s, dt):
     """The whole sequence i = 0 .. 2n/s + 2 at n = 2,000 (10 dead columns), and A^L V."""
