@@ -213,6 +213,123 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
   }
 }
 
+// Two SELL slices by one workgroup for s = 8, the common block width: a wave
+// takes 32 rows of a slice, two lanes per row, and a lane keeps four of the
+// row's eight components. Each gather is then one 16-byte load (half a row of
+// W_i) and a wave instruction covers 32 rows, against 8 rows and 4-byte loads
+// in the (row, component) layout. The entry words are read once per wave with
+// lane = row (as they are stored), which also yields each row's value index
+// by ballots; the words and the index then move to the lanes of their row by
+// shuffles. With PROJ the wave writes its rows of U and W_{i+1} to LDS and
+// lane p = 8a + c sums U[row][a] W_{i+1}[row][c] over the wave's 32 rows.
+// X, Y and U have leading dimension 8.
+// GU: 4-column groups loaded together.
+template <class AR, bool PROJ, int GU>
+__device__ inline void sell_slice_h8(const DevMat& A, const Tile& T, uint32_t slice, uint32_t half,
+                                     const int32_t* __restrict__ X, int32_t* __restrict__ Y,
+                                     const int32_t* __restrict__ U, uint32_t* wl /* LDS [2][32][8] of this wave */,
+                                     uint64_t* red /* LDS [TILE_THREADS] */) {
+  const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const uint32_t rr = lane >> 1, h = lane & 1u;
+  const uint32_t src = half * 32u + rr;  // lane holding this row's words (lane = row of the slice)
+  const bool live = slice < T.ne;
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < slice && live; ++k) off += A.swidth[T.aux + k];
+  const uint32_t groups = live ? A.swidth[T.aux + slice] : 0u;
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
+  const uint32_t* choff = A.choff + T.c0 + off;
+  const uint32_t slot = slice * WAVE + src;
+  const uint32_t prow = !live ? 0xFFFFFFFFu : (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
+  const bool pok = prow < A.nrows;
+  // U of the projection does not depend on the product: its load goes out first
+  u32x4 uq = {0u, 0u, 0u, 0u};
+  if (PROJ && pok) uq = *(const u32x4*)(U + (int64_t)prow * 8 + 4 * h);
+  LaneAcc<AR, 4> acc;
+  acc.init(A);
+  const uint32_t nd = tile_nd(T.kind), rows_in_tile = tile_rows(T.kind);
+  for (uint32_t d = 0; d < nd && live; ++d) {
+    const int64_t col = (int64_t)prow + A.boffs[T.boff + d];
+    const bool ok = pok && col >= 0 && col < (int64_t)A.ncols;
+    const uint32_t v = ok ? ldval<typename AR::ValT>(A.bval, T.b0 + d * rows_in_tile + slot) : 0u;
+    u32x4 x = {0u, 0u, 0u, 0u};
+    if (ok) x = *(const u32x4*)(X + col * 8 + 4 * h);
+    acc.a[0] += AR::mul(v, x.x);
+    acc.a[1] += AR::mul(v, x.y);
+    acc.a[2] += AR::mul(v, x.z);
+    acc.a[3] += AR::mul(v, x.w);
+    acc.tick(A);
+  }
+  for (uint32_t g0 = 0; g0 < groups; g0 += GU) {
+    uint32_t w[GU][WIDE], idx[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      u32x4 q = g0 + u < groups ? __builtin_nontemporal_load((const u32x4*)(ent + (size_t)(g0 + u) * SELL_GROUP))
+                                : (u32x4)(PAD_WORD);
+      w[u][0] = q.x;
+      w[u][1] = q.y;
+      w[u][2] = q.z;
+      w[u][3] = q.w;
+      idx[u] = value_index4(w[u], g0 + u < groups ? choff[g0 + u] : 0u);
+    }
+    // to the lanes of the row: words first, so the gathers can leave before the values
+    uint32_t wr[GU][WIDE];
+    u32x4 xv[GU][WIDE];
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        wr[u][k] = (uint32_t)__shfl((int)w[u][k], (int)src);
+        xv[u][k] = (u32x4){0u, 0u, 0u, 0u};
+        if ((wr[u][k] >> TAG_SHIFT) != TAG_PAD && pok)
+          xv[u][k] = *(const u32x4*)(X + (int64_t)(wr[u][k] & COL_MASK) * 8 + 4 * h);
+      }
+    uint32_t v[GU][WIDE];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const uint32_t ir = (uint32_t)__shfl((int)idx[u], (int)src);
+      if (pok) {
+        load_values_at<AR>(A, wr[u], ir, v[u]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < WIDE; ++k) v[u][k] = 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        const uint32_t tag = wr[u][k] >> TAG_SHIFT;
+        acc.a[0] += term<AR>(tag, v[u][k], xv[u][k].x, A.m);
+        acc.a[1] += term<AR>(tag, v[u][k], xv[u][k].y, A.m);
+        acc.a[2] += term<AR>(tag, v[u][k], xv[u][k].z, A.m);
+        acc.a[3] += term<AR>(tag, v[u][k], xv[u][k].w, A.m);
+        acc.tick(A);
+      }
+  }
+  u32x4 r;
+  r.x = AR::reduce(acc.a[0], A);
+  r.y = AR::reduce(acc.a[1], A);
+  r.z = AR::reduce(acc.a[2], A);
+  r.w = AR::reduce(acc.a[3], A);
+  if (pok) *(u32x4*)(Y + (int64_t)prow * 8 + 4 * h) = r;
+  if constexpr (PROJ) {
+    // this wave's rows of W_{i+1} (wl[0]) and U (wl[1]); rows outside the matrix hold zeros
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    *(u32x4*)(wl + rr * 8 + 4 * h) = pok ? r : z;
+    *(u32x4*)(wl + 256 + rr * 8 + 4 * h) = pok ? uq : z;
+    __syncthreads();
+    const uint32_t a = lane >> 3, c = lane & 7u;
+    LaneAcc<AR, 1> pj;
+    pj.init(A);
+#pragma unroll 8
+    for (uint32_t q = 0; q < 32; ++q) {
+      pj.a[0] += AR::mul(wl[256 + q * 8 + a], wl[q * 8 + c]);
+      pj.tick(A);
+    }
+    red[wave * WAVE + lane] = (uint64_t)AR::reduce(pj.a[0], A);
+  }
+}
+
 // ------------------------------------------------------------- kernels -----
 // The blocks W_i and U live in workspace as int32 (n x s, ld = s), whatever the
 // caller's element type: residues are below 2^31, and the 32-bit copies halve
@@ -249,9 +366,16 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_first(DevMat A, SeqArgs q)
 // turns the sums of iteration i-1 into S_{i-1}.
 constexpr uint32_t NMID = 64;
 
+// groups per load round of the s = 8 step (sell_slice_h8)
+constexpr int SEQ_H8_GROUPS = 1;
+
 // ONLY_SELL: the matrix has SELL tiles only, and the kernel is built without
 // the STREAM/LONG path, whose registers would otherwise set the occupancy.
-template <class AR, typename Ts, int S, bool ONLY_SELL>
+// H8 > 0 (s = 8): two workgroups per tile, each taking two SELL slices (two
+// waves per slice, sell_slice_h8 loading H8 groups together); workgroup
+// 2t + h writes the partial of slot 4t + 2h and zeros into slot 4t + 2h + 1,
+// so the partial buffers keep four slots per tile either way.
+template <class AR, typename Ts, int S, bool ONLY_SELL, int H8>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int64_t i = *q.base + j;
@@ -259,8 +383,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
   const int s = q.s;
   const int64_t ss = (int64_t)s * s;
   const uint32_t nparts = A.ntiles * SELL_SLICES;
-  if (blockIdx.x >= nparts) {
-    const uint32_t r = blockIdx.x - nparts;
+  const uint32_t nwork = H8 ? A.ntiles * 2 : nparts;
+  if (blockIdx.x >= nwork) {
+    const uint32_t r = blockIdx.x - nwork;
     uint32_t pair;
     if (r < NMID) {  // stage 1 for iteration i
       uint64_t t = fold_partials(A, q.part[i & 1], r, NMID, nparts, s, (uint64_t*)lds, &pair);
@@ -276,17 +401,40 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
   const Tw* Win = q.W[i & 1];
   Tw* Wout = q.W[(i + 1) & 1];
   const int64_t ldin = s;
-  const uint32_t t = blockIdx.x / SELL_SLICES, slice = blockIdx.x % SELL_SLICES;
+  const uint32_t t = H8 ? blockIdx.x / 2 : blockIdx.x / SELL_SLICES;
+  const uint32_t slice = H8 ? 2 * (blockIdx.x % 2) : blockIdx.x % SELL_SLICES;  // H8: first of the two slices
   const Tile T = A.tiles[t];
-  uint64_t* out = q.part[(i + 1) & 1] + (int64_t)blockIdx.x * ss;
+  uint64_t* out = q.part[(i + 1) & 1] + (int64_t)(t * SELL_SLICES + slice) * ss;
   if (tile_kind(T.kind) == TK_SELL) {
-    if (last) sell_slice_rc<AR, Tw, S, false>(A, T, slice, Win, ldin, Wout, s, s, nullptr, 0, nullptr, nullptr);
-    else sell_slice_rc<AR, Tw, S, true>(A, T, slice, Win, ldin, Wout, s, s, q.U, s, out, (uint64_t*)lds);
+    if constexpr (H8 > 0) {
+      const uint32_t wave = threadIdx.x / WAVE;
+      uint32_t* wl = (uint32_t*)lds + wave * 512;
+      uint64_t* red = (uint64_t*)(lds + 4 * 512 * sizeof(uint32_t));
+      if (last) {
+        sell_slice_h8<AR, false, H8>(A, T, slice + (wave >> 1), wave & 1u, Win, Wout, nullptr, nullptr, nullptr);
+        return;
+      }
+      sell_slice_h8<AR, true, H8>(A, T, slice + (wave >> 1), wave & 1u, Win, Wout, q.U, wl, red);
+      __syncthreads();
+      if (threadIdx.x < WAVE) {
+        uint64_t sum = 0;  // four residues
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sum += red[w * WAVE + threadIdx.x];
+        out[threadIdx.x] = sum;
+        out[ss + threadIdx.x] = 0;
+      }
+    } else {
+      if (last) sell_slice_rc<AR, Tw, S, false>(A, T, slice, Win, ldin, Wout, s, s, nullptr, 0, nullptr, nullptr);
+      else sell_slice_rc<AR, Tw, S, true>(A, T, slice, Win, ldin, Wout, s, s, q.U, s, out, (uint64_t*)lds);
+    }
     return;
   }
   if constexpr (!ONLY_SELL) {
-    if (slice != 0) {  // idle slice of a STREAM/LONG tile: an empty partial
-      if (!last && threadIdx.x < ss) out[threadIdx.x] = 0;
+    if (slice != 0) {  // idle slices of a STREAM/LONG tile: empty partials
+      if (!last && threadIdx.x < ss) {
+        out[threadIdx.x] = 0;
+        if (H8) out[ss + threadIdx.x] = 0;
+      }
       return;
     }
     if (tile_kind(T.kind) == TK_LONG) long_tile<AR, Tw, Tw, S, 1>(A, T, Win, ldin, Wout, s, s, 1, 0, lds);
@@ -295,6 +443,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
     // the projection reads back only rows this workgroup wrote: a workgroup barrier orders them
     __syncthreads();
     tile_projection<AR, Tw>(A, T, q.U, s, Wout, s, s, (uint64_t*)lds, out);
+    if (H8 && threadIdx.x < ss) out[ss + threadIdx.x] = 0;
   }
 }
 
@@ -319,14 +468,21 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   const int S = s <= 2 ? 2 : s <= 4 ? 4 : s <= 8 ? 8 : 16;  // the step always runs the multi-vector tiles
   size_t lds = tiles_lds_bytes<AR>(mte, S);
   if (lds < SELL_SLICES * TILE_THREADS * sizeof(uint64_t)) lds = SELL_SLICES * TILE_THREADS * sizeof(uint64_t);
+  // s = 8: half-row lanes (sell_slice_h8), whose LDS holds 4 waves x 2 KB of rows and the 256 sums
+  const bool h8 = s == 8;
+  const size_t h8_lds = 4 * 512 * sizeof(uint32_t) + TILE_THREADS * sizeof(uint64_t);
+  if (h8 && lds < h8_lds) lds = h8_lds;
   int64_t* base = const_cast<int64_t*>(q.base);
   auto step = [&](hipStream_t st, int32_t j) {
-    dim3 g(A.ntiles * SELL_SLICES + NMID + 1), b(TILE_THREADS);
+    dim3 g((h8 ? A.ntiles * 2 : A.ntiles * SELL_SLICES) + NMID + 1), b(TILE_THREADS);
     switch (S) {
-      case 2: hipLaunchKernelGGL((k_seq_step<AR, Ts, 2, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      case 4: hipLaunchKernelGGL((k_seq_step<AR, Ts, 4, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      case 8: hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL>), g, b, lds, st, A, q, j); break;
-      default: hipLaunchKernelGGL((k_seq_step<AR, Ts, 16, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 2: hipLaunchKernelGGL((k_seq_step<AR, Ts, 2, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
+      case 4: hipLaunchKernelGGL((k_seq_step<AR, Ts, 4, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
+      case 8:
+        if (h8) hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL, SEQ_H8_GROUPS>), g, b, lds, st, A, q, j);
+        else hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL, 0>), g, b, lds, st, A, q, j);
+        break;
+      default: hipLaunchKernelGGL((k_seq_step<AR, Ts, 16, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
     }
   };
   hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, user, base, (int64_t)0, 1);

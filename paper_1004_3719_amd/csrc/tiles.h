@@ -286,19 +286,25 @@ __device__ inline void band_terms(const DevMat& A, const Tile& T, LaneAcc<AR, S>
   }
 }
 
-// Values of the four entry words w of this lane (entries 4*lane .. 4*lane+3
-// of a chunk whose value offset is vo). Values follow the entry order, so the
-// lane's general values are consecutive, after those of lower lanes (four
-// ballots): one 12-byte (16-bit values) or 16-byte load fetches them all.
-template <class AR>
-__device__ inline void load_values4(const DevMat& A, const uint32_t* w, uint32_t vo, uint32_t* v) {
-  uint32_t idx = vo, g = 0;
+// Index of the first general value of this lane's four entry words w
+// (entries 4*lane .. 4*lane+3 of a chunk whose value offset is vo). Values
+// follow the entry order, so the lane's general values are consecutive, after
+// those of lower lanes (four ballots over the wave).
+__device__ inline uint32_t value_index4(const uint32_t* w, uint32_t vo) {
+  uint32_t idx = vo;
 #pragma unroll
-  for (int k = 0; k < WIDE; ++k) {
-    bool gen = (w[k] >> TAG_SHIFT) == TAG_GEN;
-    idx += lanes_below(__ballot(gen));
-    g += gen ? 1u : 0u;
-  }
+  for (int k = 0; k < WIDE; ++k) idx += lanes_below(__ballot((w[k] >> TAG_SHIFT) == TAG_GEN));
+  return idx;
+}
+
+// The general values of four entry words w whose first value is at index idx:
+// one 12-byte (16-bit values) or 16-byte load fetches them all. Per lane: any
+// lane may load the values of any row once it holds that row's words and index.
+template <class AR>
+__device__ inline void load_values_at(const DevMat& A, const uint32_t* w, uint32_t idx, uint32_t* v) {
+  uint32_t g = 0;
+#pragma unroll
+  for (int k = 0; k < WIDE; ++k) g += (w[k] >> TAG_SHIFT) == TAG_GEN ? 1u : 0u;
   uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, j = 0;
   if constexpr (sizeof(typename AR::ValT) == 2) {
     if (g) {
@@ -330,6 +336,13 @@ __device__ inline void load_values4(const DevMat& A, const uint32_t* w, uint32_t
     v[k] = gen ? val : 0u;
     j += gen ? 1u : 0u;
   }
+}
+
+// Values of the four entry words w of this lane (entries 4*lane .. 4*lane+3
+// of a chunk whose value offset is vo).
+template <class AR>
+__device__ inline void load_values4(const DevMat& A, const uint32_t* w, uint32_t vo, uint32_t* v) {
+  load_values_at<AR>(A, w, value_index4(w, vo), v);
 }
 
 // U chunks of 256 entries, 4 words (16 bytes) per lane: the chunks of STREAM

@@ -141,10 +141,10 @@ def test_tune_tile_entries(dev, s):
     A = synth.c4_matrix(5, nmax=40_000)
     print("[case] tune tile entries", s, A.nrows, A.nnz, flush=True)
     best, us = tune_tile_entries(A.nrows, A.ncols, A.rowptr, A.col, A.val, A.m, s=s, reps=3,
-                                 fixed_format="stream")
+                                 fixed_format="STREAM")
     assert best in (512, 1024, 2048, 4096)
     assert all(t > 0 for t in us.values()) and us[best] == min(us.values())
-    M = Matrix.from_synth(A, fixed_format="stream", tile_entries=best)
+    M = Matrix.from_synth(A, fixed_format="STREAM", tile_entries=best)
     X = synth.vector(synth.SEED0 + 3, 9000 + s, A.ncols * s, 0, A.m - 1).reshape(A.ncols, s)
     Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.int64)).to(dev)
     Y = torch.zeros((A.nrows, s), dtype=torch.int64, device=dev)

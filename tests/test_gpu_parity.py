@@ -462,7 +462,7 @@ def test_compact_x_and_unroll(dev, orc, ffx, compact, acc, tile_entries):
 
 
 @pytest.mark.parametrize("fmt", ["STREAM", "SELL", "SELL_SORTED", "BAND_STREAM", "BAND_SELL_SORTED"])
-@pytest.mark.parametrize("s,m", [(2, 65521), (5, 2**31 - 1), (16, 32749)])
+@pytest.mark.parametrize("s,m", [(2, 65521), (5, 2**31 - 1), (16, 32749), (8, 65521), (8, 2**31 - 19)])
 def test_sequence_formats(dev, orc, ffx, fmt, s, m):
     """The sequence through the graph path (L >= 128) on every tile kind, with long rows and a band."""
     sp = synth.c2_spec(n=3000, kmax=600)
