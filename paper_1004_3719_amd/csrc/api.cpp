@@ -484,6 +484,8 @@ void ffx_build_opts_default(ffx_build_opts* o) {
   o->tile_entries = 0;
   o->compact_x = -1;
   o->model_path = nullptr;
+  o->reorder = 0;
+  o->col_sorted = -1;
 }
 
 ffx_status ffx_matrix_create_csr(int64_t nrows, int64_t ncols, const int64_t* rowptr, const int32_t* colidx,

@@ -32,6 +32,18 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, n), n
 
 
+def test_build_opts_defaults():
+    """ffx_build_opts_default gives the documented defaults (a C caller that only fills `size` and
+    calls it gets the same behaviour as the Python binding's defaults)."""
+    o = ffx.BuildOpts()
+    P.lib().ffx_build_opts_default(ctypes.byref(o))
+    assert o.size == ctypes.sizeof(ffx.BuildOpts)
+    assert (o.acc, o.selector, o.split_pm1, o.block_rows, o.build_transpose, o.tile_entries) == (
+        ffx.ACC["auto"], ffx.SEL["heuristic"], 1, 4096, 0, 0)
+    assert (o.compact_x, o.reorder, o.col_sorted) == (-1, 0, -1)
+    assert o.model_path is None
+
+
 def test_status_strings():
     L = P.lib()
     assert L.ffx_status_str(2) == b"FFX_EBOUND"
