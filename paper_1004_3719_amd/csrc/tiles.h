@@ -886,6 +886,12 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* _
   // EU entries of the row at a time: their gathers are all issued before the
   // first term is added (16 in flight per lane)
   constexpr int EU = S >= 16 ? 1 : 16 / S;
+  // s = S with 16-byte aligned rows of X: a row is gathered in 16-byte loads
+  // (two for s = 8 int32 instead of eight 4-byte ones), so the vector cache
+  // looks up each line once per load, not once per component
+  constexpr bool VT = sizeof(Tx) == 4 || sizeof(Tx) == 8;  // int32 or int64 rows (not a 16-bit copy)
+  constexpr int NV = VT && (S * sizeof(Tx)) % 16 == 0 ? (int)((S * sizeof(Tx)) / 16) : 0;
+  const bool vx = NV > 0 && s == S && ((uintptr_t)X & 15) == 0 && ((ldx * (int64_t)sizeof(Tx)) & 15) == 0;
   for (uint32_t k0 = kb; k0 < ke; k0 += EU) {
     uint32_t w[EU], xv[EU][S];
 #pragma unroll
@@ -893,8 +899,24 @@ __device__ inline void stream_tile_s(const DevMat& A, const Tile& T, const Tx* _
       w[e] = k0 + e < ke ? sw[k0 + e] : PAD_WORD;
       const Tx* xr = X + (int64_t)(w[e] & COL_MASK) * ldx;
       const bool live = (w[e] >> TAG_SHIFT) != TAG_PAD;
+      if (NV > 0 && vx) {
 #pragma unroll
-      for (int c = 0; c < S; ++c) xv[e][c] = (live && c < s) ? (uint32_t)xr[c] : 0u;
+        for (int j = 0; j < (NV > 0 ? NV : 1); ++j) {
+          const u32x4 q = live ? ((const u32x4*)xr)[j] : (u32x4){0u, 0u, 0u, 0u};
+          if constexpr (sizeof(Tx) == 4) {
+            xv[e][4 * j] = q.x;
+            xv[e][4 * j + 1] = q.y;
+            xv[e][4 * j + 2] = q.z;
+            xv[e][4 * j + 3] = q.w;
+          } else if constexpr (sizeof(Tx) == 8) {  // residues: the low words of two int64
+            xv[e][2 * j] = q.x;
+            xv[e][2 * j + 1] = q.z;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < S; ++c) xv[e][c] = (live && c < s) ? (uint32_t)xr[c] : 0u;
+      }
     }
 #pragma unroll
     for (int e = 0; e < EU; ++e) {

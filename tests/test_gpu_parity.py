@@ -212,9 +212,12 @@ def test_small_modulus_accumulators(dev, orc, ffx, acc, fmt):
 
 
 # ---------------------------------------------------------------- SpMM -----
-@pytest.mark.parametrize("s", [1, 2, 3, 5, 8, 13, 16])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 8, 13, 16])
 @pytest.mark.parametrize("fmt", [None, "STREAM", "SELL_SORTED", "BAND_SELL"])
 def test_spmm(dev, orc, ffx, s, fmt):
+    """Y = alpha*A*X + beta*Y with X a strided view (leading dimension s + 3), with X contiguous in both
+    dtypes (16-byte aligned rows for s = 4, 8, 16 in int32 and even s in int64, which the STREAM
+    tiles gather in 16-byte loads), and with X one element off 16-byte alignment; A^T X."""
     A = synth.c2(n=20_000)
     note("spmm", s, fmt)
     M = ffx.from_synth(A, fixed_format=fmt, build_transpose=True)
@@ -226,7 +229,13 @@ def test_spmm(dev, orc, ffx, s, fmt):
     Y0 = vec(7, s, A.nrows, A.m, s)
     Yd = tdev(Y0, dev)
     M.spmm(Xd, alpha=9, beta=4, Y=Yd)
+    want = orc.spmm(A, X)
     assert np.array_equal(Yd.cpu().numpy(), orc.spmm(A, X, 9, 4, Y0))
+    for dt in (torch.int32, torch.int64):
+        assert np.array_equal(M.spmm(tdev(X, dev, dt)).cpu().numpy(), want), dt
+        flat = torch.zeros(A.ncols * s + 1, dtype=dt, device=dev)
+        flat[1:] = tdev(X, dev, dt).reshape(-1)
+        assert np.array_equal(M.spmm(flat[1:].view(A.ncols, s)).cpu().numpy(), want), dt
     Xt = vec(8, s, A.nrows, A.m, s)
     assert np.array_equal(M.spmm_t(tdev(Xt, dev, torch.int64)).cpu().numpy(), orc.spmm_t(A, Xt))
 
