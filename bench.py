@@ -822,14 +822,30 @@ def bench_batch(args):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch (persistent)",
                 "kernel_ms": round(t_batch, 5), "algorithmic_bytes": int(b_alg)}
-    # one row gather of X per entry and column chunk (at most 8 columns): against the GPU's random
-    # gather rate of 32-byte rows (a chunk of 8 int32 columns) from a 16 MB table (a large X block)
-    nnz_chunks = sum(Ms[k].info()["nnz"] * ((S[k] + 7) // 8) for k in range(count))
-    ceil = gather_ceiling(16 * 2**20, 32, nnz_chunks)
+    # one row gather of X per entry and column chunk (at most 8 columns, 32 bytes). The ceiling adds,
+    # matrix by matrix, the time the calibration kernel takes for that many gathers of rows of the
+    # chunk's width (rounded up to a power of two) from a table of the X block's size (likewise):
+    # uniformly
+    # random for the uniform-column matrices, inside 4,096-row windows for the banded and
+    # block-diagonal ones
+    rates, t_ceil, nnz_chunks = {}, 0.0, 0
+    for k in range(count):
+        nnz_k = Ms[k].info()["nnz"]
+        chunks = (S[k] + 7) // 8
+        row_bytes = 1 << int(math.ceil(math.log2(4 * min(S[k], 8))))  # the calibration's widths: powers of 2
+        table = 1 << max(13, int(math.ceil(math.log2(max(1, Ms[k].info()["ncols"] * S[k] * 4)))))
+        window = 0 if synth.c4_params(k)["structure"] == 0 else 4096
+        key = (table, row_bytes, window)
+        if key not in rates:
+            rates[key] = gather_ceiling(table, row_bytes, 8 * 2**20, window=min(window, table // row_bytes))
+        t_ceil += nnz_k * chunks / rates[key]
+        nnz_chunks += nnz_k * chunks
+    ceil = nnz_chunks / t_ceil
     got = nnz_chunks / (t_batch * 1e-3)
     roofline["gather"] = {"achieved": round(got, 1), "ceiling": round(ceil, 1), "unit": "row gathers/s",
-                          "frac": round(got / ceil, 4),
-                          "ceiling_kernel": "ffx_gather_rate: random 32-byte rows from a 16 MiB table"}
+                          "frac": round(got / ceil, 4), "ceiling_calibrations": len(rates),
+                          "ceiling_kernel": "ffx_gather_rate per matrix: rows of the chunk's width from a table of "
+                                            "its X block's size, random (uniform columns) or in 4,096-row windows"}
     line(work / (t_batch * 1e-3), t_batch, args, "int64", config, roofline, cpu, extra)
 
 
