@@ -264,6 +264,16 @@ def bench_spmv(args, big=True):
                               "frac": round(got / ceil, 4),
                               "ceiling_kernel": "ffx_gather_rate: %d random %d-byte gathers from a %d-byte table"
                                                 % (A.nnz, row_b, A.ncols * row_b)}
+        if info["sg_groups"]:
+            # the column-sorted groups gather 64 consecutive sorted columns per instruction, which span
+            # about 64 * ncols * groups / nnz columns: against the same gathers kept inside windows of
+            # that many rows (rounded up to a power of two), walked in order as a group walks x
+            span = 64.0 * A.ncols * info["sg_groups"] / max(1, A.nnz)
+            win = 1 << max(6, int(math.ceil(math.log2(span))))
+            ceil_s = gather_ceiling(A.ncols * row_b, row_b, A.nnz, window=win)
+            roofline["gather"].update({"ceiling_sorted": round(ceil_s, 1), "frac_sorted": round(got / ceil_s, 4),
+                                       "ceiling_sorted_kernel": "ffx_gather_rate: the same gathers inside "
+                                                                "%d-row windows visited in order" % win})
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
