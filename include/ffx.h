@@ -28,8 +28,14 @@
  *    The library never frees caller memory.
  *  - Input and output vectors must not overlap. With beta = 0 the output is
  *    write-only (its previous contents are ignored).
- *  - A matrix handle is read-only after creation: products on one handle
- *    may run concurrently on different streams.
+ *  - A matrix handle's matrix is read-only after creation, and products on
+ *    one handle may be issued on different streams and from several host
+ *    threads. The handle keeps one device temporary for its row products
+ *    (the 16-bit copy of x, or x in the stored order of a reordered matrix;
+ *    allocated by the first product that needs it, freed by destroy): the
+ *    first product on a second stream synchronizes the device once, and from
+ *    then on products on different streams are ordered on that temporary by
+ *    an event (they serialize rather than overlap).
  */
 #ifndef FFX_H
 #define FFX_H

@@ -386,13 +386,34 @@ static void product(ffx_matrix M, bool trans, int s, uint32_t alpha, const void*
   const int64_t nout = trans ? M->info.ncols : M->info.nrows;
   if (row_product(*M, trans)) {
     const size_t bytes = row_scratch_bytes(*M, trans, s, dt);
-    void* scratch = nullptr;
-    if (bytes) {
-      warm_pool(st);
-      if (hipMallocAsync(&scratch, bytes, st) != hipSuccess) fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", bytes);
+    if (!bytes) {
+      FFX_HIP(row_product_in(*M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, nullptr));
+      return;
     }
-    hipError_t e = row_product_in(*M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, scratch);
-    if (scratch) (void)hipFreeAsync(scratch, st);
+    auto& C = M->scr;
+    std::lock_guard<std::mutex> lock(C.mu);
+    if (C.bytes < bytes) {  // grow: the previous temporary is freed once every product is done
+      if (C.p) {
+        FFX_HIP(hipDeviceSynchronize());
+        (void)hipFree(C.p);
+        C.p = nullptr;
+        C.bytes = 0;
+      }
+      if (hipMalloc(&C.p, bytes) != hipSuccess) fail(FFX_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+      C.bytes = bytes;
+    } else if (C.used && C.last != st) {
+      if (!C.multi) {  // the products so far recorded nothing: wait for all of them, once
+        FFX_HIP(hipDeviceSynchronize());
+        FFX_HIP(hipEventCreateWithFlags(&C.done, hipEventDisableTiming));
+        C.multi = true;
+      } else {
+        FFX_HIP(hipStreamWaitEvent(st, C.done, 0));
+      }
+    }
+    hipError_t e = row_product_in(*M, trans, s, alpha, X, ldx, beta, Y, ldy, dt, st, C.p);
+    if (e == hipSuccess && C.multi) e = hipEventRecord(C.done, st);
+    C.last = st;
+    C.used = true;
     FFX_HIP(e);
     return;
   }
@@ -537,6 +558,11 @@ ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* ou
 ffx_status ffx_matrix_destroy(ffx_matrix A) {
   return guard([&] {
     if (!A) return;
+    if (A->scr.p) {  // every product that used the temporary is done before it is freed
+      (void)hipDeviceSynchronize();
+      (void)hipFree(A->scr.p);
+    }
+    if (A->scr.done) (void)hipEventDestroy(A->scr.done);
     A->A.release();
     A->AT.release();
     A->sg.release();

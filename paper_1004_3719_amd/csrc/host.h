@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -164,4 +165,21 @@ struct ffx_matrix_s {
   // reordered matrices: A and AT hold P A P^T; perm[new] = old on the device
   uint32_t* perm = nullptr;
   ffx_matrix_info info{};
+  // The temporary of the row products (x in 16 bits and/or in the stored order), allocated on the
+  // first product that needs one and kept until destroy: a stream-ordered allocation per product
+  // cost the host ~75 us. While every product uses one stream, stream order protects it. The first
+  // product on another stream synchronizes the device once; from then on (`multi`) `done` is
+  // recorded after each product and a product on another stream than `last` waits for it, so
+  // products on one handle stay correct on any streams (they serialize where they share the
+  // temporary). An event per product costs the GPU a few microseconds, hence not before it is
+  // needed. `mu` makes the wait, the launches and the record atomic.
+  struct {
+    std::mutex mu;
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+    bool multi = false;
+  } scr;
 };

@@ -789,3 +789,29 @@ def test_col_sorted_bound_edges(dev, orc, ffx, m):
     x = vec(43, 1, ncols, m)
     assert np.array_equal(M.spmv(tdev(x, dev, torch.int64)).cpu().numpy(), orc.spmv(A, x))
     M.close()
+
+
+def test_products_on_two_streams(dev, orc, ffx):
+    """Products on one handle from two streams, alternating, through the handle's kept temporary (the
+    16-bit x of the column-sorted groups, then x in the stored order of a reordered handle with
+    several vectors): every result equals the oracle's."""
+    A = synth.c2(n=150_000)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for opts, s in (({"col_sorted": 1}, 1), ({"reorder": True}, 5)):
+        note("two streams", opts, s)
+        M = ffx.from_synth(A, **opts)
+        xs = [vec(50 + k, s, A.ncols, A.m, s if s > 1 else None) for k in range(6)]
+        ys = [torch.empty((A.nrows, s) if s > 1 else (A.nrows,), dtype=torch.int32, device=dev) for _ in xs]
+        xd = [tdev(x, dev) for x in xs]
+        torch.cuda.synchronize()
+        for k in range(6):
+            with torch.cuda.stream(s1 if k % 2 == 0 else s2):
+                if s == 1:
+                    M.spmv(xd[k], y=ys[k])
+                else:
+                    M.spmm(xd[k], Y=ys[k])
+        torch.cuda.synchronize()
+        for k in range(6):
+            want = orc.spmv(A, xs[k]) if s == 1 else orc.spmm(A, xs[k])
+            assert np.array_equal(ys[k].cpu().numpy(), want), (opts, k)
+        M.close()
