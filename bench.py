@@ -92,6 +92,21 @@ def event_pairs(n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
 
+def timed(run, steps, stream):
+    """(GPU ms per call from one pair of HIP events around `steps` calls on `stream`, wall ms per
+    call); the caller has warmed up and synchronized. One pair, not one per call: an event per call
+    adds its own few microseconds of GPU time to every call."""
+    import torch
+    a, b = event_pairs(1)[0]
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        run()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps, (time.perf_counter() - t0) * 1e3 / steps
+
+
 def copy_calibration(mib):
     """A plain elementwise copy (mib MiB read, mib MiB written), three times: the reference
     kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -215,17 +230,8 @@ def bench_spmv(args, big=True):
     for _ in range(args.warmup):
         M.spmv(x, y=y)
     torch.cuda.synchronize()
-    ev = event_pairs(args.steps)
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        M.spmv(x, y=y)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ms = (t_end - t_start) * 1e3 / args.steps
-    log("%d steps: %.4f ms/step wall, %.4f ms/launch (events)" % (args.steps, ms, kernel_ms))
+    kernel_ms, ms = timed(lambda: M.spmv(x, y=y), args.steps, stream)
+    log("%d steps: %.4f ms/step wall, %.4f ms/product (events)" % (args.steps, ms, kernel_ms))
     extra = {}
     if not big:  # the plain configuration also times A^T x
         yt = torch.empty(A.ncols, dtype=torch.int32, device=dev)
@@ -361,13 +367,7 @@ def bench_accumulators(args):
             for _ in range(args.warmup):
                 run()
             torch.cuda.synchronize()
-            ev = event_pairs(steps)
-            for i in range(steps):
-                ev[i][0].record(stream)
-                run()
-                ev[i][1].record(stream)
-            torch.cuda.synchronize()
-            k_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+            k_ms, _ = timed(run, steps, stream)
             row["s%d_ms" % s_] = round(k_ms, 5)
             row["s%d_Gnnz_vec_per_s" % s_] = round(A.nnz * s_ / (k_ms * 1e-3) / 1e9, 1)
             if s_ == 1 and acc == args.acc:
@@ -381,13 +381,7 @@ def bench_accumulators(args):
     for _ in range(args.warmup):
         M.spmv(x1, y=y1)
     torch.cuda.synchronize()
-    ev = event_pairs(args.steps)
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        M.spmv(x1, y=y1)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    k_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+    k_ms, _ = timed(lambda: M.spmv(x1, y=y1), args.steps, stream)
     table["int64_col_sorted"] = {"s1_ms": round(k_ms, 5), "s1_Gnnz_vec_per_s": round(A.nnz / (k_ms * 1e-3) / 1e9, 1)}
     log("int64, column-sorted groups: %s" % table["int64_col_sorted"])
     M.close()
@@ -490,15 +484,7 @@ def bench_reorder(args):
         for _ in range(args.warmup):
             M.spmv(x, y=y)
         torch.cuda.synchronize()
-        ev = event_pairs(args.steps)
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            ev[i][0].record(stream)
-            M.spmv(x, y=y)
-            ev[i][1].record(stream)
-        torch.cuda.synchronize()
-        wall_ms = (time.perf_counter() - t1) * 1e3 / args.steps
-        ev_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+        ev_ms, wall_ms = timed(lambda: M.spmv(x, y=y), args.steps, stream)
         a_, b_ = event_pairs(1)[0]
         M.power(10, x)
         a_.record(stream)
@@ -566,16 +552,8 @@ def bench_gf2(args):
     for _ in range(args.warmup):
         M.spmm_gf2(X, Y)
     torch.cuda.synchronize()
-    ev = event_pairs(args.steps)
     stream = torch.cuda.current_stream()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        M.spmm_gf2(X, Y)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kernel_ms, ms = timed(lambda: M.spmm_gf2(X, Y), args.steps, stream)
     vecs = 32 * w
     b_alg = 4 * nnz + 4 * (A.nrows + 1) + 4 * w * (A.ncols + A.nrows)  # no values over GF(2)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
