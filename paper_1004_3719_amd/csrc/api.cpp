@@ -765,10 +765,10 @@ ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu,
       return;
     }
     warm_pool(st);
-    const int G = (int)((n + 255) / 256);  // 256 rows per projection workgroup
+    const Encoded& E = A->A;
     size_t wbytes = (size_t)n * w * 4;
     void* ws[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t sizes[5] = {wbytes, wbytes, wbytes, (size_t)G * npairs * 4, wbytes};
+    size_t sizes[5] = {wbytes, wbytes, wbytes, gf2_sequence_part_words(E.dm, w) * 4, wbytes};
     const int nws = (A->perm && Wlast) ? 5 : 4;  // reordered: A^L V is scattered back from ws[4]
     for (int q = 0; q < nws; ++q)
       if (hipMallocAsync(&ws[q], sizes[q], st) != hipSuccess) {
@@ -783,10 +783,9 @@ ffx_status ffx_sequence_gf2(ffx_matrix A, int32_t w, const void* U, int64_t ldu,
       e = launch_copy_block(FFX_I32, U, ldu, ws[0], w, n, w, st);
       if (e == hipSuccess) e = launch_copy_block(FFX_I32, V, ldv, ws[1], w, n, w, st);
     }
-    const Encoded& E = A->A;
     if (e == hipSuccess)
       e = launch_sequence_gf2(E.dm, E.max_tile_entries, w, (const uint32_t*)ws[0], (const uint32_t*)ws[1], L,
-                              (uint32_t*)S, (uint32_t*)ws[2], (uint32_t*)ws[3], G,
+                              (uint32_t*)S, (uint32_t*)ws[2], (uint32_t*)ws[3],
                               (uint32_t*)(A->perm && Wlast ? ws[4] : Wlast), st);
     if (e == hipSuccess && A->perm && Wlast) e = launch_permute_rows(4, ws[4], w, Wlast, w, A->perm, n, w, true, st);
     for (void* p : ws) if (p) (void)hipFreeAsync(p, st);

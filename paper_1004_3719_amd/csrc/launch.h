@@ -74,8 +74,10 @@ hipError_t launch_tiles_gf2(const DevMat& A, int64_t mte, const void* X, int64_t
 // L * 32w * w words. Workspace: w1 (n x w words), part (G * 32w * w words, G = ceil(n / 256)); W0 is
 // overwritten.
 // Wlast (n x w, or null) receives A^L W0.
+// Words of the partial buffers of launch_sequence_gf2.
+size_t gf2_sequence_part_words(const DevMat& A, int w);
 hipError_t launch_sequence_gf2(const DevMat& A, int64_t mte, int w, const uint32_t* U, const uint32_t* W0, int64_t L,
-                               uint32_t* S, uint32_t* w1, uint32_t* part, int G, uint32_t* Wlast, hipStream_t st);
+                               uint32_t* S, uint32_t* w1, uint32_t* part, uint32_t* Wlast, hipStream_t st);
 
 // 16-bit copy of one vector of n residues (stride ldx) for the compact-x path.
 hipError_t launch_compact_x(ffx_dtype dt, const void* X, int64_t ldx, uint16_t* out, int64_t n, hipStream_t st);

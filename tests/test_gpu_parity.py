@@ -564,11 +564,11 @@ def test_gf2_rejects_other_moduli(dev, ffx):
         M.spmm_gf2(torch.zeros((A.ncols, 1), dtype=torch.int32, device=dev))
 
 
-@pytest.mark.parametrize("w", [1, 2, 3])
+@pytest.mark.parametrize("w", [1, 2, 3, 9])
 @pytest.mark.parametrize("kind", ["c3", "powerlaw"])
 def test_gf2_sequence(dev, orc, ffx, w, kind):
     """S_i = U^T A^i V over GF(2) on packed blocks against the oracle on the 32w unpacked vectors, with
-    A^L V."""
+    A^L V (w = 9: more words of S per term than a workgroup has lanes)."""
     if kind == "c3":
         A = synth.c3(n=1500, ndead=10, m=2)
     else:
@@ -587,6 +587,11 @@ def test_gf2_sequence(dev, orc, ffx, w, kind):
     want = np.stack([pack_bits(So[i]) for i in range(L)])
     assert np.array_equal(S.cpu().numpy(), want)
     assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
+    # one term, and a run without A^L V
+    S1 = M.sequence_gf2(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), 1)
+    assert np.array_equal(S1.cpu().numpy(), want[:1])
+    S5 = M.sequence_gf2(torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev), 5)
+    assert np.array_equal(S5.cpu().numpy(), want[:5])
 
 
 # ------------------------------------------------------------- reordering --
