@@ -180,6 +180,9 @@ ffx_status ffx_matrix_info_get(ffx_matrix A, ffx_matrix_info* info);
  * writes min(cap, nblocks) ffx_format values to out (host memory). */
 ffx_status ffx_matrix_block_formats(ffx_matrix A, int32_t transpose, int32_t* out, int64_t cap);
 
+/* Frees the handle and its device memory (NULL: nothing). When the handle
+ * holds the temporary of its row products, the device is synchronized first,
+ * so no product still running uses it. */
 ffx_status ffx_matrix_destroy(ffx_matrix A);
 
 /* Y <- A X over GF(2) with bit-packed blocks (Section 4 points to compressing

@@ -144,6 +144,7 @@ size_t gf2_sequence_part_words(const DevMat& A, int w) {
 hipError_t launch_sequence_gf2(const DevMat& A, int64_t mte, int w, const uint32_t* U, const uint32_t* W0, int64_t L,
                                uint32_t* S, uint32_t* w1, uint32_t* part, uint32_t* Wlast, hipStream_t st) {
   if (L <= 0) return hipSuccess;
+  if (A.ntiles == 0) return hipErrorInvalidValue;  // every row lies in a tile, so n > 0 means tiles
   const int npairs = 32 * w * w;
   const size_t pw = (size_t)(A.ntiles > 0 ? A.ntiles : 1) * npairs, mw = (size_t)GF2_NMID * npairs;
   Gf2SeqArgs q;
