@@ -820,3 +820,29 @@ def test_products_on_two_streams(dev, orc, ffx):
             want = orc.spmv(A, xs[k]) if s == 1 else orc.spmm(A, xs[k])
             assert np.array_equal(ys[k].cpu().numpy(), want), (opts, k)
         M.close()
+
+
+@pytest.mark.parametrize("n", [1, 5, 300])
+def test_sequences_of_an_empty_matrix(dev, orc, ffx, n):
+    """A square matrix without entries: S_0 = U^T V and every later term 0, A^L V = 0, for residues
+    (s = 8 and 3) and over GF(2) (64 packed vectors)."""
+    A = synth.Csr(n, n, np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64), m=2**31 - 1)
+    note("empty matrix sequence", n)
+    M = ffx.from_synth(A)
+    for s in (8, 3):
+        U, V = vec(60, s, n, A.m, s), vec(61, s, n, A.m, s)
+        S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), 4, want_last=True)
+        So, Wo = orc.sequence(A, U, V, 4, want_last=True)
+        assert np.array_equal(S.cpu().numpy(), So) and np.array_equal(W.cpu().numpy(), Wo), s
+        assert not So[1:].any()
+    B = synth.Csr(n, n, np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64), m=2)
+    M2 = ffx.from_synth(B)
+    rng = np.random.default_rng(n)
+    Ub = rng.integers(-(2**31), 2**31, size=(n, 2), dtype=np.int64).astype(np.int32)
+    Vb = rng.integers(-(2**31), 2**31, size=(n, 2), dtype=np.int64).astype(np.int32)
+    S, W = M2.sequence_gf2(torch.from_numpy(Ub).to(dev), torch.from_numpy(Vb).to(dev), 3, want_last=True)
+    So, Wo = orc.sequence(B, unpack_bits(Ub), unpack_bits(Vb), 3, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), np.stack([pack_bits(So[i]) for i in range(3)]))
+    assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
+    M.close()
+    M2.close()
