@@ -446,6 +446,8 @@ void encode(const RCsr& A, const Modulus& md, const PlanOpts& o, hipStream_t str
   out->block_tile0[nblocks] = (uint32_t)H.tiles.size();
   if (H.ent.size() >= UINT32_MAX || H.val.size() >= UINT32_MAX || H.bval.size() >= UINT32_MAX)
     fail(FFX_EUNSUPPORTED, "encoded matrix exceeds 2^32 words in one array");
+  // a last value offset after the last chunk: chunk c's values end at choff[c + 1] for every c
+  H.choff.push_back((uint32_t)H.val.size());
 
   // one device allocation, 256-byte aligned parts
   const bool small = md.small();

@@ -217,11 +217,13 @@ __device__ inline void sell_slice_rc(const DevMat& A, const Tile& T, uint32_t sl
 // takes 32 rows of a slice, two lanes per row, and a lane keeps four of the
 // row's eight components. Each gather is then one 16-byte load (half a row of
 // W_i) and a wave instruction covers 32 rows, against 8 rows and 4-byte loads
-// in the (row, component) layout. The entry words are read once per wave with
-// lane = row (as they are stored), which also yields each row's value index
-// by ballots; the words and the index then move to the lanes of their row by
-// shuffles. With PROJ the wave writes its rows of U and W_{i+1} to LDS and
-// lane p = 8a + c sums U[row][a] W_{i+1}[row][c] over the wave's 32 rows.
+// in the (row, component) layout. Both lanes of a row load the row's entry
+// words themselves. Its values are found without the other half's words: a
+// group's values lie in row order, so the lower half's start at the group's
+// offset and the upper half's end where the next chunk's begin (the offsets
+// end with the total), and ballots over one lane per row count those before a
+// row within the half. With PROJ the wave writes its rows of U and W_{i+1} to
+// LDS and lane p = 8a + c sums U[row][a] W_{i+1}[row][c] over its 32 rows.
 // X, Y and U have leading dimension 8.
 // GU: 4-column groups loaded together.
 template <class AR, bool PROJ, int GU>
@@ -231,14 +233,14 @@ __device__ inline void sell_slice_h8(const DevMat& A, const Tile& T, uint32_t sl
                                      uint64_t* red /* LDS [TILE_THREADS] */) {
   const uint32_t lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const uint32_t rr = lane >> 1, h = lane & 1u;
-  const uint32_t src = half * 32u + rr;  // lane holding this row's words (lane = row of the slice)
   const bool live = slice < T.ne;
   uint32_t off = 0;
   for (uint32_t k = 0; k < slice && live; ++k) off += A.swidth[T.aux + k];
   const uint32_t groups = live ? A.swidth[T.aux + slice] : 0u;
-  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + lane * WIDE;
+  const uint32_t srow = half * 32u + rr;  // this lane's row in the slice
+  const uint32_t* ent = A.ent + T.e0 + (size_t)off * SELL_GROUP + srow * WIDE;
   const uint32_t* choff = A.choff + T.c0 + off;
-  const uint32_t slot = slice * WAVE + src;
+  const uint32_t slot = slice * WAVE + srow;
   const uint32_t prow = !live ? 0xFFFFFFFFu : (T.kind & TF_SORTED) ? A.perm[T.row0 + slot] : T.row0 + slot;
   const bool pok = prow < A.nrows;
   // U of the projection does not depend on the product: its load goes out first
@@ -259,8 +261,10 @@ __device__ inline void sell_slice_h8(const DevMat& A, const Tile& T, uint32_t sl
     acc.a[3] += AR::mul(v, x.w);
     acc.tick(A);
   }
+  const uint64_t even = 0x5555555555555555ull;  // one lane per row
   for (uint32_t g0 = 0; g0 < groups; g0 += GU) {
-    uint32_t w[GU][WIDE], idx[GU];
+    uint32_t w[GU][WIDE], v[GU][WIDE];
+    u32x4 xv[GU][WIDE];
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       u32x4 q = g0 + u < groups ? __builtin_nontemporal_load((const u32x4*)(ent + (size_t)(g0 + u) * SELL_GROUP))
@@ -269,36 +273,37 @@ __device__ inline void sell_slice_h8(const DevMat& A, const Tile& T, uint32_t sl
       w[u][1] = q.y;
       w[u][2] = q.z;
       w[u][3] = q.w;
-      idx[u] = value_index4(w[u], g0 + u < groups ? choff[g0 + u] : 0u);
-    }
-    // to the lanes of the row: words first, so the gathers can leave before the values
-    uint32_t wr[GU][WIDE];
-    u32x4 xv[GU][WIDE];
-#pragma unroll
-    for (int u = 0; u < GU; ++u)
+      // general values of the rows before this one in the half (even lanes only), and in the half
+      uint32_t below = 0, total = 0, mine = 0;
 #pragma unroll
       for (int k = 0; k < WIDE; ++k) {
-        wr[u][k] = (uint32_t)__shfl((int)w[u][k], (int)src);
-        xv[u][k] = (u32x4){0u, 0u, 0u, 0u};
-        if ((wr[u][k] >> TAG_SHIFT) != TAG_PAD && pok)
-          xv[u][k] = *(const u32x4*)(X + (int64_t)(wr[u][k] & COL_MASK) * 8 + 4 * h);
+        const bool gen = (w[u][k] >> TAG_SHIFT) == TAG_GEN;
+        const uint64_t mk = __ballot(gen && h == 0) & even;
+        below += lanes_below(mk);
+        total += (uint32_t)__builtin_popcountll(mk);
+        mine += gen ? 1u : 0u;
       }
-    uint32_t v[GU][WIDE];
-#pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const uint32_t ir = (uint32_t)__shfl((int)idx[u], (int)src);
+      if (h) below -= mine;  // an odd lane's count includes its own row's even lane
+      uint32_t base = 0;
+      if (g0 + u < groups) base = half ? choff[g0 + u + 1] - total : choff[g0 + u];
       if (pok) {
-        load_values_at<AR>(A, wr[u], ir, v[u]);
+        load_values_at<AR>(A, w[u], base + below, v[u]);
       } else {
 #pragma unroll
         for (int k = 0; k < WIDE; ++k) v[u][k] = 0u;
       }
+#pragma unroll
+      for (int k = 0; k < WIDE; ++k) {
+        xv[u][k] = (u32x4){0u, 0u, 0u, 0u};
+        if ((w[u][k] >> TAG_SHIFT) != TAG_PAD && pok)
+          xv[u][k] = *(const u32x4*)(X + (int64_t)(w[u][k] & COL_MASK) * 8 + 4 * h);
+      }
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u)
 #pragma unroll
       for (int k = 0; k < WIDE; ++k) {
-        const uint32_t tag = wr[u][k] >> TAG_SHIFT;
+        const uint32_t tag = w[u][k] >> TAG_SHIFT;
         acc.a[0] += term<AR>(tag, v[u][k], xv[u][k].x, A.m);
         acc.a[1] += term<AR>(tag, v[u][k], xv[u][k].y, A.m);
         acc.a[2] += term<AR>(tag, v[u][k], xv[u][k].z, A.m);
@@ -376,8 +381,7 @@ constexpr int SEQ_H8_GROUPS = 1;
 // 2t + h writes the partial of slot 4t + 2h and zeros into slot 4t + 2h + 1,
 // so the partial buffers keep four slots per tile either way.
 template <class AR, typename Ts, int S, bool ONLY_SELL, int H8>
-__global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
-  extern __shared__ __align__(16) unsigned char lds[];
+__device__ __forceinline__ void seq_step(const DevMat& A, const SeqArgs& q, int32_t j, unsigned char* lds) {
   const int64_t i = *q.base + j;
   if (i >= q.L) return;
   const int s = q.s;
@@ -447,6 +451,20 @@ __global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, 
   }
 }
 
+template <class AR, typename Ts, int S, bool ONLY_SELL>
+__global__ __launch_bounds__(TILE_THREADS) void k_seq_step(DevMat A, SeqArgs q, int32_t j) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  seq_step<AR, Ts, S, ONLY_SELL, 0>(A, q, j, lds);
+}
+
+// s = 8 (sell_slice_h8): the 6,256 waves of a 200,000-row operand are resident at once with 7 waves
+// per SIMD, so the kernel is held to the registers that allow 7
+template <class AR, typename Ts, bool ONLY_SELL>
+__global__ __launch_bounds__(TILE_THREADS, 7) void k_seq_step_h8(DevMat A, SeqArgs q, int32_t j) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  seq_step<AR, Ts, 8, ONLY_SELL, SEQ_H8_GROUPS>(A, q, j, lds);
+}
+
 // S_{L-1} from the sums of the last iteration.
 template <typename Ts>
 __global__ __launch_bounds__(TILE_THREADS) void k_seq_finish(DevMat A, SeqArgs q) {
@@ -476,13 +494,13 @@ static hipError_t seq_go(const DevMat& A, int64_t mte, const SeqArgs& q, int bat
   auto step = [&](hipStream_t st, int32_t j) {
     dim3 g((h8 ? A.ntiles * 2 : A.ntiles * SELL_SLICES) + NMID + 1), b(TILE_THREADS);
     switch (S) {
-      case 2: hipLaunchKernelGGL((k_seq_step<AR, Ts, 2, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
-      case 4: hipLaunchKernelGGL((k_seq_step<AR, Ts, 4, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
+      case 2: hipLaunchKernelGGL((k_seq_step<AR, Ts, 2, ONLY_SELL>), g, b, lds, st, A, q, j); break;
+      case 4: hipLaunchKernelGGL((k_seq_step<AR, Ts, 4, ONLY_SELL>), g, b, lds, st, A, q, j); break;
       case 8:
-        if (h8) hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL, SEQ_H8_GROUPS>), g, b, lds, st, A, q, j);
-        else hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL, 0>), g, b, lds, st, A, q, j);
+        if (h8) hipLaunchKernelGGL((k_seq_step_h8<AR, Ts, ONLY_SELL>), g, b, lds, st, A, q, j);
+        else hipLaunchKernelGGL((k_seq_step<AR, Ts, 8, ONLY_SELL>), g, b, lds, st, A, q, j);
         break;
-      default: hipLaunchKernelGGL((k_seq_step<AR, Ts, 16, ONLY_SELL, 0>), g, b, lds, st, A, q, j); break;
+      default: hipLaunchKernelGGL((k_seq_step<AR, Ts, 16, ONLY_SELL>), g, b, lds, st, A, q, j); break;
     }
   };
   hipLaunchKernelGGL((k_seq_counter), dim3(1), dim3(64), 0, user, base, (int64_t)0, 1);
