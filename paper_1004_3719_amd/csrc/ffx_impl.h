@@ -73,7 +73,7 @@ struct DevMat {
   const Tile* tiles;
   const uint32_t* ent;
   const void* val;       // uint16_t or uint32_t, by the modulus
-  const uint32_t* choff; // value offset of each 256-entry chunk, then the total (chunk c ends at c + 1)
+  const uint32_t* choff; // value offset of each 256-entry chunk
   const uint32_t* rowp;  // STREAM tiles: rows+1 absolute entry offsets per tile
   const uint32_t* perm;  // sorted SELL: slot -> row (0xFFFFFFFF for padding slots)
   const uint32_t* swidth;// SELL: 4-column groups of each slice
