@@ -454,11 +454,17 @@ static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, i
     }
     // one vector on a handle with column-sorted groups: every product on the groups (through a
     // 16-bit copy of the current vector when the handle takes one); they write y with unit stride
+    // Each product but the last also writes its result as the next one's 16-bit x (two buffers in turn),
+    // so only V is copied to 16 bits.
     const bool sg = s == 1 && M.sg.ngroups && ldw == 1;
-    uint16_t* x16 = nullptr;
-    if (sg && M.compact_x && n > 0 && hipMallocAsync((void**)&x16, (size_t)n * 2, st) != hipSuccess) {
-      for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
-      fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", (size_t)n * 2);
+    uint16_t* x16[2] = {nullptr, nullptr};
+    if (sg && M.compact_x && n > 0) {
+      for (int q = 0; q < (k >= 2 ? 2 : 1); ++q)
+        if (hipMallocAsync((void**)&x16[q], (size_t)n * 2, st) != hipSuccess) {
+          for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
+          for (void* p : x16) if (p) (void)hipFreeAsync(p, st);
+          fail(FFX_ENOMEM, "hipMallocAsync of %zu bytes failed", (size_t)n * 2);
+        }
     }
     const void* cur = V;
     int64_t ldc = ldv;
@@ -467,11 +473,12 @@ static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, i
       bool last = it == k - 1;
       void* dst = last ? W : tmp[it & 1];
       int64_t ldd = last ? ldw : s;
-      if (sg && (x16 || ldc == 1)) {
+      if (sg && (x16[0] || ldc == 1)) {
         SgMat g = M.sg.dm;
         g.rowmap = last ? rowmap : nullptr;
-        if (x16) e = launch_compact_x(dtype, cur, ldc, x16, n, st);
-        if (e == hipSuccess) e = launch_sg(g, dtype, cur, x16, dst, 1, 0, st);
+        uint16_t* xin = x16[it & 1];
+        if (xin && it == 0) e = launch_compact_x(dtype, cur, ldc, xin, n, st);
+        if (e == hipSuccess) e = launch_sg(g, dtype, cur, xin, dst, 1, 0, st, last ? nullptr : x16[(it + 1) & 1]);
       } else {
         DevMat dm = E.dm;
         if (last) dm.rowmap = rowmap;
@@ -481,7 +488,7 @@ static void power_iter(const ffx_matrix_s& M, int64_t k, int s, const void* V, i
       ldc = ldd;
     }
     for (void* p : tmp) if (p) (void)hipFreeAsync(p, st);
-    if (x16) (void)hipFreeAsync(x16, st);
+    for (void* p : x16) if (p) (void)hipFreeAsync(p, st);
     FFX_HIP(e);
   }
 }

@@ -57,8 +57,10 @@ struct SgMat {
   uint64_t mu;
 };
 
-// y = alpha*A*x + beta*y from the groups; x16: 16-bit copy of x, or null to gather from x (Tv).
+// y = alpha*A*x + beta*y from the groups; x16: 16-bit copy of x, or null to gather from x (Tv);
+// y16: when not null, also receives y as 16-bit residues (row rowmap[r] when there is a row map), the
+// next product's x16 in a chain of products.
 hipError_t launch_sg(const SgMat& G, ffx_dtype dt, const void* x, const uint16_t* x16, void* y, uint32_t alpha,
-                     uint32_t beta, hipStream_t st);
+                     uint32_t beta, hipStream_t st, uint16_t* y16 = nullptr);
 
 }  // namespace ffx

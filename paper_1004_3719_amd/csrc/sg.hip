@@ -19,7 +19,7 @@ __device__ inline uint32_t sg_lanes_below(uint64_t mask) {
 
 template <typename Tx, typename Tv, int NT, int U>
 __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv* __restrict__ y, uint32_t alpha,
-                                           uint32_t beta) {
+                                           uint32_t beta, uint16_t* __restrict__ y16) {
   extern __shared__ __align__(16) unsigned long long acc[];
   constexpr uint32_t NW = NT / WAVE;
   const SgGroup g = G.groups[blockIdx.x];
@@ -103,7 +103,9 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
     const uint32_t row = g.row0 + r;
     Tv* yr = y + (G.rowmap ? G.rowmap[row] : row);
     const uint32_t res = mod_u64(acc[r], G.m, G.mu);
-    *yr = (Tv)((alpha == 1 && beta == 0) ? res : axpby(alpha, res, beta, beta ? (uint32_t)*yr : 0u, G.m, G.mu));
+    const uint32_t out = (alpha == 1 && beta == 0) ? res : axpby(alpha, res, beta, beta ? (uint32_t)*yr : 0u, G.m, G.mu);
+    *yr = (Tv)out;
+    if (y16) y16[G.rowmap ? G.rowmap[row] : row] = (uint16_t)out;  // the next product's 16-bit x
   }
 }
 
@@ -111,7 +113,8 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
 constexpr size_t SG_LDS_MAX = (size_t)SG_MAX_ROWS * 8;
 
 template <typename Tx, typename Tv>
-static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint32_t beta, hipStream_t st) {
+static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint32_t beta, uint16_t* y16,
+                        hipStream_t st) {
   const size_t lds = std::max<size_t>((size_t)G.max_rows * 8, SG_LDS_FLOOR);
   auto k = k_sg<Tx, Tv, SG_THREADS, SG_U>;
   // the kernel's LDS limit is raised once per device to the most any group can need (the
@@ -130,19 +133,19 @@ static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint
       done[dev] = true;
     }
   }
-  hipLaunchKernelGGL(k, dim3(G.ngroups), dim3(SG_THREADS), lds, st, G, x, y, alpha, beta);
+  hipLaunchKernelGGL(k, dim3(G.ngroups), dim3(SG_THREADS), lds, st, G, x, y, alpha, beta, y16);
   return hipGetLastError();
 }
 
 hipError_t launch_sg(const SgMat& G, ffx_dtype dt, const void* x, const uint16_t* x16, void* y, uint32_t alpha,
-                     uint32_t beta, hipStream_t st) {
+                     uint32_t beta, hipStream_t st, uint16_t* y16) {
   if (G.ngroups == 0) return hipSuccess;
   if (dt == FFX_I32) {
-    if (x16) return sg_go<uint16_t, int32_t>(G, x16, (int32_t*)y, alpha, beta, st);
-    return sg_go<int32_t, int32_t>(G, (const int32_t*)x, (int32_t*)y, alpha, beta, st);
+    if (x16) return sg_go<uint16_t, int32_t>(G, x16, (int32_t*)y, alpha, beta, y16, st);
+    return sg_go<int32_t, int32_t>(G, (const int32_t*)x, (int32_t*)y, alpha, beta, y16, st);
   }
-  if (x16) return sg_go<uint16_t, int64_t>(G, x16, (int64_t*)y, alpha, beta, st);
-  return sg_go<int64_t, int64_t>(G, (const int64_t*)x, (int64_t*)y, alpha, beta, st);
+  if (x16) return sg_go<uint16_t, int64_t>(G, x16, (int64_t*)y, alpha, beta, y16, st);
+  return sg_go<int64_t, int64_t>(G, (const int64_t*)x, (int64_t*)y, alpha, beta, y16, st);
 }
 
 }  // namespace ffx
