@@ -558,7 +558,9 @@ def bench_gf2(args):
     b_alg = 4 * nnz + 4 * (A.nrows + 1) + 4 * w * (A.ncols + A.nrows)  # no values over GF(2)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_tiles (GF(2) packed)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": ("k_sg (column-sorted groups, exclusive-or sums)" if w == 1 and M.info()["sg_groups"]
+                           else "k_tiles (GF(2) packed)"),
                 "kernel_ms": round(kernel_ms, 5), "algorithmic_bytes": int(b_alg)}
     cpu = None
     if not args.no_cpu_baseline:

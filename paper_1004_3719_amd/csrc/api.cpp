@@ -736,6 +736,10 @@ ffx_status ffx_spmm_gf2(ffx_matrix A, int32_t w, const void* X, int64_t ldx, voi
       });
       return;
     }
+    if (w == 1 && A->sg.ngroups) {  // one word per row: the column-sorted groups, summed by exclusive or
+      FFX_HIP(launch_sg_gf2(A->sg.dm, (const uint32_t*)X, ldx, (uint32_t*)Y, ldy, st));
+      return;
+    }
     FFX_HIP(launch_tiles_gf2(E.dm, E.max_tile_entries, X, ldx, Y, ldy, w, st));
   });
 }

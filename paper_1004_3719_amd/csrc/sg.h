@@ -62,5 +62,8 @@ struct SgMat {
 // next product's x16 in a chain of products.
 hipError_t launch_sg(const SgMat& G, ffx_dtype dt, const void* x, const uint16_t* x16, void* y, uint32_t alpha,
                      uint32_t beta, hipStream_t st, uint16_t* y16 = nullptr);
+// Y = A X over GF(2) for a matrix mod 2 and one bit-packed word per row (32 vectors): X ncols x 1
+// words with stride ldx, Y nrows x 1 with stride ldy (through the row map when there is one).
+hipError_t launch_sg_gf2(const SgMat& G, const uint32_t* X, int64_t ldx, uint32_t* Y, int64_t ldy, hipStream_t st);
 
 }  // namespace ffx

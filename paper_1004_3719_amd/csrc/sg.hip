@@ -17,14 +17,20 @@ __device__ inline uint32_t sg_lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-template <typename Tx, typename Tv, int NT, int U>
+// GF2: a matrix mod 2 times one bit-packed word per row (32 vectors over GF(2)): x and y are words
+// (stride ldx, ldy), a row's sum is the exclusive or of its columns' words (32-bit LDS sums).
+template <typename Tx, typename Tv, int NT, int U, bool GF2>
 __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv* __restrict__ y, uint32_t alpha,
-                                           uint32_t beta, uint16_t* __restrict__ y16) {
+                                           uint32_t beta, uint16_t* __restrict__ y16, int64_t ldx, int64_t ldy) {
   extern __shared__ __align__(16) unsigned long long acc[];
+  uint32_t* accx = (uint32_t*)acc;  // GF2
   constexpr uint32_t NW = NT / WAVE;
   const SgGroup g = G.groups[blockIdx.x];
   const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-  for (uint32_t r = tid; r < g.nrows; r += NT) acc[r] = 0ull;
+  for (uint32_t r = tid; r < g.nrows; r += NT) {
+    if constexpr (GF2) accx[r] = 0u;
+    else acc[r] = 0ull;
+  }
   __syncthreads();
   // the entry words of the next U chunks are requested before the values and gathers of the
   // current ones, so each pass waits on one round trip to memory instead of two
@@ -76,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
         const uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
         v[u][k] = tag == TAG_GEN ? (d >> ((j & 1u) * 16)) & 0xFFFFu : 0u;
         j += tag == TAG_GEN ? 1u : 0u;
-        xv[u][k] = tag != TAG_PAD ? (uint32_t)x[cb[u] + (w[u][k] & SG_COL_MASK)] : 0u;
+        xv[u][k] = tag != TAG_PAD ? (uint32_t)x[(int64_t)(cb[u] + (w[u][k] & SG_COL_MASK)) * ldx] : 0u;
       }
     }
 #pragma unroll
@@ -85,9 +91,14 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
       for (int k = 0; k < 4; ++k) {
         const uint32_t tag = w[u][k] >> TAG_SHIFT;
         if (tag != TAG_PAD) {
-          // a term is below 2^32: (m-1)^2, x or m - x
-          const uint32_t t = tag == TAG_GEN ? v[u][k] * xv[u][k] : tag == TAG_PLUS ? xv[u][k] : G.m - xv[u][k];
-          atomicAdd(&acc[(w[u][k] >> SG_ROW_SHIFT) & (SG_MAX_ROWS - 1)], (unsigned long long)t);
+          const uint32_t row = (w[u][k] >> SG_ROW_SHIFT) & (SG_MAX_ROWS - 1);
+          if constexpr (GF2) {  // entries are 1 (with values off, a stored value is odd)
+            atomicXor(&accx[row], (tag != TAG_GEN || (v[u][k] & 1u)) ? xv[u][k] : 0u);
+          } else {
+            // a term is below 2^32: (m-1)^2, x or m - x
+            const uint32_t t = tag == TAG_GEN ? v[u][k] * xv[u][k] : tag == TAG_PLUS ? xv[u][k] : G.m - xv[u][k];
+            atomicAdd(&acc[row], (unsigned long long)t);
+          }
         }
       }
 #pragma unroll
@@ -99,6 +110,13 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
     }
   }
   __syncthreads();
+  if constexpr (GF2) {
+    for (uint32_t r = tid; r < g.nrows; r += NT) {
+      const uint32_t row = g.row0 + r;
+      y[(int64_t)(G.rowmap ? G.rowmap[row] : row) * ldy] = (Tv)accx[r];
+    }
+    return;
+  }
   for (uint32_t r = tid; r < g.nrows; r += NT) {
     const uint32_t row = g.row0 + r;
     Tv* yr = y + (G.rowmap ? G.rowmap[row] : row);
@@ -112,11 +130,11 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
 // The largest dynamic LDS a group can ask for: SG_MAX_ROWS 64-bit sums.
 constexpr size_t SG_LDS_MAX = (size_t)SG_MAX_ROWS * 8;
 
-template <typename Tx, typename Tv>
+template <typename Tx, typename Tv, bool GF2 = false>
 static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint32_t beta, uint16_t* y16,
-                        hipStream_t st) {
+                        hipStream_t st, int64_t ldx = 1, int64_t ldy = 1) {
   const size_t lds = std::max<size_t>((size_t)G.max_rows * 8, SG_LDS_FLOOR);
-  auto k = k_sg<Tx, Tv, SG_THREADS, SG_U>;
+  auto k = k_sg<Tx, Tv, SG_THREADS, SG_U, GF2>;
   // the kernel's LDS limit is raised once per device to the most any group can need (the
   // attribute is a host call that would otherwise cost a few microseconds per product)
   static std::mutex mu;
@@ -133,7 +151,7 @@ static hipError_t sg_go(const SgMat& G, const Tx* x, Tv* y, uint32_t alpha, uint
       done[dev] = true;
     }
   }
-  hipLaunchKernelGGL(k, dim3(G.ngroups), dim3(SG_THREADS), lds, st, G, x, y, alpha, beta, y16);
+  hipLaunchKernelGGL(k, dim3(G.ngroups), dim3(SG_THREADS), lds, st, G, x, y, alpha, beta, y16, ldx, ldy);
   return hipGetLastError();
 }
 
@@ -146,6 +164,11 @@ hipError_t launch_sg(const SgMat& G, ffx_dtype dt, const void* x, const uint16_t
   }
   if (x16) return sg_go<uint16_t, int64_t>(G, x16, (int64_t*)y, alpha, beta, y16, st);
   return sg_go<int64_t, int64_t>(G, (const int64_t*)x, (int64_t*)y, alpha, beta, y16, st);
+}
+
+hipError_t launch_sg_gf2(const SgMat& G, const uint32_t* X, int64_t ldx, uint32_t* Y, int64_t ldy, hipStream_t st) {
+  if (G.ngroups == 0) return hipSuccess;
+  return sg_go<uint32_t, uint32_t, true>(G, X, Y, 1, 0, nullptr, st, ldx, ldy);
 }
 
 }  // namespace ffx

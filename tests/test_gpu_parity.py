@@ -543,7 +543,9 @@ def pack_bits(B):
 @pytest.mark.parametrize("fmt", [None] + FORMATS)
 @pytest.mark.parametrize("w", [1, 3, 16])
 def test_gf2_packed(dev, orc, ffx, fmt, w):
-    """Y = A X over GF(2) on bit-packed blocks against the oracle applied to the 32w unpacked vectors."""
+    """Y = A X over GF(2) on bit-packed blocks against the oracle applied to the 32w unpacked vectors;
+    with one word per row also on the column-sorted groups (exclusive-or sums), with values stored or
+    not, and with X and Y columns of wider blocks."""
     s = synth.spec(6000, 5000, 91 + w, len_kind=synth.LEN_ZIPF, len_a=1, len_b=900, len_alpha=1.6,
                    col_kind=synth.COL_UNIFORM, band_lo=-2, band_hi=2, p_pm1=0.5, val_lo=-(2**31), val_hi=2**31 - 1)
     A = synth.rows(s)
@@ -555,6 +557,18 @@ def test_gf2_packed(dev, orc, ffx, fmt, w):
     Y = M.spmm_gf2(torch.from_numpy(X).to(dev)).cpu().numpy()
     want = pack_bits(orc.spmm(A, unpack_bits(X)))
     assert np.array_equal(Y, want)
+    if w == 1 and fmt is None:
+        for split in (True, False):
+            Mc = ffx.from_synth(A, col_sorted=1, split_pm1=split)
+            assert Mc.info()["sg_groups"] > 0
+            assert np.array_equal(Mc.spmm_gf2(torch.from_numpy(X).to(dev)).cpu().numpy(), want), split
+            Xw = torch.zeros((A.ncols, 3), dtype=torch.int32, device=dev)
+            Xw[:, 1] = torch.from_numpy(X[:, 0]).to(dev)
+            Yw = torch.full((A.nrows, 4), 7, dtype=torch.int32, device=dev)
+            Mc.spmm_gf2(Xw[:, 1:2], Y=Yw[:, 2:3])
+            assert np.array_equal(Yw[:, 2:3].cpu().numpy(), want), split
+            assert (Yw[:, [0, 1, 3]] == 7).all()
+            Mc.close()
 
 
 def test_gf2_rejects_other_moduli(dev, ffx):
