@@ -82,7 +82,8 @@ __global__ __launch_bounds__(NT) void k_sg(SgMat G, const Tx* __restrict__ x, Tv
         const uint32_t d = j < 2 ? q0 : j < 4 ? q1 : q2;
         v[u][k] = tag == TAG_GEN ? (d >> ((j & 1u) * 16)) & 0xFFFFu : 0u;
         j += tag == TAG_GEN ? 1u : 0u;
-        xv[u][k] = tag != TAG_PAD ? (uint32_t)x[(int64_t)(cb[u] + (w[u][k] & SG_COL_MASK)) * ldx] : 0u;
+        const uint32_t col = cb[u] + (w[u][k] & SG_COL_MASK);
+        xv[u][k] = tag != TAG_PAD ? (uint32_t)(GF2 ? x[(int64_t)col * ldx] : x[col]) : 0u;
       }
     }
 #pragma unroll
