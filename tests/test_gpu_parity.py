@@ -860,3 +860,27 @@ def test_sequences_of_an_empty_matrix(dev, orc, ffx, n):
     assert np.array_equal(W.cpu().numpy(), pack_bits(Wo))
     M.close()
     M2.close()
+
+
+@pytest.mark.parametrize("s", [8, 16, 3])
+@pytest.mark.parametrize("fmt", [None, "SELL"])
+def test_sequence_long_rows(dev, orc, ffx, s, fmt):
+    """The sequence on a matrix with rows longer than a STREAM tile holds (LONG tiles, and the
+    long-row flag of the multi-vector STREAM tiles) beside short rows, for the half-row step (s = 8)
+    and the per-component one; A^L V too."""
+    n = 3000
+    rng = np.random.default_rng(70 + s)
+    lens = rng.integers(0, 12, n)
+    lens[[5, 777, 2999]] = [2900, 2500, 2100]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(n, size=int(L), replace=False)) for L in lens]).astype(np.int32)
+    vals = rng.integers(-(2**40), 2**40, size=int(rp[-1]))
+    A = synth.Csr(n, n, rp, cols, vals, m=2**31 - 1)
+    U, V = vec(71, s, n, A.m, s), vec(72, s, n, A.m, s)
+    note("sequence long rows", s, fmt)
+    M = ffx.from_synth(A, fixed_format=fmt)
+    S, W = M.sequence(tdev(U, dev, torch.int64), tdev(V, dev, torch.int64), 9, want_last=True)
+    So, Wo = orc.sequence(A, U, V, 9, want_last=True)
+    assert np.array_equal(S.cpu().numpy(), So)
+    assert np.array_equal(W.cpu().numpy(), Wo)
