@@ -896,6 +896,10 @@ def bench_selector(args):
     orc = oracle.get()
     tot = {}
     same, nev = True, 0
+    eval_fixed = FORMATS if args.eval_fixed == "all" else [f for f in args.eval_fixed.split(",") if f]
+    for f in eval_fixed:
+        if f not in FORMATS:
+            raise SystemExit("--eval-fixed: unknown format %s (formats: %s)" % (f, ",".join(FORMATS)))
     for k in range(1800, 1800 + args.eval_mats):
         sp, p = synth.c5_spec(k)
         r1 = min(sp.nrows, args.eval_rows) if args.eval_rows else sp.nrows
@@ -903,7 +907,7 @@ def bench_selector(args):
         A.m = synth.M_C5
         xh = synth.vector(k, 8, A.ncols, 0, A.m - 1)
         x = torch.from_numpy(xh.astype(np.int32)).to(dev)
-        r = ST.evaluate(A, model, x, reps=10, fixed=FORMATS, rounds=3)
+        r = ST.evaluate(A, model, x, reps=10, fixed=eval_fixed, rounds=3)
         want = orc.spmv(A, xh)
         for y in r["results"].values():
             same = same and np.array_equal(y.cpu().numpy(), want)
@@ -911,17 +915,17 @@ def bench_selector(args):
             if key.endswith("_us"):
                 tot[key] = tot.get(key, 0.0) + v
         nev += 1
-        if nev % 10 == 0:
-            log("held-out %d: heuristic %.1f us, learned %.1f us so far" % (nev, tot["heuristic_us"],
-                                                                              tot["learned_us"]))
+        if nev % 10 == 0 or not args.eval_rows:
+            log("held-out %d (matrix %d, %d rows, %d entries): totals so far %s, equal to the oracle %s"
+                % (nev, k, A.nrows, A.nnz, json.dumps({key: round(v, 1) for key, v in tot.items()}), same))
     if not nev:  # training only (--eval-mats 0)
         print(json.dumps({"trained": rep, "validation_block_cost_vs_best": block_cost, "model": model}), flush=True)
         return
     tot_h, tot_l = tot["heuristic_us"], tot["learned_us"]
-    fixed = {f: tot["fixed_%s_us" % f] for f in FORMATS}
-    best_fixed = min(fixed, key=fixed.get)
+    fixed = {f: tot["fixed_%s_us" % f] for f in eval_fixed}
+    best_fixed = min(fixed, key=fixed.get) if fixed else None
     log("held-out: heuristic %.1f us, learned %.1f us, best fixed %s %.1f us, all equal to the oracle %s"
-        % (tot_h, tot_l, best_fixed, fixed[best_fixed], same))
+        % (tot_h, tot_l, best_fixed, fixed.get(best_fixed, float("nan")), same))
     config = {"workload": "learned format selection mod 65521: %d training windows x %d blocks, %d held-out "
                           "matrices (%s), 32->64->64->6 FP32"
                           % (args.train_mats, args.train_blocks, nev,
@@ -931,7 +935,7 @@ def bench_selector(args):
              "heuristic_total_us": round(tot_h, 1), "learned_total_us": round(tot_l, 1),
              "fixed_total_us": {f: round(v, 1) for f, v in fixed.items()}, "best_fixed_format": best_fixed,
              "learned_speedup_vs_heuristic": round(tot_h / max(tot_l, 1e-9), 4),
-             "learned_speedup_vs_best_fixed": round(fixed[best_fixed] / max(tot_l, 1e-9), 4),
+             "learned_speedup_vs_best_fixed": round(fixed[best_fixed] / max(tot_l, 1e-9), 4) if fixed else None,
              "timing": "per matrix: median of 3 interleaved rounds of 10 launches",
              "results_equal_oracle": same}
     args.steps, args.warmup = nev, 0
@@ -966,7 +970,9 @@ def main():
     ap.add_argument("--train-mats", type=int, default=600)
     ap.add_argument("--train-blocks", type=int, default=16)
     ap.add_argument("--eval-mats", type=int, default=200)
-    ap.add_argument("--eval-rows", type=int, default=131072)
+    ap.add_argument("--eval-rows", type=int, default=131072, help="rows of each held-out matrix (0: whole)")
+    ap.add_argument("--eval-fixed", default="all",
+                    help="held-out matrices: formats forced on every block to compare with (comma list, or all)")
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
