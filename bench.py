@@ -219,6 +219,14 @@ def bench_spmv(args, big=True):
                 build_transpose=not big, compact_x=args.compact_x, col_sorted=args.col_sorted)
     if args.selector == "learned":
         opts["model_path"] = args.model
+    tuned = None
+    if args.tune_tiles:  # the library's tile-size tuner, as a caller keeping this matrix would run it
+        from paper_1004_3719_amd.ffx import tune_tile_entries
+        topts = {k: v for k, v in opts.items() if k != "tile_entries"}
+        best, us = tune_tile_entries(A.nrows, A.ncols, A.rowptr, A.col, A.val, m, s=1, reps=20, **topts)
+        opts["tile_entries"] = best
+        tuned = {"tile_entries": best, "candidates_us": {str(k): round(v, 2) for k, v in us.items()}}
+        log("tile sizes tuned: %s" % tuned)
     M = Matrix.from_synth(A, **opts)
     info = M.info()
     log("built in %.1fs: %s" % (time.time() - t0, info["format_blocks"]))
@@ -233,6 +241,28 @@ def bench_spmv(args, big=True):
     kernel_ms, ms = timed(lambda: M.spmv(x, y=y), args.steps, stream)
     log("%d steps: %.4f ms/step wall, %.4f ms/product (events)" % (args.steps, ms, kernel_ms))
     extra = {}
+    if not big:
+        # a launch-bound product: the same products replayed from a captured HIP graph, which
+        # takes the per-call host work (Python, the C ABI, the launch) out of the interval
+        want = y.clone()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            M.spmv(x, y=y)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        per_graph = 100
+        with torch.cuda.graph(g):
+            for _ in range(per_graph):
+                M.spmv(x, y=y)
+        replays = max(1, args.steps // per_graph)
+        g.replay()
+        torch.cuda.synchronize()
+        graph_ms, _ = timed(g.replay, replays, stream)
+        extra["graph_ms_per_product"] = round(graph_ms / per_graph, 5)
+        extra["graph_result_equal"] = bool(torch.equal(y, want))
+        log("graph replay: %.4f ms/product" % extra["graph_ms_per_product"])
     if not big:  # the plain configuration also times A^T x
         yt = torch.empty(A.ncols, dtype=torch.int32, device=dev)
         for _ in range(args.warmup):
@@ -300,6 +330,8 @@ def bench_spmv(args, big=True):
                 "-2..2, 60% +-1, x int32") if big else "plain SpMV mod 65521: n=10,000, 10 nnz/row, x int32"
     config = {"workload": workload, "n": A.nrows, "nnz": A.nnz, "m": m, "acc": args.acc, "selector": args.selector,
               "formats": info["format_blocks"], "col_sorted_groups": info["sg_groups"], "kernel_hash": khash}
+    if tuned:
+        config["tile_tuning"] = tuned
     line(A.nnz / (ms * 1e-3), ms, args, args.acc, config, roofline, cpu, extra)
 
 
@@ -956,6 +988,8 @@ def main():
                          "heuristic if the model is missing) or the plain heuristic")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
     ap.add_argument("--tile-entries", type=int, default=0)
+    ap.add_argument("--tune-tiles", action="store_true",
+                    help="c1/c2: pick tile_entries with the library's tuner (ffx_tune_tile_entries) before building")
     ap.add_argument("--compact-x", type=int, default=-1, choices=[-1, 0, 1],
                     help="16-bit copy of x for m <= 65536: -1 auto (x above 1 MiB), 0 never, 1 always")
     ap.add_argument("--fixed-format", default=None)

@@ -246,6 +246,7 @@ class Matrix:
 
     def __init__(self, handle):
         self._h = ctypes.c_void_p(handle)
+        self._dims = None  # (nrows, ncols), read once: a handle's shape never changes
 
     @classmethod
     def from_csr(cls, nrows, ncols, rowptr, col, val, m, stream=None, **opts):
@@ -324,10 +325,17 @@ class Matrix:
         return out[:n]
 
     # ----- products -----
+    def shape(self):
+        """(nrows, ncols) of the matrix."""
+        if self._dims is None:
+            inf = self.info()
+            self._dims = (inf["nrows"], inf["ncols"])
+        return self._dims
+
     def _prod(self, fn, trans, X, alpha, beta, Y, stream):
         import torch
-        inf = self.info()
-        nin, nout = (inf["nrows"], inf["ncols"]) if trans else (inf["ncols"], inf["nrows"])
+        nrows, ncols = self.shape()
+        nin, nout = (nrows, ncols) if trans else (ncols, nrows)
         px, s, ldx = _block(X, nin, "x")
         if Y is None:
             Y = torch.empty((nout,) if X.dim() == 1 else (nout, s), dtype=X.dtype, device=X.device)
@@ -384,7 +392,7 @@ class Matrix:
         """S_i = U^T A^i V over GF(2), i < L, for int32 tensors U, V of n x w packed words; returns S as an
         L x 32w x w int32 tensor (and A^L V)."""
         import torch
-        n = self.info()["nrows"]
+        n = self.shape()[0]
         for t in (U, V):
             if t.dtype != torch.int32:
                 raise TypeError("GF(2) blocks are int32 tensors of packed words")
@@ -401,7 +409,7 @@ class Matrix:
 
     def power(self, k, V, W=None, stream=None):
         import torch
-        n = self.info()["nrows"]
+        n = self.shape()[0]
         pv, s, ldv = _block(V, n, "V")
         if W is None:
             W = torch.empty_like(V)
@@ -412,7 +420,7 @@ class Matrix:
 
     def sequence(self, U, V, L, want_last=False, stream=None):
         import torch
-        n = self.info()["nrows"]
+        n = self.shape()[0]
         pu, s, ldu = _block(U, n, "U")
         pv, sv, ldv = _block(V, n, "V")
         if sv != s or U.dtype != V.dtype:
