@@ -213,6 +213,68 @@ __global__ void __launch_bounds__(PM_TILE) k_polymul4(const uint32_t* __restrict
     if (t + v < len) C[(int64_t)blockIdx.y * sc + t + v] = acc[v].reduce(F);
 }
 
+// Products with at most PM_TILE output coefficients per entry and A entries of at
+// most PMS_MAXA coefficients: the lower levels of the recursion, where a product
+// is a few thousand multiply-adds per entry and the tile kernel's time goes to a
+// barrier and a round trip to memory per inner index. Here one workgroup per
+// output entry stages every A and B coefficient the entry needs in LDS at once,
+// and four groups of PM_TILE lanes each take every fourth inner index q; the
+// four partial sums, reduced, meet in LDS.
+constexpr int PMS_MAXA = PM_TILE + 1;
+constexpr int PMS_NT = 4 * PM_TILE;
+inline size_t polymul_small_lds(int Q, int64_t la, int64_t len) {
+  return ((size_t)Q * la + (size_t)Q * (len + la - 1) + 3 * PM_TILE) * sizeof(uint32_t);
+}
+template <bool MERS>
+__global__ void __launch_bounds__(PMS_NT) k_polymul_small(const uint32_t* __restrict__ A, int64_t sa, int la,
+                                                          const uint32_t* __restrict__ B, int64_t sb, int64_t lb,
+                                                          uint32_t* __restrict__ C, int64_t sc, int64_t k0, int len,
+                                                          int Q, int NC, Field F) {
+  extern __shared__ uint32_t pms[];
+  const int tid = threadIdx.x;
+  const int r = blockIdx.x / NC, c = blockIdx.x % NC;
+  const int nb = len + la - 1;  // B[k0 - (la - 1) .. k0 + len - 1]
+  uint32_t* As = pms;
+  uint32_t* Bs = pms + Q * la;
+  uint32_t* part_s = Bs + Q * nb;
+  for (int i = tid; i < Q * la; i += PMS_NT) {
+    const int q = i / la, j = i - q * la;
+    As[i] = A[(int64_t)(r * Q + q) * sa + j];
+  }
+  const int64_t b0 = k0 - (la - 1);
+  for (int i = tid; i < Q * nb; i += PMS_NT) {
+    const int q = i / nb, u = i - q * nb;
+    const int64_t idx = b0 + u;
+    Bs[i] = (idx >= 0 && idx < lb) ? B[(int64_t)(q * NC + c) * sb + idx] : 0u;
+  }
+  __syncthreads();
+  const int t = tid % PM_TILE, part = tid / PM_TILE;
+  Acc96<MERS> acc;
+  if (t < len) {
+    // output k0 + t meets A[j] and B[k0 + t - j] = Bs[t - j + la - 1], for j with 0 <= k0 + t - j < lb
+    const int64_t kt = k0 + t;
+    const int jlo = (int)std::max<int64_t>(0, kt - (lb - 1));
+    const int jhi = (int)std::min<int64_t>(la - 1, kt);
+    for (int q = part; q < Q; q += 4) {
+      const uint32_t* a = As + q * la;
+      const uint32_t* b = Bs + q * nb + t + la - 1;
+      for (int j = jlo; j <= jhi; ++j) acc.add((uint64_t)a[j] * b[-j]);
+    }
+  }
+  const uint32_t v = acc.reduce(F);
+  if (part > 0) part_s[(part - 1) * PM_TILE + t] = v;
+  __syncthreads();
+  if (part == 0 && t < len) {
+    uint32_t sum = v;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {  // residues below p < 2^31: a sum of two stays below 2^32
+      sum += part_s[k * PM_TILE + t];
+      sum = sum >= F.p ? sum - F.p : sum;
+    }
+    C[(int64_t)blockIdx.x * sc + t] = sum;
+  }
+}
+
 // One-order-at-a-time basis (M-Basis) of the m x n series G to order sg <= SB_LEAF
 // with shifted degrees d (in/out, device). M: m x m entries of sm >= sg + 1 coefficients.
 // LEAF_NT lanes: the residual takes 8 lanes per entry and the basis update 4 lanes per entry, each
@@ -651,6 +713,18 @@ static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B
   if (len <= 0) return;
   const int64_t nt = g_ntt_min.load();
   if (nt > 0 && la >= nt && lb >= nt && polymul_ntt(A, sa, la, B, sb, lb, C, sc, k0, len, R, Q, NC, F, st)) return;
+  if (len <= PM_TILE && la <= PMS_MAXA && polymul_small_lds(Q, std::max<int64_t>(la, 1), len) <= 64 * 1024) {
+    const int la1 = (int)std::max<int64_t>(la, 1);
+    const size_t lds = polymul_small_lds(Q, la1, len);
+    if (F.mersenne)
+      hipLaunchKernelGGL((k_polymul_small<true>), dim3((unsigned)(R * NC)), dim3(PMS_NT), lds, st, A, sa, la1, B, sb,
+                         lb, C, sc, k0, (int)len, Q, NC, F);
+    else
+      hipLaunchKernelGGL((k_polymul_small<false>), dim3((unsigned)(R * NC)), dim3(PMS_NT), lds, st, A, sa, la1, B, sb,
+                         lb, C, sc, k0, (int)len, Q, NC, F);
+    FFX_HIP(hipGetLastError());
+    return;
+  }
   const int64_t tiles4 = (len + PM_OUT - 1) / PM_OUT;
   if (tiles4 * R * NC >= 2048) {  // enough four-per-lane tiles to fill the GPU
     dim3 grid4((unsigned)tiles4, (unsigned)(R * NC));
