@@ -213,27 +213,33 @@ __global__ void __launch_bounds__(PM_TILE) k_polymul4(const uint32_t* __restrict
     if (t + v < len) C[(int64_t)blockIdx.y * sc + t + v] = acc[v].reduce(F);
 }
 
-// Products with at most PM_TILE output coefficients per entry and A entries of at
-// most PMS_MAXA coefficients: the lower levels of the recursion, where a product
-// is a few thousand multiply-adds per entry and the tile kernel's time goes to a
-// barrier and a round trip to memory per inner index. Here one workgroup per
-// output entry stages every A and B coefficient the entry needs in LDS at once,
-// and four groups of PM_TILE lanes each take every fourth inner index q; the
-// four partial sums, reduced, meet in LDS.
+// Products whose A entries have at most PMS_MAXA coefficients and whose output
+// entries at most PMS_MAX_TILES * PM_TILE: the lower levels of the recursion,
+// where a product is a few thousand multiply-adds per entry and the tile
+// kernel's time goes to a barrier and a round trip to memory per inner index.
+// Here one workgroup per output entry and PM_TILE outputs stages every A and B
+// coefficient it needs in LDS at once, and four groups of PM_TILE lanes each
+// take every fourth inner index q; the four partial sums, reduced, meet in LDS.
 constexpr int PMS_MAXA = PM_TILE + 1;
 constexpr int PMS_NT = 4 * PM_TILE;
-inline size_t polymul_small_lds(int Q, int64_t la, int64_t len) {
-  return ((size_t)Q * la + (size_t)Q * (len + la - 1) + 3 * PM_TILE) * sizeof(uint32_t);
+constexpr int PMS_MAX_TILES = 4;  // longer outputs go to the tile kernels
+inline size_t polymul_small_lds(int Q, int64_t la) {
+  return ((size_t)Q * la + (size_t)Q * (PM_TILE + la - 1) + 3 * PM_TILE) * sizeof(uint32_t);
 }
 template <bool MERS>
 __global__ void __launch_bounds__(PMS_NT) k_polymul_small(const uint32_t* __restrict__ A, int64_t sa, int la,
                                                           const uint32_t* __restrict__ B, int64_t sb, int64_t lb,
-                                                          uint32_t* __restrict__ C, int64_t sc, int64_t k0, int len,
+                                                          uint32_t* __restrict__ C, int64_t sc, int64_t k0, int64_t len,
                                                           int Q, int NC, Field F) {
   extern __shared__ uint32_t pms[];
   const int tid = threadIdx.x;
   const int r = blockIdx.x / NC, c = blockIdx.x % NC;
-  const int nb = len + la - 1;  // B[k0 - (la - 1) .. k0 + len - 1]
+  // this workgroup's PM_TILE outputs: coefficients t0 .. t0 + tl - 1 of the entry
+  const int64_t t0 = (int64_t)blockIdx.y * PM_TILE;
+  const int tl = (int)std::min<int64_t>(PM_TILE, len - t0);
+  k0 += t0;
+  C += t0;
+  const int nb = tl + la - 1;  // B[k0 - (la - 1) .. k0 + tl - 1]
   uint32_t* As = pms;
   uint32_t* Bs = pms + Q * la;
   uint32_t* part_s = Bs + Q * nb;
@@ -250,7 +256,7 @@ __global__ void __launch_bounds__(PMS_NT) k_polymul_small(const uint32_t* __rest
   __syncthreads();
   const int t = tid % PM_TILE, part = tid / PM_TILE;
   Acc96<MERS> acc;
-  if (t < len) {
+  if (t < tl) {
     // output k0 + t meets A[j] and B[k0 + t - j] = Bs[t - j + la - 1], for j with 0 <= k0 + t - j < lb
     const int64_t kt = k0 + t;
     const int jlo = (int)std::max<int64_t>(0, kt - (lb - 1));
@@ -264,7 +270,7 @@ __global__ void __launch_bounds__(PMS_NT) k_polymul_small(const uint32_t* __rest
   const uint32_t v = acc.reduce(F);
   if (part > 0) part_s[(part - 1) * PM_TILE + t] = v;
   __syncthreads();
-  if (part == 0 && t < len) {
+  if (part == 0 && t < tl) {
     uint32_t sum = v;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {  // residues below p < 2^31: a sum of two stays below 2^32
@@ -713,15 +719,17 @@ static void polymul(const uint32_t* A, int64_t sa, int64_t la, const uint32_t* B
   if (len <= 0) return;
   const int64_t nt = g_ntt_min.load();
   if (nt > 0 && la >= nt && lb >= nt && polymul_ntt(A, sa, la, B, sb, lb, C, sc, k0, len, R, Q, NC, F, st)) return;
-  if (len <= PM_TILE && la <= PMS_MAXA && polymul_small_lds(Q, std::max<int64_t>(la, 1), len) <= 64 * 1024) {
+  const int64_t tiles = (len + PM_TILE - 1) / PM_TILE;
+  if (tiles <= PMS_MAX_TILES && la <= PMS_MAXA && polymul_small_lds(Q, std::max<int64_t>(la, 1)) <= 64 * 1024) {
     const int la1 = (int)std::max<int64_t>(la, 1);
-    const size_t lds = polymul_small_lds(Q, la1, len);
+    const size_t lds = polymul_small_lds(Q, la1);
+    const dim3 grid((unsigned)(R * NC), (unsigned)tiles);
     if (F.mersenne)
-      hipLaunchKernelGGL((k_polymul_small<true>), dim3((unsigned)(R * NC)), dim3(PMS_NT), lds, st, A, sa, la1, B, sb,
-                         lb, C, sc, k0, (int)len, Q, NC, F);
+      hipLaunchKernelGGL((k_polymul_small<true>), grid, dim3(PMS_NT), lds, st, A, sa, la1, B, sb, lb, C, sc, k0, len,
+                         Q, NC, F);
     else
-      hipLaunchKernelGGL((k_polymul_small<false>), dim3((unsigned)(R * NC)), dim3(PMS_NT), lds, st, A, sa, la1, B, sb,
-                         lb, C, sc, k0, (int)len, Q, NC, F);
+      hipLaunchKernelGGL((k_polymul_small<false>), grid, dim3(PMS_NT), lds, st, A, sa, la1, B, sb, lb, C, sc, k0, len,
+                         Q, NC, F);
     FFX_HIP(hipGetLastError());
     return;
   }
@@ -747,18 +755,30 @@ struct SbCtx {
   Field F;
   int m, n;
   hipStream_t st;
-  int32_t* d_dev;  // m shifted degrees on the device
+  int32_t* d_dev;       // m shifted degrees on the device: the leaves read and update them there
+  bool d_host = true;   // the host copy of the degrees is current
 };
 
+// Nodes of at most this order take no degrees from the device: their lengths are the bound
+// sigma + 1 (the extra coefficients come out zero), so a subtree of such nodes is queued without
+// waiting for the GPU; larger nodes read the degrees back to size their products exactly.
+constexpr int64_t SB_EXACT_ABOVE = 256;
+
+// The host copy of the degrees, read back when a leaf has run since the last read.
+static void host_degrees(SbCtx& X, std::vector<int32_t>& d) {
+  if (X.d_host) return;
+  FFX_HIP(hipMemcpyAsync(d.data(), X.d_dev, X.m * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
+  FFX_HIP(hipStreamSynchronize(X.st));
+  X.d_host = true;
+}
+
 // Basis of G (m x n entries, stride sg, order sigma) into M (m x m entries, stride sm >= sigma + 1,
-// zero beyond the returned length); d: shifted degrees in and out. Returns the number of
-// coefficients of M that can be nonzero.
+// zero beyond the returned length); the shifted degrees are updated in X.d_dev (and in d when it is
+// read back). Returns a bound on the number of coefficients of M that can be nonzero.
 static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, std::vector<int32_t>& d, uint32_t* M,
                        int64_t sm) {
   const int m = X.m, n = X.n;
-  const int32_t dmin = *std::min_element(d.begin(), d.end());
   if (sigma <= SB_LEAF) {
-    FFX_HIP(hipMemcpyAsync(X.d_dev, d.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, X.st));
     if (X.F.mersenne)
       hipLaunchKernelGGL((k_mbasis_leaf<true>), dim3(1), dim3(LEAF_NT), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M,
                          sm, X.F);
@@ -766,10 +786,14 @@ static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, s
       hipLaunchKernelGGL((k_mbasis_leaf<false>), dim3(1), dim3(LEAF_NT), 0, X.st, G, sg, m, n, (int)sigma, X.d_dev, M,
                          sm, X.F);
     FFX_HIP(hipGetLastError());
-    FFX_HIP(hipMemcpyAsync(d.data(), X.d_dev, m * sizeof(int32_t), hipMemcpyDeviceToHost, X.st));
-    FFX_HIP(hipStreamSynchronize(X.st));
-    const int32_t dmax = *std::max_element(d.begin(), d.end());
-    return std::min<int64_t>(sigma + 1, (int64_t)dmax - dmin + 1);
+    X.d_host = false;
+    return sigma + 1;
+  }
+  const bool exact = sigma > SB_EXACT_ABOVE;
+  int32_t dmin = 0;
+  if (exact) {
+    host_degrees(X, d);
+    dmin = *std::min_element(d.begin(), d.end());
   }
   const int64_t s1 = sigma / 2, s2 = sigma - s1;
   uint32_t *M1 = nullptr, *R = nullptr, *M2 = nullptr;
@@ -785,8 +809,12 @@ static int64_t pmbasis(SbCtx& X, const uint32_t* G, int64_t sg, int64_t sigma, s
     // R = [x^s1 .. x^(sigma-1)] (M1 G)
     polymul(M1, s1 + 1, l1, G, sg, sigma, R, s2, s1, s2, m, m, n, X.F, X.st);
     const int64_t l2 = pmbasis(X, R, s2, s2, d, M2, s2 + 1);
-    const int32_t dmax = *std::max_element(d.begin(), d.end());
-    const int64_t len = std::min<int64_t>(std::min<int64_t>(sigma + 1, l1 + l2 - 1), (int64_t)dmax - dmin + 1);
+    int64_t len = std::min<int64_t>(sigma + 1, l1 + l2 - 1);
+    if (exact) {
+      host_degrees(X, d);
+      const int32_t dmax = *std::max_element(d.begin(), d.end());
+      len = std::min<int64_t>(len, (int64_t)dmax - dmin + 1);
+    }
     polymul(M2, s2 + 1, l2, M1, s1 + 1, l1, M, sm, 0, len, m, m, m, X.F, X.st);
     if (len < sm) FFX_HIP(hipMemset2DAsync(M + len, sm * 4, 0, (sm - len) * 4, (size_t)m * m, X.st));
     (void)hipFreeAsync(M1, X.st);
@@ -847,8 +875,10 @@ void sigma_basis(uint32_t p, int m, int n, int64_t sigma, const uint32_t* G, int
   if (hipMallocAsync((void**)&X.d_dev, SB_MAXM * sizeof(int32_t), st) != hipSuccess)
     fail(FFX_ENOMEM, "order basis workspace allocation failed");
   try {
+    FFX_HIP(hipMemcpyAsync(X.d_dev, d.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st));
     const int64_t len = pmbasis(X, G, ldg, sigma, d, M, ldm);
     if (len < ldm) FFX_HIP(hipMemset2DAsync(M + len, ldm * 4, 0, (ldm - len) * 4, (size_t)m * m, st));
+    host_degrees(X, d);
   } catch (...) {
     (void)hipFreeAsync(X.d_dev, st);
     throw;
