@@ -363,9 +363,23 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
     // the scales are divided out once, when the leaf writes its basis. The
     // pivot column of the later rows becomes zero and is never written: the
     // lanes read it in place, and the scans skip the columns of earlier pivots.
+    // Every lane keeps the row order in registers (indexed by the unrolled pivot counter below) and
+    // works on one fixed (position lp of a later row, column lcol of [residual | T]) for the whole
+    // order: a pivot step is then one read of the pivot row, one read of the lane's three operands
+    // and one barrier.
+    int ord[SB_MAXM];
+#pragma unroll
+    for (int q = 0; q < SB_MAXM; ++q) ord[q] = q < m ? order[q] : 0;
+    constexpr int EW = SB_MAXN + SB_MAXM;
+    static_assert(SB_MAXM * EW <= LEAF_NT, "one lane per entry of [residual | T]");
+    const int lp = tid / EW, lcol = tid % EW;
+    const bool lane_on = tid < SB_MAXM * EW && lp < m && (lcol < SB_MAXN ? lcol < n : lcol - SB_MAXN < m);
+    const int lj = lane_on ? order[lp] : 0;
     uint32_t used = 0;  // pivot columns so far (the same in every lane)
-    for (int oi = 0; oi < m; ++oi) {
-      const int i = order[oi];
+#pragma unroll
+    for (int oi = 0; oi < SB_MAXM; ++oi) {
+      if (oi >= m) break;
+      const int i = ord[oi];
       int first = -1;
       uint32_t rowv[SB_MAXN];
 #pragma unroll
@@ -376,23 +390,23 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
       if (first < 0) continue;  // the same answer in every lane
       const uint32_t pv = rowv[first];
       used |= 1u << first;
-      const int w = n + m, later = m - oi - 1;
-      for (int task = tid; task < later * w; task += LEAF_NT) {
-        const int pos = oi + 1 + task / w, col = task % w;
-        if (col < n && ((used >> col) & 1u)) continue;  // this pivot's column and the earlier ones
-        const int j = order[pos];
-        const uint32_t x = Dl[j][first];
-        if (!x) continue;
-        const uint32_t nx = F.p - x;
-        if (col < n) {
-          const uint32_t v = fmul(pv, Dl[j][col], F) + fmul(nx, Dl[i][col], F);
-          Dl[j][col] = v >= F.p ? v - F.p : v;
-        } else {
-          const uint32_t v = fmul(pv, T[j][col - n], F) + fmul(nx, T[i][col - n], F);
-          T[j][col - n] = v >= F.p ? v - F.p : v;
+      if (lane_on && lp > oi) {
+        const uint32_t x = Dl[lj][first];
+        if (lcol < SB_MAXN) {
+          if (!((used >> lcol) & 1u)) {  // neither this pivot's column nor an earlier one
+            if (x) {
+              const uint32_t v = fmul(pv, Dl[lj][lcol], F) + fmul(F.p - x, Dl[i][lcol], F);
+              Dl[lj][lcol] = v >= F.p ? v - F.p : v;
+            }
+          } else if (lcol == first && x) {  // the lane of the pivot column scales the row
+            sc[lj] = fmul(sc[lj], pv, F);
+          }
+        } else if (x) {
+          const int tc = lcol - SB_MAXN;
+          const uint32_t v = fmul(pv, T[lj][tc], F) + fmul(F.p - x, T[i][tc], F);
+          T[lj][tc] = v >= F.p ? v - F.p : v;
         }
       }
-      if (tid > oi && tid < m && Dl[order[tid]][first]) sc[order[tid]] = fmul(sc[order[tid]], pv, F);
       if (tid == 0) {
         piv[i] = 1;
         dl[i] += 1;
