@@ -375,47 +375,57 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
     const int lp = tid / EW, lcol = tid % EW;
     const bool lane_on = tid < SB_MAXM * EW && lp < m && (lcol < SB_MAXN ? lcol < n : lcol - SB_MAXN < m);
     const int lj = lane_on ? order[lp] : 0;
-    uint32_t used = 0;  // pivot columns so far (the same in every lane)
+    // The lane's own entry stays in a register (no other lane writes it), the scale of row lj is
+    // kept by the row's column-0 lane, and the pivots are marked after the loop.
+    uint32_t own = 0u, scr = 0u;
+    if (lane_on) {
+      own = lcol < SB_MAXN ? Dl[lj][lcol] : T[lj][lcol - SB_MAXN];
+      if (lcol == 0) scr = sc[lj];
+    }
+    uint32_t used = 0, pivmask = 0;  // pivot columns and pivot rows so far (the same in every lane)
 #pragma unroll
     for (int oi = 0; oi < SB_MAXM; ++oi) {
       if (oi >= m) break;
       const int i = ord[oi];
-      int first = -1;
       uint32_t rowv[SB_MAXN];
 #pragma unroll
       for (int c = 0; c < SB_MAXN; ++c) rowv[c] = (c < n && !((used >> c) & 1u)) ? Dl[i][c] : 0u;
+      const uint32_t prv = lane_on ? (lcol < SB_MAXN ? Dl[i][lcol] : T[i][lcol - SB_MAXN]) : 0u;
+      int first = -1;
 #pragma unroll
       for (int c = SB_MAXN - 1; c >= 0; --c)
         if (rowv[c]) first = c;
       if (first < 0) continue;  // the same answer in every lane
-      const uint32_t pv = rowv[first];
+      uint32_t pv = rowv[0];
+#pragma unroll
+      for (int c = 1; c < SB_MAXN; ++c)
+        if (first == c) pv = rowv[c];
       used |= 1u << first;
+      pivmask |= 1u << i;
       if (lane_on && lp > oi) {
         const uint32_t x = Dl[lj][first];
-        if (lcol < SB_MAXN) {
-          if (!((used >> lcol) & 1u)) {  // neither this pivot's column nor an earlier one
-            if (x) {
-              const uint32_t v = fmul(pv, Dl[lj][lcol], F) + fmul(F.p - x, Dl[i][lcol], F);
-              Dl[lj][lcol] = v >= F.p ? v - F.p : v;
-            }
-          } else if (lcol == first && x) {  // the lane of the pivot column scales the row
-            sc[lj] = fmul(sc[lj], pv, F);
+        if (x) {
+          if (lcol == 0) scr = fmul(scr, pv, F);
+          if (lcol >= SB_MAXN || !((used >> lcol) & 1u)) {  // neither this pivot's column nor an earlier one
+            const uint32_t v = fmul(pv, own, F) + fmul(F.p - x, prv, F);
+            own = v >= F.p ? v - F.p : v;
+            if (lcol < SB_MAXN) Dl[lj][lcol] = own;
+            else T[lj][lcol - SB_MAXN] = own;
           }
-        } else if (x) {
-          const int tc = lcol - SB_MAXN;
-          const uint32_t v = fmul(pv, T[lj][tc], F) + fmul(F.p - x, T[i][tc], F);
-          T[lj][tc] = v >= F.p ? v - F.p : v;
         }
-      }
-      if (tid == 0) {
-        piv[i] = 1;
-        dl[i] += 1;
       }
       __syncthreads();
     }
+    if (lane_on && lcol == 0) sc[lj] = scr;
+    if (tid < m && ((pivmask >> tid) & 1u)) {
+      piv[tid] = 1;
+      dl[tid] += 1;
+    }
+    __syncthreads();
     // M <- diag(x^piv) T M: four lanes per entry (i, c), each over every fourth coefficient, T's row
     // in registers. M has degree <= k before order k, so only coefficients 0..k+1 change (the
-    // buffers hold zeros above).
+    // buffers hold zeros above). The 64 lanes of a wave share the row i, so T's zero entries (rows
+    // no pivot was combined into) are skipped without divergence.
     const int nxt = cur ^ 1;
     {
       const int e = tid >> 2, j0 = tid & 3;
@@ -436,13 +446,13 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
                 uint64_t g = 0;
 #pragma unroll
                 for (int q = q0; q < q0 + 4; ++q)
-                  if (q < m) g += (uint64_t)t[q] * Ms[cur][q][c][js];
+                  if (q < m && t[q]) g += (uint64_t)t[q] * Ms[cur][q][c][js];
                 acc.lo += (g & 0x7FFFFFFFull) + (g >> 31);
               }
             } else {
 #pragma unroll
               for (int q = 0; q < SB_MAXM; ++q)
-                if (q < m) acc.add((uint64_t)t[q] * Ms[cur][q][c][js]);
+                if (q < m && t[q]) acc.add((uint64_t)t[q] * Ms[cur][q][c][js]);
             }
             out = acc.reduce(F);
           }
