@@ -458,6 +458,16 @@ def bench_rank(args):
     planted = A.nrows - 1000
     log("sequence %.3f s, sigma basis + rank %.3f s: rank %d (planted %d), deg det %d, codeg %d"
         % (t1 - t0, t2 - t1, r, planted, D, e))
+    ntt_times = {}
+    if args.ntt_thresholds:  # steps 2-3 again with other cut-overs to the NTT products
+        from paper_1004_3719_amd.ffx import set_ntt_threshold
+        for th in (int(v) for v in args.ntt_thresholds.split(",")):
+            set_ntt_threshold(th)
+            ta = time.perf_counter()
+            r2 = sequence_rank(S, A.m)
+            ntt_times[th] = round(time.perf_counter() - ta, 4)
+            log("NTT above %d coefficients: sigma basis + rank %.3f s, rank %d" % (th, ntt_times[th], r2[0]))
+        set_ntt_threshold(1024)
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle's order basis, one order at a time, on a bounded prefix of the same sequence
@@ -988,6 +998,8 @@ def main():
                          "heuristic if the model is missing) or the plain heuristic")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1004_3719_amd", "models", "selector.bin"))
     ap.add_argument("--tile-entries", type=int, default=0)
+    ap.add_argument("--ntt-thresholds", default="",
+                    help="rank: also time steps 2-3 with these NTT cut-overs (comma list of lengths)")
     ap.add_argument("--tune-tiles", action="store_true",
                     help="c1/c2: pick tile_entries with the library's tuner (ffx_tune_tile_entries) before building")
     ap.add_argument("--compact-x", type=int, default=-1, choices=[-1, 0, 1],
