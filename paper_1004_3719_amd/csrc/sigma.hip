@@ -299,6 +299,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
   __shared__ int dl[SB_MAXM];
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   __shared__ int order[SB_MAXM];                // rows by (shifted degree, index)
+  __shared__ uint32_t rinfo[SB_MAXM][2];        // per position: first nonzero unused column, its value
   const int tid = threadIdx.x;
   for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += LEAF_NT) {
     int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
@@ -364,56 +365,63 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
     // pivot column of the later rows becomes zero and is never written: the
     // lanes read it in place, and the scans skip the columns of earlier pivots.
     // Every lane keeps the row order in registers (indexed by the unrolled pivot counter below) and
-    // works on one fixed (position lp of a later row, column lcol of [residual | T]) for the whole
-    // order: a pivot step is then one read of the pivot row, one read of the lane's three operands
-    // and one barrier.
+    // works on one fixed entry of [residual | T] for the whole order: half a wave per row (lane lcol
+    // < 8 a residual column, 8 <= lcol < 24 a column of T), so a row's lanes trade values by
+    // shuffles. The lane's own entry stays in a register (no other lane writes it) and goes to LDS
+    // for the pivot steps of later rows; the scale of a row is kept by its lane 0. After each pivot
+    // step the lanes of every later row publish the row's first nonzero unused column and its value
+    // (rinfo), so a pivot step reads two words and the lane's column of the pivot row, and a row left
+    // with zeros costs one read and no barrier.
     int ord[SB_MAXM];
 #pragma unroll
     for (int q = 0; q < SB_MAXM; ++q) ord[q] = q < m ? order[q] : 0;
-    constexpr int EW = SB_MAXN + SB_MAXM;
-    static_assert(SB_MAXM * EW <= LEAF_NT, "one lane per entry of [residual | T]");
+    constexpr int EW = WAVE / 2;
+    static_assert(SB_MAXN + SB_MAXM <= EW && SB_MAXM * EW <= LEAF_NT && SB_MAXN <= 32, "lanes of the elimination");
     const int lp = tid / EW, lcol = tid % EW;
-    const bool lane_on = tid < SB_MAXM * EW && lp < m && (lcol < SB_MAXN ? lcol < n : lcol - SB_MAXN < m);
+    const bool el_wave = tid < SB_MAXM * EW;  // whole waves
+    const bool lane_on = el_wave && lp < m && (lcol < SB_MAXN ? lcol < n : lcol - SB_MAXN < m);
     const int lj = lane_on ? order[lp] : 0;
-    // The lane's own entry stays in a register (no other lane writes it), the scale of row lj is
-    // kept by the row's column-0 lane, and the pivots are marked after the loop.
+    const int rowbase = tid & ~(EW - 1);
     uint32_t own = 0u, scr = 0u;
     if (lane_on) {
       own = lcol < SB_MAXN ? Dl[lj][lcol] : T[lj][lcol - SB_MAXN];
       if (lcol == 0) scr = sc[lj];
     }
     uint32_t used = 0, pivmask = 0;  // pivot columns and pivot rows so far (the same in every lane)
+    // rinfo of the rows at positions after `after`, from their lanes (called by whole waves)
+    auto publish = [&](int after) {
+      const uint64_t bal = __ballot(lane_on && lcol < SB_MAXN && !((used >> lcol) & 1u) && own != 0u);
+      const uint32_t rm = (uint32_t)(bal >> (tid & EW)) & ((1u << SB_MAXN) - 1u);
+      const int f = rm ? __builtin_ctz(rm) : -1;
+      const uint32_t fv = (uint32_t)__shfl((int)own, rowbase + (f < 0 ? 0 : f));
+      if (lane_on && lcol == 0 && lp > after) {
+        rinfo[lp][0] = (uint32_t)f;
+        rinfo[lp][1] = fv;
+      }
+    };
+    if (el_wave) publish(-1);
+    __syncthreads();
 #pragma unroll
     for (int oi = 0; oi < SB_MAXM; ++oi) {
       if (oi >= m) break;
       const int i = ord[oi];
-      uint32_t rowv[SB_MAXN];
-#pragma unroll
-      for (int c = 0; c < SB_MAXN; ++c) rowv[c] = (c < n && !((used >> c) & 1u)) ? Dl[i][c] : 0u;
+      const int first = (int)rinfo[oi][0];
+      const uint32_t pv = rinfo[oi][1];
       const uint32_t prv = lane_on ? (lcol < SB_MAXN ? Dl[i][lcol] : T[i][lcol - SB_MAXN]) : 0u;
-      int first = -1;
-#pragma unroll
-      for (int c = SB_MAXN - 1; c >= 0; --c)
-        if (rowv[c]) first = c;
       if (first < 0) continue;  // the same answer in every lane
-      uint32_t pv = rowv[0];
-#pragma unroll
-      for (int c = 1; c < SB_MAXN; ++c)
-        if (first == c) pv = rowv[c];
       used |= 1u << first;
       pivmask |= 1u << i;
-      if (lane_on && lp > oi) {
-        const uint32_t x = Dl[lj][first];
-        if (x) {
-          if (lcol == 0) scr = fmul(scr, pv, F);
-          if (lcol >= SB_MAXN || !((used >> lcol) & 1u)) {  // neither this pivot's column nor an earlier one
-            const uint32_t v = fmul(pv, own, F) + fmul(F.p - x, prv, F);
-            own = v >= F.p ? v - F.p : v;
-            if (lcol < SB_MAXN) Dl[lj][lcol] = own;
-            else T[lj][lcol - SB_MAXN] = own;
-          }
+      const uint32_t x = (uint32_t)__shfl((int)own, rowbase + first);  // this row's entry in the pivot column
+      if (lane_on && lp > oi && x) {
+        if (lcol == 0) scr = fmul(scr, pv, F);
+        if (lcol >= SB_MAXN || !((used >> lcol) & 1u)) {  // neither this pivot's column nor an earlier one
+          const uint32_t v = fmul(pv, own, F) + fmul(F.p - x, prv, F);
+          own = v >= F.p ? v - F.p : v;
+          if (lcol < SB_MAXN) Dl[lj][lcol] = own;
+          else T[lj][lcol - SB_MAXN] = own;
         }
       }
+      if (el_wave) publish(oi);
       __syncthreads();
     }
     if (lane_on && lcol == 0) sc[lj] = scr;
