@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
   __shared__ uint32_t Ms[2][SB_MAXM][SB_MAXM][LC];
   __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF + 1];  // padded: the 8 columns fall in different banks
   __shared__ uint32_t Dl[SB_MAXM][SB_MAXN];      // residual coefficient, reduced in place
-  __shared__ uint32_t T[SB_MAXM][SB_MAXM];       // this order's row transformation
+  __shared__ __align__(16) uint32_t T[SB_MAXM][SB_MAXM];  // this order's row transformation
   __shared__ int piv[SB_MAXM];
   __shared__ int dl[SB_MAXM];
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
@@ -441,7 +441,14 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
       if (i < m && c < m) {
         uint32_t t[SB_MAXM];
 #pragma unroll
-        for (int q = 0; q < SB_MAXM; ++q) t[q] = q < m ? T[i][q] : 0u;
+        for (int q4 = 0; q4 < SB_MAXM; q4 += 4) {  // T's row in 16-byte reads
+          typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+          const u32x4_t tv = *(const u32x4_t*)&T[i][q4];
+          t[q4] = q4 < m ? tv.x : 0u;
+          t[q4 + 1] = q4 + 1 < m ? tv.y : 0u;
+          t[q4 + 2] = q4 + 2 < m ? tv.z : 0u;
+          t[q4 + 3] = q4 + 3 < m ? tv.w : 0u;
+        }
         const int sh = piv[i];
         for (int j = j0; j <= k + 1 && j < LC; j += 4) {
           const int js = j - sh;
