@@ -25,10 +25,14 @@ def dev():
 @pytest.mark.parametrize("m,n,sig,shift_kind,p", [
     (2, 1, 1, "zero", 65521), (2, 1, 40, "zero", M31), (4, 2, 33, "gen", 65521), (16, 8, 31, "gen", M31),
     (16, 8, 32, "gen", M31), (16, 8, 33, "gen", 65521), (16, 8, 64, "zero", M31), (16, 8, 100, "gen", M31),
-    (6, 3, 257, "rand", 65521), (16, 8, 300, "gen", M31), (5, 5, 70, "rand", 3), (16, 1, 90, "rand", 65521)])
+    (6, 3, 257, "rand", 65521), (16, 8, 300, "gen", M31), (5, 5, 70, "rand", 3), (16, 1, 90, "rand", 65521),
+    (16, 8, 600, "gen", M31), (16, 8, 1100, "gen", 65521)])
 def test_sigma_basis_matches_oracle(dev, m, n, sig, shift_kind, p):
     """Random series of every shape the entry point takes, orders around the leaf size (32) and
-    across several levels of the recursion, zero / generator / random shifts, small and large p."""
+    across several levels of the recursion, zero / generator / random shifts, small and large p.
+    Orders 600 and 1,100 reach the levels whose lengths come from the degrees read back (above 256)
+    below ones queued with bound lengths, the small-product kernel with several output tiles and
+    the tile kernel for A entries of more than 257 coefficients."""
     from paper_1004_3719_amd import sigma_basis
     G = synth.vector(m * 1000 + n * 10 + sig, 7, m * n * sig, 0, p - 1).reshape(m, n, sig)
     shift = {"zero": [0] * m, "gen": [0] * (m // 2) + [1] * (m - m // 2),
