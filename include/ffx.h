@@ -35,7 +35,9 @@
  *    allocated by the first product that needs it, freed by destroy): the
  *    first product on a second stream synchronizes the device once, and from
  *    then on products on different streams are ordered on that temporary by
- *    an event (they serialize rather than overlap).
+ *    an event (they serialize rather than overlap). Such products are not
+ *    for HIP graph capture (the allocation and the synchronization are not
+ *    stream operations); ffx_spmv_noalloc is.
  */
 #ifndef FFX_H
 #define FFX_H
@@ -230,7 +232,7 @@ ffx_status ffx_spmv_t(ffx_matrix A, uint32_t alpha, const void* x, uint32_t beta
 /* y <- alpha*A*x + beta*y (mod m), as ffx_spmv, for callers that cannot
  * allocate device memory (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc): this call allocates nothing. The
- * temporary that ffx_spmv allocates per call (the 16-bit copy of x when
+ * temporary that ffx_spmv keeps in the handle (the 16-bit copy of x when
  * m <= 65536, or x gathered into the stored order of a reordered handle)
  * lives instead in a static device array of FFX_NOALLOC_SCRATCH_BYTES bytes,
  * one per GPU, held from the first call on that GPU until the process ends.
