@@ -295,7 +295,6 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
   __shared__ uint32_t Gs[SB_MAXM][SB_MAXN][SB_LEAF + 1];  // padded: the 8 columns fall in different banks
   __shared__ uint32_t Dl[SB_MAXM][SB_MAXN];      // residual coefficient, reduced in place
   __shared__ __align__(16) uint32_t T[SB_MAXM][SB_MAXM];  // this order's row transformation
-  __shared__ int piv[SB_MAXM];
   __shared__ int dl[SB_MAXM];
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   __shared__ int order[SB_MAXM];                // rows by (shifted degree, index)
@@ -337,7 +336,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
       }
       if (part8 == 0 && r < m && c < n) Dl[r][c] = v;
     }
-    __syncthreads();
+    // (no barrier here: the row order reads only the degrees; the barrier after it covers both)
     // Echelon form of the residual, rows by increasing shifted degree (ties by
     // index), right-looking: when a row keeps a nonzero residual it becomes a
     // pivot (column: its first nonzero entry) and every later row is reduced by
@@ -354,7 +353,6 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
         pos += (dj < di) || (dj == di && j < tid);
       }
       order[pos] = tid;
-      piv[tid] = 0;
     }
     for (int idx = tid; idx < m * m; idx += LEAF_NT) T[idx / m][idx % m] = (idx / m == idx % m) ? 1u : 0u;
     __syncthreads();
@@ -425,11 +423,9 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
       __syncthreads();
     }
     if (lane_on && lcol == 0) sc[lj] = scr;
-    if (tid < m && ((pivmask >> tid) & 1u)) {
-      piv[tid] = 1;
-      dl[tid] += 1;
-    }
-    __syncthreads();
+    if (tid < m && ((pivmask >> tid) & 1u)) dl[tid] += 1;
+    // (no barrier here: the update reads T, complete at the last pivot's barrier, and takes the
+    // pivot rows from pivmask; the scales and degrees are next read after the update's barrier)
     // M <- diag(x^piv) T M: four lanes per entry (i, c), each over every fourth coefficient, T's row
     // in registers. M has degree <= k before order k, so only coefficients 0..k+1 change (the
     // buffers hold zeros above). The 64 lanes of a wave share the row i, so T's zero entries (rows
@@ -449,7 +445,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
           t[q4 + 2] = q4 + 2 < m ? tv.z : 0u;
           t[q4 + 3] = q4 + 3 < m ? tv.w : 0u;
         }
-        const int sh = piv[i];
+        const int sh = (int)((pivmask >> i) & 1u);
         for (int j = j0; j <= k + 1 && j < LC; j += 4) {
           const int js = j - sh;
           uint32_t out = 0;
