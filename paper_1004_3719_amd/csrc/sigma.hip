@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
   __shared__ int dl[SB_MAXM];
   __shared__ uint32_t sc[SB_MAXM];              // scale of each row from fraction-free elimination
   __shared__ int order[SB_MAXM];                // rows by (shifted degree, index)
-  __shared__ uint32_t rinfo[SB_MAXM][2];        // per position: first nonzero unused column, its value
+  __shared__ uint32_t rinfo[SB_MAXM][2];        // per row: first nonzero unused column, its value
   const int tid = threadIdx.x;
   for (int i = tid; i < SB_MAXM * SB_MAXN * SB_LEAF; i += LEAF_NT) {
     int r = i / (SB_MAXN * SB_LEAF), c = (i / SB_LEAF) % SB_MAXN, k = i % SB_LEAF;
@@ -335,6 +335,14 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
         v = t >= F.p ? t - F.p : t;
       }
       if (part8 == 0 && r < m && c < n) Dl[r][c] = v;
+      // the wave holds row r's residual (lane 8c, column c): its first nonzero column and value
+      const uint64_t bal = __ballot(part8 == 0 && r < m && c < n && v != 0u);
+      const int f = bal ? __builtin_ctzll(bal) / 8 : -1;
+      const uint32_t fv = (uint32_t)__shfl((int)v, f < 0 ? 0 : 8 * f);
+      if ((tid & (WAVE - 1)) == 0 && r < m) {
+        rinfo[r][0] = (uint32_t)f;
+        rinfo[r][1] = fv;
+      }
     }
     // (no barrier here: the row order reads only the degrees; the barrier after it covers both)
     // Echelon form of the residual, rows by increasing shifted degree (ties by
@@ -366,10 +374,10 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
     // works on one fixed entry of [residual | T] for the whole order: half a wave per row (lane lcol
     // < 8 a residual column, 8 <= lcol < 24 a column of T), so a row's lanes trade values by
     // shuffles. The lane's own entry stays in a register (no other lane writes it) and goes to LDS
-    // for the pivot steps of later rows; the scale of a row is kept by its lane 0. After each pivot
-    // step the lanes of every later row publish the row's first nonzero unused column and its value
-    // (rinfo), so a pivot step reads two words and the lane's column of the pivot row, and a row left
-    // with zeros costs one read and no barrier.
+    // for the pivot steps of later rows; the scale of a row is kept by its lane 0. Every row's first
+    // nonzero unused column and its value (rinfo, by row) come from the residual phase and, after
+    // each pivot step, from the lanes of every later row, so a pivot step reads two words and the
+    // lane's column of the pivot row, and a row left with zeros costs one read and no barrier.
     int ord[SB_MAXM];
 #pragma unroll
     for (int q = 0; q < SB_MAXM; ++q) ord[q] = q < m ? order[q] : 0;
@@ -386,25 +394,24 @@ __global__ void __launch_bounds__(LEAF_NT) k_mbasis_leaf(const uint32_t* __restr
       if (lcol == 0) scr = sc[lj];
     }
     uint32_t used = 0, pivmask = 0;  // pivot columns and pivot rows so far (the same in every lane)
-    // rinfo of the rows at positions after `after`, from their lanes (called by whole waves)
+    // rinfo of the rows at positions after `after`, from their lanes (called by whole waves; the rows
+    // at earlier positions are left alone, since slower waves may still read the pivot row's)
     auto publish = [&](int after) {
       const uint64_t bal = __ballot(lane_on && lcol < SB_MAXN && !((used >> lcol) & 1u) && own != 0u);
       const uint32_t rm = (uint32_t)(bal >> (tid & EW)) & ((1u << SB_MAXN) - 1u);
       const int f = rm ? __builtin_ctz(rm) : -1;
       const uint32_t fv = (uint32_t)__shfl((int)own, rowbase + (f < 0 ? 0 : f));
       if (lane_on && lcol == 0 && lp > after) {
-        rinfo[lp][0] = (uint32_t)f;
-        rinfo[lp][1] = fv;
+        rinfo[lj][0] = (uint32_t)f;
+        rinfo[lj][1] = fv;
       }
     };
-    if (el_wave) publish(-1);
-    __syncthreads();
 #pragma unroll
     for (int oi = 0; oi < SB_MAXM; ++oi) {
       if (oi >= m) break;
       const int i = ord[oi];
-      const int first = (int)rinfo[oi][0];
-      const uint32_t pv = rinfo[oi][1];
+      const int first = (int)rinfo[i][0];
+      const uint32_t pv = rinfo[i][1];
       const uint32_t prv = lane_on ? (lcol < SB_MAXN ? Dl[i][lcol] : T[i][lcol - SB_MAXN]) : 0u;
       if (first < 0) continue;  // the same answer in every lane
       used |= 1u << first;
